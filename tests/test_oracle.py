@@ -1,0 +1,346 @@
+"""Pins of the CPU oracle against what the mathematics and the paper fix.
+
+None of these compare the oracle with itself: closed forms (DFT, GHZ),
+invariants (unitarity), an independent density-matrix implementation,
+exhaustive enumeration, published generator outputs, the paper's printed tree
+numbers, and binomial / chi-square statistics.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import density, tree
+from paper_2203_13892_amd import workloads as W
+
+
+# ------------------------------------------------------------- generator --
+
+def test_splitmix64_published_outputs():
+    # SplitMix64 seeded with 0 (Steele, Lea & Flood 2014 reference code):
+    # node 0's stream is exactly that sequence.
+    want = [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F, 0xF88BB8A8724C81EC]
+    assert [oracle.draw(0, 0, j) for j in range(4)] == want
+
+
+def test_node_streams_are_disjoint_subsequences():
+    # node nu starts 2^32 draws further along the same sequence
+    assert oracle.draw(5, 1, 0) == oracle.draw(5, 0, 1 << 32)
+    assert oracle.draw(5, 3, 7) == oracle.draw(5, 0, (3 << 32) + 7)
+
+
+def test_uniform_range():
+    u = [oracle.uniform(11, nu, j) for nu in range(20) for j in range(50)]
+    assert min(u) >= 0.0 and max(u) < 1.0
+    assert abs(np.mean(u) - 0.5) < 4 * math.sqrt(1 / 12 / len(u))
+
+
+# ----------------------------------------------------------- gate apply --
+
+def dft_state(n, x):
+    y = np.arange(1 << n)
+    return np.exp(2j * np.pi * x * y / (1 << n)) / math.sqrt(1 << n)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 7, 10])
+def test_qft_closed_form(n):
+    rng = np.random.default_rng(n)
+    for x in [0, 1, (1 << n) - 1, int(rng.integers(1 << n))]:
+        c = W.concat(W.basis_prep(n, x), W.qft(n))
+        _, psi = oracle.run_events(n, c.gates)
+        assert np.max(np.abs(psi - dft_state(n, x))) < 1e-12
+
+
+def test_qft_decomposed_matches_native():
+    n = 6
+    c1 = W.concat(W.basis_prep(n, 37), W.qft(n))
+    c2 = W.concat(W.basis_prep(n, 37), W.qft(n, decompose=True))
+    _, a = oracle.run_events(n, c1.gates)
+    _, b = oracle.run_events(n, c2.gates)
+    assert np.max(np.abs(a - b)) < 1e-12
+
+
+@pytest.mark.parametrize("n", [2, 5, 9])
+def test_ghz_closed_form(n):
+    _, psi = oracle.run_events(n, W.ghz(n).gates)
+    want = np.zeros(1 << n, np.complex128)
+    want[0] = want[-1] = 1 / math.sqrt(2)
+    assert np.max(np.abs(psi - want)) < 1e-14
+
+
+def test_apply_gate_against_full_operator():
+    # brute force: a gate equals its embedded 2^n x 2^n operator
+    rng = np.random.default_rng(3)
+    n = 5
+    for qubits in [(0,), (4,), (2,), (0, 1), (1, 0), (3, 1), (4, 0), (2, 4)]:
+        m = W.haar_unitary(1 << len(qubits), rng)
+        psi = rng.standard_normal(1 << n) + 1j * rng.standard_normal(1 << n)
+        want = density.embed(n, qubits, m) @ psi
+        got = psi.copy()
+        oracle.apply_gate(got, qubits, m)
+        assert np.max(np.abs(got - want)) < 1e-13
+
+
+def test_pauli_codes():
+    # code c_j on qubits[j]: X flips, Z signs, Y = i X Z
+    n = 3
+    psi = np.arange(1, 9).astype(np.complex128)
+    got = psi.copy()
+    oracle.apply_pauli(got, (1,), 1)              # X on qubit 1
+    assert np.array_equal(got, psi[np.arange(8) ^ 2])
+    got = psi.copy()
+    oracle.apply_pauli(got, (2,), 3)              # Z on qubit 2
+    assert np.array_equal(got, psi * np.where(np.arange(8) & 4, -1, 1))
+    got = psi.copy()
+    oracle.apply_pauli(got, (0,), 2)              # Y on qubit 0
+    y = np.arange(8)
+    want = psi[y ^ 1] * np.where(y & 1, 1j, -1j)
+    assert np.allclose(got, want, atol=0)
+    got = psi.copy()
+    oracle.apply_pauli(got, (0, 2), 1 + 4 * 3)    # X on qubit 0, Z on qubit 2
+    want = psi[y ^ 1] * np.where((y & 4), -1, 1)
+    assert np.array_equal(got, want)
+
+
+def test_norm_preserved_by_every_gate_and_pauli():
+    rng = np.random.default_rng(9)
+    n = 8
+    psi = rng.standard_normal(1 << n) + 1j * rng.standard_normal(1 << n)
+    psi /= np.linalg.norm(psi)
+    c = W.random_circuit(n, 60, seed=4)
+    for q, m, _ in c.gates:
+        oracle.apply_gate(psi, q, m)
+        assert abs(np.vdot(psi, psi).real - 1) < 1e-13
+        oracle.apply_pauli(psi, q, int(rng.integers(1, 4 ** len(q))))
+        assert abs(np.vdot(psi, psi).real - 1) < 1e-13
+
+
+# -------------------------------------------------------------- sampling --
+
+def test_sampling_inverse_cdf_brute_force():
+    # probabilities 0.25, 0.25, 0.5, 0 on 2 qubits
+    psi = np.array([0.5, 0.5j, -math.sqrt(0.5), 0], np.complex128)
+    cases = {0.0: 0, 0.1: 0, 0.2499: 0, 0.25: 1, 0.3: 1, 0.49: 1, 0.5: 2, 0.99: 2,
+             0.9999999999: 2}
+    for u, x in cases.items():
+        assert oracle.sample_state(psi, u) == x
+    # unnormalised input: the CDF is scaled by the FP64 total
+    assert oracle.sample_state(3 * psi, 0.3) == 1
+
+
+def test_sampling_matches_distribution():
+    rng = np.random.default_rng(1)
+    n = 4
+    psi = rng.standard_normal(16) + 1j * rng.standard_normal(16)
+    p = np.abs(psi) ** 2 / np.sum(np.abs(psi) ** 2)
+    us = (np.arange(4000) + 0.5) / 4000
+    counts = np.bincount([oracle.sample_state(psi, u) for u in us], minlength=16)
+    # stratified uniforms: counts within 1 of 4000 p_x
+    assert np.max(np.abs(counts - 4000 * p)) <= 1.0 + 1e-9
+
+
+# ------------------------------------------------------------ noise list --
+
+def test_noise_event_rates_binomial():
+    n = 4
+    c = W.random_circuit(n, 40, seed=2, p1=0.05, p2=0.2)
+    N = 4000
+    nz = oracle.sample_noise(c.gates, ([N], [0, len(c)]), seed=7)
+    per_gate = np.bincount(nz.ev_gate, minlength=len(c))
+    for g, (_, _, p) in enumerate(c.gates):
+        pg = float(np.sum(p[1:]))
+        sd = math.sqrt(N * pg * (1 - pg))
+        assert abs(per_gate[g] - N * pg) < 4 * sd + 1
+    # at most one event per gate per node, events sorted by gate within a node
+    for nu in range(N):
+        ev = nz.ev_gate[nz.node_off[nu]:nz.node_off[nu + 1]]
+        assert np.all(np.diff(ev.astype(np.int64)) > 0)
+
+
+def test_noise_codes_uniform_chi2():
+    from scipy.stats import chi2
+    c = W.Circuit(2).add((0, 1), W.cx(), W.depolarizing_probs(0.9, 2))
+    nz = oracle.sample_noise(c.gates, ([20000], [0, 1]), seed=3)
+    cnt = np.bincount(nz.ev_code, minlength=16)
+    assert cnt[0] == 0
+    obs = cnt[1:]
+    exp = np.full(15, obs.sum() / 15)
+    stat = float(np.sum((obs - exp) ** 2 / exp))
+    assert stat < chi2.ppf(0.9999, 14)
+
+
+def test_noise_zero_probability_is_ideal():
+    n = 5
+    c = W.concat(W.basis_prep(n, 11), W.qft(n)).with_depolarizing(0.0, 0.0)
+    nz = oracle.sample_noise(c.gates, ([64], [0, len(c)]), seed=1)
+    assert nz.ev_gate.size == 0
+    cd = W.concat(W.basis_prep(n, 11), W.qft(n)).with_depolarizing(1e-12, 1e-12)
+    nz2 = oracle.sample_noise(cd.gates, ([64], [0, len(cd)]), seed=1)
+    assert nz2.ev_gate.size == 0
+    # leaf uniforms do not depend on the probabilities (draw positions are fixed)
+    assert np.array_equal(nz.leaf_u, nz2.leaf_u)
+
+
+def test_noise_deterministic_and_seed_dependent():
+    c = W.random_circuit(3, 30, seed=5, p1=0.1, p2=0.3)
+    t = ([4, 5], [0, 12, 30])
+    a = oracle.sample_noise(c.gates, t, 123)
+    b = oracle.sample_noise(c.gates, t, 123)
+    d = oracle.sample_noise(c.gates, t, 124)
+    assert np.array_equal(a.ev_gate, b.ev_gate) and np.array_equal(a.leaf_u, b.leaf_u)
+    assert not np.array_equal(a.leaf_u, d.leaf_u)
+
+
+# ----------------------------------------------- channel / density matrix --
+
+def test_full_depolarizing_1q_is_maximally_mixed():
+    c = W.Circuit(1).add((0,), W.H, W.depolarizing_probs(0.75, 1))
+    rho = density.dm_run(1, c.gates)
+    assert np.max(np.abs(rho - np.eye(2) / 2)) < 1e-15
+
+
+def test_full_depolarizing_2q_is_maximally_mixed():
+    c = W.Circuit(2).add((0,), W.H).add((0, 1), W.cx(), W.depolarizing_probs(15 / 16, 2))
+    rho = density.dm_run(2, c.gates)
+    assert np.max(np.abs(rho - np.eye(4) / 4)) < 1e-15
+
+
+def test_enumeration_equals_density_matrix():
+    # exact Pauli-pattern mixture (C trajectories) == DM channel (numpy)
+    for seed in range(3):
+        c = W.random_circuit(4, 12, seed=seed)
+        rng = np.random.default_rng(100 + seed)
+        gates = list(c.gates)
+        noisy = rng.choice(len(gates), 3, replace=False)
+        for g in noisy:
+            q, m, _ = gates[g]
+            p = rng.dirichlet(np.ones(4 ** len(q)))
+            gates[g] = (q, m, p)
+        rho_dm = density.dm_run(4, gates)
+        rho_en = density.enumerate_mixture(4, gates)
+        assert np.max(np.abs(rho_dm - rho_en)) < 1e-12
+
+
+def test_trajectory_average_converges_to_density_matrix():
+    n = 4
+    c = W.concat(W.ghz(n), W.random_circuit(n, 10, seed=8)).with_depolarizing(0.05, 0.1)
+    M = 3000
+    nz = oracle.sample_noise(c.gates, ([M], [0, len(c)]), seed=2)
+    _, st = oracle.run_leaves(n, c.gates, ([M], [0, len(c)]), nz, states=True)
+    p_traj = np.abs(st) ** 2
+    mean = p_traj.mean(axis=0)
+    se = p_traj.std(axis=0) / math.sqrt(M)
+    diag = np.real(np.diag(density.dm_run(n, c.gates)))
+    assert np.all(np.abs(mean - diag) <= 4 * se + 1e-12)
+
+
+# ----------------------------------------------------------------- trees --
+
+def test_tree_leaf_equals_per_shot_with_ancestor_events():
+    # a leaf of a tree is one ordinary trajectory whose noise is the union of
+    # its ancestors' events
+    n = 5
+    c = W.random_circuit(n, 24, seed=11, p1=0.2, p2=0.4)
+    A, cut = [3, 2, 4], [0, 7, 15, 24]
+    nz = oracle.sample_noise(c.gates, (A, cut), seed=9)
+    leaves = np.arange(24)
+    out, st = oracle.run_leaves(n, c.gates, (A, cut), nz, leaves, states=True)
+    offs = [0, 3, 9]
+    for lam in leaves:
+        ev = []
+        for l in range(3):
+            nu = offs[l] + tree.ancestor(A, l, int(lam))
+            s, e = int(nz.node_off[nu]), int(nz.node_off[nu + 1])
+            ev += list(zip(nz.ev_gate[s:e].tolist(), nz.ev_code[s:e].tolist()))
+        x, psi = oracle.run_events(n, c.gates, ev, u=float(nz.leaf_u[lam]))
+        assert x == out[lam]
+        assert np.max(np.abs(psi - st[lam])) == 0.0
+
+
+def test_printed_tree_numbers():
+    # Sec. 3: baseline BV tree (64,1,1) has 193 nodes with the root; DCP tree
+    # (16,2,2) has 113 nodes and 64 outcomes
+    assert tree.node_count([64, 1, 1]) == 193
+    assert tree.node_count([16, 2, 2]) == 113
+    assert tree.outcomes([16, 2, 2]) == 64
+    # Sec. 3.2.1: UCP (10,10,10) simulates the subcircuits 10, 100, 1000 times
+    assert tree.instances([10, 10, 10]) == [10, 100, 1000]
+
+
+def test_printed_speedup_qft14():
+    # Sec. 5.1: QFT_14 with 7 subcircuits and A_0 = 500: theoretical 3.53x
+    A = [500] + [2] * 6
+    assert tree.outcomes(A) == 32000
+    assert round(tree.work_ratio_equal(A), 2) == 3.53
+
+
+def test_max_speedup_formula_matches_tree():
+    # Sec. 3.6: (1, .., 1, N) with k equal subcircuits gives kN / ((k-1) + N)
+    for k, N in [(2, 1000), (3, 32000), (7, 50)]:
+        A = [1] * (k - 1) + [N]
+        assert abs(tree.work_ratio_equal(A) - tree.max_speedup_equal(k, N)) < 1e-12
+
+
+# ------------------------------------------------------------------- DCP --
+
+def test_sample_size_cochran():
+    # p = 0.5, z = 1.96, eps = 0.05, infinite population: 384.16
+    assert abs(tree.sample_size(0.5, 1.96, 0.05) - 384.16) < 1e-9
+    # finite-population correction
+    n0 = 384.16
+    assert abs(tree.sample_size(0.5, 1.96, 0.05, 1000) - n0 / (1 + n0 / 1000)) < 1e-9
+
+
+def test_first_error_rate():
+    assert abs(tree.first_error_rate([0.1, 0.2]) - (1 - 0.9 * 0.8)) < 1e-15
+    assert tree.first_error_rate([]) == 0.0
+
+
+def test_dcp_printed_shapes():
+    # Sec. 5.6: QPE_9 with 1000 shots -> (250, 2, 2)
+    for a0 in (126, 200, 250):
+        A, cut = tree.dcp([1e-3] * 120, 1000, copy_cost=8, A0_min=a0)
+        assert A == [250, 2, 2]
+    # Sec. 5.1: QFT_14 with 32000 shots -> 7 subcircuits, A_0 = 500
+    for a0 in (251, 400, 500):
+        A, cut = tree.dcp([1e-3] * 472, 32000, copy_cost=8, A0_min=a0)
+        assert A == [500] + [2] * 6
+        assert len(cut) == 8 and cut[0] == 0 and cut[-1] == 472
+
+
+def test_dcp_reproduces_shapes_from_error_rates():
+    # z = 1.96, eps = 0.01 and 0.1% gate error: first subcircuits of a few
+    # gates give both printed shapes
+    A, _ = tree.dcp([1e-3] * 120, 1000, z=1.96, eps=0.01, copy_cost=6)
+    assert A == [250, 2, 2]
+    A, _ = tree.dcp([1e-3] * 472, 32000, z=1.96, eps=0.01, copy_cost=8)
+    assert A == [500] + [2] * 6
+
+
+def test_dcp_invariants():
+    rng = np.random.default_rng(0)
+    for _ in range(200):
+        G = int(rng.integers(1, 400))
+        N = int(rng.integers(1, 100000))
+        e = rng.uniform(0, 0.02, G)
+        C = float(rng.uniform(0, 30))
+        A, cut = tree.dcp(e, N, copy_cost=C, max_levels=int(rng.integers(1, 9)))
+        assert tree.outcomes(A) >= N
+        assert cut[0] == 0 and cut[-1] == G and all(b > a for a, b in zip(cut, cut[1:]))
+        assert len(cut) == len(A) + 1
+        if len(A) > 1:
+            assert all(a == A[1] for a in A[1:]) and A[1] >= 2
+            # A_0 is the smallest first arity reaching N outcomes
+            assert (A[0] - 1) * A[1] ** (len(A) - 1) < N
+
+
+# -------------------------------------------------------------- fidelity --
+
+def test_fidelity_metrics():
+    p = np.array([0.5, 0.5, 0, 0])
+    assert abs(tree.fidelity_s(p, p) - 1) < 1e-15
+    assert abs(tree.fidelity_norm(p, p) - 1) < 1e-15
+    assert abs(tree.fidelity_norm(p, np.full(4, 0.25))) < 1e-15
+    assert math.isnan(tree.fidelity_norm(np.full(4, 0.25), p))
+    assert tree.tv_distance(p, np.array([0, 0, 0.5, 0.5])) == 1.0
