@@ -1,0 +1,232 @@
+/*
+ * tqsim.h -- C ABI of an MI355X (gfx950) library for tree-based noisy
+ * quantum-circuit simulation by Monte Carlo Pauli trajectories, after
+ * "Accelerating Simulation of Quantum Circuits under Noise via
+ * Computational Reuse" (Wang, Tannu, Nair; arXiv 2203.13892).
+ *
+ * The problem statement follows the paper: a circuit and a noise model go in
+ * (Sec. 2.4 and Sec. 4.3: noise operators are inserted into the circuit,
+ * the depolarizing channel being the main model), together with the shot
+ * count and the tree shape (Sec. 3.1: a tree (A_0, .., A_{k-1}) over k
+ * consecutive subcircuits; Sec. 3.2: Dynamic Circuit Partition chooses it);
+ * one measured outcome per leaf comes out (Sec. 2.2 and Sec. 3.1: the tree
+ * yields prod A_j outcomes).
+ *
+ * Conventions used by every call:
+ *   - Bit q of a basis index is qubit q (little-endian).
+ *   - A gate on qubits (q_0, .., q_{a-1}), a in {1, 2}, carries a
+ *     (2^a x 2^a) complex matrix, row-major, interleaved (re, im) doubles;
+ *     local index bit j of the matrix is qubit q_j.
+ *   - Pauli probabilities of a gate are 4^a doubles indexed by
+ *     code = sum_j c_j 4^j with c_j in {0: I, 1: X, 2: Y, 3: Z} acting on
+ *     q_j; entry 0 is the identity.  The drawn operator acts right after its
+ *     gate, on that gate's qubits.
+ *   - The tree has `levels` subcircuits; cut[0] = 0 < cut[1] < .. <
+ *     cut[levels] = number of gates; subcircuit l is gates
+ *     [cut[l], cut[l+1]).  Level l has I_l = A_0 * .. * A_l instances; node
+ *     (l, m) is a child of (l-1, m / A_l); global node ids run level by
+ *     level.  Leaf lambda is node (levels-1, lambda).  The per-shot form is
+ *     levels = 1, arity = {N}.
+ *   - Noise sampling: SplitMix64 (Steele, Lea, Flood 2014).  Node nu's
+ *     stream under seed s is SplitMix64 started at state s + nu * 2^32 *
+ *     0x9E3779B97F4A7C15; a draw z becomes (z >> 11) * 2^-53.  In gate order
+ *     each gate takes one uniform u1; when u1 < p_g (p_g = sum of the
+ *     non-identity probabilities in code order) a second uniform u2 selects
+ *     the first code whose running probability sum exceeds u2 * p_g.  A leaf
+ *     then takes one more uniform: its measurement uniform u.
+ *   - Measurement: outcome = min { x : sum_{y <= x} |psi_y|^2 > u * T } with
+ *     T = sum_x |psi_x|^2, accumulated in FP64 in index order (largest x with
+ *     nonzero probability if rounding leaves no such x).
+ *
+ * Ownership: every input array is copied during the call.  Opaque objects
+ * belong to the caller until their *_destroy (NULL is accepted).  Device
+ * memory is never allocated by the library: the caller passes a device
+ * workspace (for example a torch uint8 tensor) of at least the size that
+ * tqs_workspace_bytes reports, and a HIP stream (NULL = the null stream).
+ *
+ * Errors: every call returns a tqs_status; a negative value means failure,
+ * and tqs_last_error() gives a message for the calling thread.  No call
+ * aborts or throws across this boundary.
+ */
+#ifndef TQSIM_H
+#define TQSIM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TQS_OK = 0,
+    TQS_E_ARG = -1,         /* bad argument (NULL, out of range, not unitary) */
+    TQS_E_SHAPE = -2,       /* tree shape or cuts invalid */
+    TQS_E_WORKSPACE = -3,   /* workspace too small or misaligned */
+    TQS_E_HIP = -4,         /* HIP runtime error (message carries its text) */
+    TQS_E_OOM = -5,         /* host allocation failed */
+    TQS_E_UNSUPPORTED = -6  /* valid request outside what this build supports */
+} tqs_status;
+
+typedef enum { TQS_C64 = 0, TQS_C128 = 1 } tqs_precision;
+
+typedef struct tqs_circuit tqs_circuit;
+typedef struct tqs_noise tqs_noise;
+typedef struct tqs_plan tqs_plan;
+
+/* Tree shape (Sec. 3.1).  arity[levels], cut[levels + 1]. */
+typedef struct {
+    uint32_t levels;
+    const uint64_t *arity;
+    const uint32_t *cut;
+} tqs_tree;
+
+/* Planner and executor knobs; zero fields take the defaults. */
+typedef struct {
+    uint32_t tile_qubits;      /* qubits staged per workgroup tile (default 12 c64, 11 c128) */
+    uint32_t max_ops_per_pass; /* gate ops applied per HBM pass (default 24) */
+    uint32_t chunk_states;     /* live states per tree level (default 256) */
+    uint32_t sample_block_log; /* log2 amplitudes per sampling block (default 12) */
+} tqs_tuning;
+
+/* Timing and traffic of one run. */
+typedef struct {
+    double ms_wall;            /* host wall time of the call */
+    double ms_device;          /* device time from upload to outcomes (HIP events) */
+    double ms_passes;          /* device time of the gate-apply passes */
+    double ms_sample;          /* device time of the sampling kernels */
+    uint64_t launches;         /* kernels launched */
+    uint64_t pass_states;      /* sum over pass launches of states processed */
+    uint64_t bytes_passes;     /* algorithmic HBM bytes of the passes (read + write) */
+    uint64_t bytes_sample;     /* algorithmic HBM bytes of sampling */
+    uint64_t events;           /* noise events in the insertion list */
+} tqs_run_stats;
+
+/* ---------------------------------------------------------------- circuit */
+
+/* New empty circuit on n_qubits (1..30). */
+tqs_status tqs_circuit_create(uint32_t n_qubits, tqs_circuit **out);
+
+/* Append a gate (Sec. 2.1: circuits are ordered gates).  `qubits` has
+ * `arity` distinct entries < n; `mat` is (2^arity)^2 interleaved complex
+ * doubles and must be unitary to 1e-9; `pauli` is NULL (noiseless) or 4^arity
+ * non-negative probabilities summing to 1 within 1e-9 (Sec. 2.4: noise
+ * operators drawn after the gate). */
+tqs_status tqs_circuit_add_gate(tqs_circuit *c, uint32_t arity, const uint32_t *qubits,
+                                const double *mat, const double *pauli);
+
+/* Set the depolarizing channel on every gate (Sec. 4.3, depolarizing channel
+ * built from X, Y, Z): total non-identity probability p1 for one-qubit and
+ * p2 for two-qubit gates, spread evenly over the 3 or 15 non-identity
+ * Paulis.  Replaces any per-gate probabilities. */
+tqs_status tqs_circuit_set_depolarizing(tqs_circuit *c, double p1, double p2);
+
+/* Number of qubits and gates. */
+tqs_status tqs_circuit_info(const tqs_circuit *c, uint32_t *n_qubits, uint32_t *n_gates);
+
+void tqs_circuit_destroy(tqs_circuit *c);
+
+/* -------------------------------------------------------------- tree shape */
+
+/* Dynamic Circuit Partition (Sec. 3.2).  The first subcircuit has
+ * max(1, ceil(copy_cost)) gates (the shortest that amortises one state copy,
+ * Sec. 3.2.2 and Sec. 3.6); its error rate is 1 - prod(1 - e_i) with e_i the
+ * gates' non-identity probabilities (Sec. 3.2.3); A0_min is the ceiling of
+ * the sample-size bound z^2 p(1-p)/eps^2 / (1 + z^2 p(1-p)/(eps^2 N)); k is
+ * the most further subcircuits with A_r = floor((N/A0_min)^(1/k)) >= 2,
+ * capped by floor((G - L0)/max(1, copy_cost)) and by max_levels - 1; A_0 is
+ * raised to ceil(N / A_r^k) so that the tree has at least N leaves; the
+ * remaining gates are split into k equal parts, larger parts first
+ * (Sec. 3.2.4).  A result with *levels == 1 is the per-shot form.
+ * arity and cut must hold max_levels and max_levels + 1 entries. */
+tqs_status tqs_dcp(const tqs_circuit *c, uint64_t shots, double z, double eps,
+                   double copy_cost, uint32_t max_levels, uint32_t *levels,
+                   uint64_t *arity, uint32_t *cut);
+
+/* ------------------------------------------------------------------- noise */
+
+/* Sample the noise insertion list of every tree node plus one measurement
+ * uniform per leaf (Sec. 2.4 and Sec. 3.1; generator in the header
+ * comment).  Host only. */
+tqs_status tqs_noise_sample(const tqs_circuit *c, const tqs_tree *tree, uint64_t seed,
+                            tqs_noise **out);
+
+/* Build an insertion list from explicit data: node_off[n_nodes + 1] (CSR
+ * over global node ids), ev_gate / ev_code[node_off[n_nodes]] (gate index
+ * inside the node's subcircuit range, non-zero Pauli code; sorted by gate
+ * within a node, one event per gate at most), leaf_u[n_leaves] in [0, 1). */
+tqs_status tqs_noise_import(const tqs_circuit *c, const tqs_tree *tree,
+                            const uint64_t *node_off, const uint32_t *ev_gate,
+                            const uint8_t *ev_code, const double *leaf_u, tqs_noise **out);
+
+/* Borrowed views of an insertion list; valid until tqs_noise_destroy. */
+tqs_status tqs_noise_view(const tqs_noise *nz, const uint64_t **node_off,
+                          const uint32_t **ev_gate, const uint8_t **ev_code,
+                          const double **leaf_u, uint64_t *n_nodes, uint64_t *n_leaves);
+
+void tqs_noise_destroy(tqs_noise *nz);
+
+/* -------------------------------------------------------------------- plan */
+
+/* Plan a circuit under a tree shape: gates are grouped into HBM passes
+ * (tiles of staged qubits), matrices cast once to the run precision.
+ * tuning may be NULL.  Host only. */
+tqs_status tqs_plan_create(const tqs_circuit *c, const tqs_tree *tree, tqs_precision prec,
+                           const tqs_tuning *tuning, tqs_plan **out);
+
+/* Number of HBM passes of subcircuit `level` and in total. */
+tqs_status tqs_plan_info(const tqs_plan *p, uint32_t level, uint32_t *passes_level,
+                         uint32_t *passes_total, uint32_t *chunk_states);
+
+/* Device workspace bytes that tqs_run needs for this plan and insertion
+ * list (nz may be NULL for a bound valid for any list of this tree). */
+tqs_status tqs_workspace_bytes(const tqs_plan *p, const tqs_noise *nz, uint64_t *bytes);
+
+void tqs_plan_destroy(tqs_plan *p);
+
+/* --------------------------------------------------------------------- run */
+
+/* Simulate every leaf of the tree (Sec. 3.1: each node runs its subcircuit
+ * instance with its own noise on a copy of its parent's state; each leaf
+ * is sampled once).  d_workspace: device pointer, 256-byte aligned,
+ * ws_bytes >= tqs_workspace_bytes.  stream: hipStream_t or NULL.  outcomes:
+ * host array of n_leaves.  Stream-ordered; returns after the outcomes are on
+ * the host.  stats may be NULL. */
+tqs_status tqs_run(tqs_plan *p, const tqs_noise *nz, void *d_workspace, uint64_t ws_bytes,
+                   void *stream, uint64_t *outcomes, tqs_run_stats *stats);
+
+/* As tqs_run, but only level-0 subtrees [first, last) are simulated; the
+ * outcomes of their leaves go to outcomes[0 ..): resuming a failed run or
+ * splitting one across devices gives the same outcomes as one whole run. */
+tqs_status tqs_run_range(tqs_plan *p, const tqs_noise *nz, void *d_workspace,
+                         uint64_t ws_bytes, void *stream, uint64_t first, uint64_t last,
+                         uint64_t *outcomes, tqs_run_stats *stats);
+
+/* As tqs_run, and also return the final (pre-measurement) amplitudes of the
+ * listed leaves as complex128 (host, n * 2^n interleaved doubles), with the
+ * noise frame applied (for tests and analysis; not a fast path). */
+tqs_status tqs_run_capture(tqs_plan *p, const tqs_noise *nz, void *d_workspace,
+                           uint64_t ws_bytes, void *stream, uint64_t *outcomes,
+                           const uint64_t *leaves, uint64_t n, double *host_amps);
+
+/* ------------------------------------------------------- results, errors */
+
+/* Sorted unique outcomes and their counts; values/counts hold n entries. */
+tqs_status tqs_histogram(const uint64_t *outcomes, uint64_t n, uint64_t *values,
+                         uint64_t *counts, uint64_t *n_unique);
+
+/* Device copy bandwidth probe: copies `bytes` within the workspace `reps`
+ * times with the library's streaming kernel and reports GB/s (read + write).
+ * The workspace must hold 2 * bytes. */
+tqs_status tqs_probe_copy(void *d_workspace, uint64_t bytes, uint32_t reps, void *stream,
+                          double *gbps);
+
+/* Message of the last failed call on this thread (never NULL). */
+const char *tqs_last_error(void);
+
+/* Library version string. */
+const char *tqs_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TQSIM_H */

@@ -1,0 +1,936 @@
+// Device side of tqsim for gfx950: gate-apply pass kernel, sampling
+// kernels, Pauli-frame materialisation, copy probe, and the executor that
+// walks the simulation tree.
+//
+// Noise is carried as a per-trajectory Pauli frame F = i^k X^x Z^z: the
+// stored state s satisfies psi = F s.  A gate G is applied to s as
+// F^dagger G F, which for a Pauli F is G with its local indices xor-ed by
+// the frame's X bits and signs from its Z bits, so a noise event costs no
+// memory traffic: it only updates (x, z).  At the leaf, the outcome of psi
+// is the outcome of s with its index xor-ed by x.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "tqs_internal.h"
+
+namespace tqs {
+
+constexpr uint32_t kInit = 0xFFFFFFFFu;  // src slot: start from |0..0>
+
+template <typename R>
+struct alignas(2 * sizeof(R)) cplx {
+    R re, im;
+};
+
+template <typename R>
+__device__ __forceinline__ cplx<R> cmul(cplx<R> a, cplx<R> b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+
+template <typename R>
+__device__ __forceinline__ cplx<R> cmac(cplx<R> acc, cplx<R> a, cplx<R> b) {
+    acc.re += a.re * b.re - a.im * b.im;
+    acc.im += a.re * b.im + a.im * b.re;
+    return acc;
+}
+
+template <typename R>
+__device__ __forceinline__ cplx<R> cneg_if(cplx<R> a, uint32_t neg) {
+    return neg ? cplx<R>{-a.re, -a.im} : a;
+}
+
+// Per-node noise metadata in device memory.
+struct NodeMeta {
+    const uint32_t *frame0;  // [2 * node]: x, z at node start
+    const uint32_t *ev_off;  // [node + 1]
+    const uint32_t *ev_pos;  // (pass << 16) | position of the first op that sees it
+    const uint32_t *ev_dx;
+    const uint32_t *ev_dz;
+};
+
+template <typename R>
+struct PassArgs {
+    cplx<R> *states;
+    uint64_t slot_amps;
+    const uint32_t *node_ids;
+    const uint32_t *src_slot;
+    const uint32_t *dst_slot;
+    uint32_t count;
+    uint32_t work;  // count * tiles (unpadded)
+    uint32_t pass_key;
+    const PassDesc *pass;
+    const OpDesc *ops;
+    const cplx<R> *mats;
+    NodeMeta meta;
+};
+
+__device__ __forceinline__ uint32_t insert_zero(uint32_t p, uint32_t t) {
+    const uint32_t lo = p & ((1u << t) - 1u);
+    return ((p >> t) << (t + 1)) | lo;
+}
+
+// The gate-apply pass: one workgroup stages one tile (2^m amplitudes: a
+// contiguous run of 2^c plus the staged high qubits) of one trajectory in
+// LDS, applies the pass's ops in order with the trajectory's Pauli frame,
+// and writes the tile back.  Each amplitude is read and written once per
+// pass.  Work items are laid out so each XCD gets a contiguous range:
+// neighbouring items are sibling trajectories on the same tile, which share
+// a parent state on a branching pass.
+template <typename R>
+__global__ __launch_bounds__(kThreads) void pass_kernel(PassArgs<R> a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const uint32_t nwg = gridDim.x;
+    const uint32_t bid = blockIdx.x;
+    const uint32_t w = (bid & 7u) * (nwg >> 3) + (bid >> 3);
+    if (w >= a.work) return;
+    const uint32_t traj = w % a.count;
+    const uint32_t tile = w / a.count;
+    const uint32_t tid = threadIdx.x;
+
+    const PassDesc *pd = a.pass;
+    const uint32_t m = pd->m, c = pd->c, nh = pd->nh, nfree = pd->nfree;
+    const uint32_t M = 1u << m;
+
+    cplx<R> *buf = reinterpret_cast<cplx<R> *>(smem);
+    uint32_t *hoff = reinterpret_cast<uint32_t *>(smem + (size_t)M * sizeof(cplx<R>));
+
+    // tile base: tile-index bits deposited on the free qubits
+    uint32_t base = 0;
+    for (uint32_t i = 0; i < nfree; i++) base |= ((tile >> i) & 1u) << pd->fbits[i];
+    for (uint32_t h = tid; h < (1u << nh); h += kThreads) {
+        uint32_t o = 0;
+        for (uint32_t b = 0; b < nh; b++) o |= ((h >> b) & 1u) << pd->hbits[b];
+        hoff[h] = o;
+    }
+
+    // frame at the start of this pass
+    const uint32_t node = a.node_ids[traj];
+    uint32_t fx = a.meta.frame0[2 * node], fz = a.meta.frame0[2 * node + 1];
+    uint32_t e = a.meta.ev_off[node];
+    const uint32_t e1 = a.meta.ev_off[node + 1];
+    while (e < e1 && a.meta.ev_pos[e] < a.pass_key) {
+        fx ^= a.meta.ev_dx[e];
+        fz ^= a.meta.ev_dz[e];
+        e++;
+    }
+    __syncthreads();
+
+    const uint32_t src_s = a.src_slot[traj];
+    const cplx<R> *src = src_s == kInit ? nullptr : a.states + (uint64_t)src_s * a.slot_amps;
+    cplx<R> *dst = a.states + (uint64_t)a.dst_slot[traj] * a.slot_amps;
+    const uint32_t cmask = (1u << c) - 1u;
+    for (uint32_t l = tid; l < M; l += kThreads) {
+        const uint32_t g = base + hoff[l >> c] + (l & cmask);
+        cplx<R> v;
+        if (src) {
+            v = src[g];
+        } else {
+            v.re = g == 0 ? R(1) : R(0);
+            v.im = R(0);
+        }
+        buf[l] = v;
+    }
+    __syncthreads();
+
+    for (uint32_t j = 0; j < pd->op_count; j++) {
+        const uint32_t key = a.pass_key | j;
+        while (e < e1 && a.meta.ev_pos[e] <= key) {
+            fx ^= a.meta.ev_dx[e];
+            fz ^= a.meta.ev_dz[e];
+            e++;
+        }
+        const OpDesc o = a.ops[pd->op_begin + j];
+        uint32_t xl = (fx >> o.phys[0]) & 1u, zl = (fz >> o.phys[0]) & 1u;
+        if (o.nq == 2) {
+            xl |= ((fx >> o.phys[1]) & 1u) << 1;
+            zl |= ((fz >> o.phys[1]) & 1u) << 1;
+        }
+        const cplx<R> *G = a.mats + o.mat;
+        if (o.kind == OP_DENSE1) {
+            // F^dagger G F: entries G[r^x][c^x] with sign (-1)^{z.r + z.c}
+            cplx<R> g00 = G[(0 ^ xl) * 2 + (0 ^ xl)], g01 = G[(0 ^ xl) * 2 + (1 ^ xl)];
+            cplx<R> g10 = G[(1 ^ xl) * 2 + (0 ^ xl)], g11 = G[(1 ^ xl) * 2 + (1 ^ xl)];
+            g01 = cneg_if(g01, zl);
+            g10 = cneg_if(g10, zl);
+            const uint32_t t = o.loc[0];
+            for (uint32_t p = tid; p < (M >> 1); p += kThreads) {
+                const uint32_t i0 = insert_zero(p, t), i1 = i0 | (1u << t);
+                const cplx<R> x0 = buf[i0], x1 = buf[i1];
+                buf[i0] = cmac(cmul(g00, x0), g01, x1);
+                buf[i1] = cmac(cmul(g10, x0), g11, x1);
+            }
+        } else if (o.kind == OP_DIAG) {
+            // diagonal: d'(r) = d(r ^ x); qubits outside the tile are fixed
+            cplx<R> d[4];
+            const uint32_t k = 1u << o.nq;
+            for (uint32_t r = 0; r < 4; r++) d[r] = G[(r & (k - 1u)) ^ xl];
+            uint32_t rfix = 0;
+            int l0 = -1, l1 = -1;
+            if (o.loc[0] == kNotLocal) rfix |= (base >> o.phys[0]) & 1u; else l0 = o.loc[0];
+            if (o.nq == 2) {
+                if (o.loc[1] == kNotLocal) rfix |= ((base >> o.phys[1]) & 1u) << 1; else l1 = o.loc[1];
+            }
+            for (uint32_t l = tid; l < M; l += kThreads) {
+                uint32_t r = rfix;
+                if (l0 >= 0) r |= (l >> l0) & 1u;
+                if (l1 >= 0) r |= ((l >> l1) & 1u) << 1;
+                const cplx<R> lo = (r & 1u) ? d[1] : d[0];
+                const cplx<R> hi = (r & 1u) ? d[3] : d[2];
+                buf[l] = cmul((r & 2u) ? hi : lo, buf[l]);
+            }
+        } else if (o.kind == OP_CTRL) {
+            // block-diagonal in gate qubit o.ctrl, dense in the other
+            const uint32_t jc = o.ctrl, jt = 1u - jc;
+            const uint32_t t = jt ? o.loc[1] : o.loc[0];
+            cplx<R> blk[2][4];
+            for (uint32_t bc = 0; bc < 2; bc++)
+                for (uint32_t rr = 0; rr < 2; rr++)
+                    for (uint32_t cc = 0; cc < 2; cc++) {
+                        const uint32_t r = (bc << jc) | (rr << jt), cl = (bc << jc) | (cc << jt);
+                        cplx<R> v = G[(r ^ xl) * 4 + (cl ^ xl)];
+                        v = cneg_if(v, (__builtin_popcount(zl & r) + __builtin_popcount(zl & cl)) & 1u);
+                        blk[bc][rr * 2 + cc] = v;
+                    }
+            const uint32_t locc = jc ? o.loc[1] : o.loc[0], physc = jc ? o.phys[1] : o.phys[0];
+            const int lc = locc == kNotLocal ? -1 : (int)locc;
+            const uint32_t cfix = (base >> physc) & 1u;
+            for (uint32_t p = tid; p < (M >> 1); p += kThreads) {
+                const uint32_t i0 = insert_zero(p, t), i1 = i0 | (1u << t);
+                const uint32_t bc = lc >= 0 ? ((i0 >> lc) & 1u) : cfix;
+                const cplx<R> b0 = bc ? blk[1][0] : blk[0][0], b1 = bc ? blk[1][1] : blk[0][1];
+                const cplx<R> b2 = bc ? blk[1][2] : blk[0][2], b3 = bc ? blk[1][3] : blk[0][3];
+                const cplx<R> x0 = buf[i0], x1 = buf[i1];
+                buf[i0] = cmac(cmul(b0, x0), b1, x1);
+                buf[i1] = cmac(cmul(b2, x0), b3, x1);
+            }
+        } else {  // OP_DENSE2
+            cplx<R> g[16];
+            for (uint32_t r = 0; r < 4; r++)
+                for (uint32_t cl = 0; cl < 4; cl++) {
+                    cplx<R> v = G[(r ^ xl) * 4 + (cl ^ xl)];
+                    g[r * 4 + cl] =
+                        cneg_if(v, (__builtin_popcount(zl & r) + __builtin_popcount(zl & cl)) & 1u);
+                }
+            const uint32_t t0 = o.loc[0], t1 = o.loc[1];
+            const uint32_t lo = t0 < t1 ? t0 : t1, hi = t0 < t1 ? t1 : t0;
+            for (uint32_t p = tid; p < (M >> 2); p += kThreads) {
+                const uint32_t i = insert_zero(insert_zero(p, lo), hi);
+                uint32_t idx[4];
+                cplx<R> x[4];
+                for (uint32_t r = 0; r < 4; r++) {
+                    idx[r] = i | ((r & 1u) << t0) | (((r >> 1) & 1u) << t1);
+                    x[r] = buf[idx[r]];
+                }
+                for (uint32_t r = 0; r < 4; r++) {
+                    cplx<R> acc = cmul(g[r * 4], x[0]);
+                    acc = cmac(acc, g[r * 4 + 1], x[1]);
+                    acc = cmac(acc, g[r * 4 + 2], x[2]);
+                    acc = cmac(acc, g[r * 4 + 3], x[3]);
+                    buf[idx[r]] = acc;
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    for (uint32_t l = tid; l < M; l += kThreads) {
+        const uint32_t g = base + hoff[l >> c] + (l & cmask);
+        dst[g] = buf[l];
+    }
+}
+
+// FP64 sums of |psi|^2 over blocks of 2^b consecutive amplitudes.
+template <typename R>
+__global__ __launch_bounds__(kThreads) void block_sums_kernel(const cplx<R> *states, uint64_t slot_amps,
+                                                              const uint32_t *slots, uint32_t b,
+                                                              uint32_t nblocks, double *sums) {
+    __shared__ double red[kThreads];
+    const uint32_t k = blockIdx.x / nblocks, B = blockIdx.x % nblocks;
+    const cplx<R> *psi = states + (uint64_t)slots[k] * slot_amps + ((uint64_t)B << b);
+    double acc = 0.0;
+    for (uint32_t i = threadIdx.x; i < (1u << b); i += kThreads) {
+        const cplx<R> v = psi[i];
+        acc += (double)v.re * (double)v.re + (double)v.im * (double)v.im;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (uint32_t s = kThreads / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) sums[(uint64_t)k * nblocks + B] = red[0];
+}
+
+// Inverse-CDF sampling of one leaf per workgroup, in the index order of the
+// true state psi = F s: psi's block B_L is s's block B_L ^ (x >> b) and
+// inside it index y is s's (y ^ x) low bits.  The outcome is
+// min { y : sum_{y' <= y} |psi_y'|^2 > u T } with FP64 sums.
+template <typename R>
+__global__ __launch_bounds__(kThreads) void sample_kernel(const cplx<R> *states, uint64_t slot_amps,
+                                                          const uint32_t *slots, const uint32_t *node_ids,
+                                                          uint32_t leaf_off, uint32_t b, uint32_t nblocks,
+                                                          const double *sums,
+                                                          const double *leaf_u, const uint32_t *leaf_fx,
+                                                          uint64_t *outcomes, uint64_t leaf_first) {
+    __shared__ double part[kThreads];
+    __shared__ double pre[kThreads];
+    __shared__ uint32_t hit;
+    __shared__ double tsh, cum_sh;
+    const uint32_t k = blockIdx.x, tid = threadIdx.x;
+    const uint32_t lam = node_ids[k] - leaf_off;
+    const double u = leaf_u[lam];
+    const uint32_t x = leaf_fx[lam];
+    const uint32_t xb = x >> b, xlow = x & ((1u << b) - 1u);
+    const double *S = sums + (uint64_t)k * nblocks;
+    const cplx<R> *psi = states + (uint64_t)slots[k] * slot_amps;
+
+    // logical block prefix: thread t owns blocks [t*seg, (t+1)*seg)
+    const uint32_t seg = (nblocks + kThreads - 1) / kThreads;
+    const uint32_t b0 = tid * seg, b1 = min(nblocks, b0 + seg);
+    double s = 0.0;
+    for (uint32_t B = b0; B < b1; B++) s += S[B ^ xb];
+    part[tid] = s;
+    if (tid == 0) hit = 0xFFFFFFFFu;
+    __syncthreads();
+    if (tid == 0) {
+        double run = 0.0;
+        for (uint32_t i = 0; i < kThreads; i++) {
+            pre[i] = run;
+            run += part[i];
+        }
+        tsh = u * run;
+    }
+    __syncthreads();
+    const double t = tsh;
+    {
+        double run = pre[tid];
+        for (uint32_t B = b0; B < b1; B++) {
+            run += S[B ^ xb];
+            if (run > t) {
+                atomicMin(&hit, B);
+                break;
+            }
+        }
+    }
+    __syncthreads();
+    uint32_t BL = hit;
+    if (BL == 0xFFFFFFFFu) {
+        // rounding left no crossing: last block with nonzero mass
+        if (tid == 0) {
+            uint32_t last = 0;
+            for (uint32_t B = 0; B < nblocks; B++)
+                if (S[B ^ xb] > 0.0) last = B;
+            hit = last;
+        }
+        __syncthreads();
+        BL = hit;
+    }
+    // cumulative mass before block BL (same order as above)
+    if (tid == 0) {
+        const uint32_t owner = BL / seg;
+        double run = pre[owner];
+        for (uint32_t B = owner * seg; B < BL; B++) run += S[B ^ xb];
+        cum_sh = run;
+        hit = 0xFFFFFFFFu;
+    }
+    __syncthreads();
+    const uint32_t Bp = BL ^ xb;
+    const cplx<R> *blk = psi + ((uint64_t)Bp << b);
+    const uint32_t nb = 1u << b;
+    const uint32_t iseg = (nb + kThreads - 1) / kThreads;
+    const uint32_t y0 = tid * iseg, y1 = min(nb, y0 + iseg);
+    s = 0.0;
+    for (uint32_t y = y0; y < y1; y++) {
+        const cplx<R> v = blk[y ^ xlow];
+        s += (double)v.re * (double)v.re + (double)v.im * (double)v.im;
+    }
+    part[tid] = s;
+    __syncthreads();
+    if (tid == 0) {
+        double run = cum_sh;
+        for (uint32_t i = 0; i < kThreads; i++) {
+            pre[i] = run;
+            run += part[i];
+        }
+    }
+    __syncthreads();
+    {
+        double run = pre[tid];
+        for (uint32_t y = y0; y < y1; y++) {
+            const cplx<R> v = blk[y ^ xlow];
+            run += (double)v.re * (double)v.re + (double)v.im * (double)v.im;
+            if (run > t) {
+                atomicMin(&hit, y);
+                break;
+            }
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t y = hit;
+        if (y == 0xFFFFFFFFu) {
+            y = 0;
+            for (uint32_t i = 0; i < nb; i++) {
+                const cplx<R> v = blk[i ^ xlow];
+                if ((double)v.re * v.re + (double)v.im * v.im > 0.0) y = i;
+            }
+        }
+        outcomes[lam - leaf_first] = ((uint64_t)BL << b) | y;
+    }
+}
+
+// Standalone Pauli application: out(y) = i^k (-1)^{z.(y^x)} in(y ^ x),
+// i.e. the frame F = i^k X^x Z^z applied to a stored state.
+template <typename R>
+__global__ __launch_bounds__(kThreads) void frame_apply_kernel(const cplx<R> *in, cplx<R> *out,
+                                                               uint64_t amps, uint32_t x, uint32_t z,
+                                                               uint32_t k) {
+    const uint64_t y = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (y >= amps) return;
+    const uint32_t w = (uint32_t)y ^ x;
+    cplx<R> v = in[w];
+    v = cneg_if(v, __builtin_popcount(z & w) & 1u);
+    for (uint32_t i = 0; i < (k & 3u); i++) v = cplx<R>{-v.im, v.re};
+    out[y] = v;
+}
+
+// Streaming copy (bandwidth probe): 16-byte loads and stores.
+__global__ __launch_bounds__(kThreads) void copy_kernel(const uint4 *__restrict__ in,
+                                                        uint4 *__restrict__ out, uint64_t n16) {
+    const uint64_t stride = (uint64_t)gridDim.x * kThreads;
+    for (uint64_t i = (uint64_t)blockIdx.x * kThreads + threadIdx.x; i < n16; i += stride)
+        out[i] = in[i];
+}
+
+// ------------------------------------------------------------- executor --
+
+static tqs_status hip_fail(hipError_t e, const char *what) {
+    return fail(TQS_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                      \
+    do {                                         \
+        hipError_t _e = (expr);                  \
+        if (_e != hipSuccess) return hip_fail(_e, what); \
+    } while (0)
+
+static inline uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
+
+struct Frame {
+    uint32_t x = 0, z = 0, k = 0;  // i^k X^x Z^z
+};
+
+// E * F for Pauli E = i^ke X^ex Z^ez:  X^ex Z^ez X^fx Z^fz = (-1)^{ez.fx} X^(ex^fx) Z^(ez^fz)
+static inline Frame compose(uint32_t ex, uint32_t ez, uint32_t ke, const Frame &f) {
+    Frame r;
+    r.x = ex ^ f.x;
+    r.z = ez ^ f.z;
+    r.k = (ke + f.k + 2u * ((uint32_t)__builtin_popcount(ez & f.x) & 1u)) & 3u;
+    return r;
+}
+
+struct Layout {
+    uint64_t amp_bytes, state_bytes;
+    uint32_t slots_total;
+    std::vector<uint32_t> slot_base;  // per level
+    uint32_t scratch_slot;
+    uint64_t off_meta, off_mats, off_ops, off_passes, off_frame0, off_evoff, off_evpos, off_evdx,
+        off_evdz, off_leafu, off_leaffx, off_sched, off_sums, off_out, total;
+    uint64_t n_sched;
+};
+
+static Layout make_layout(const tqs_plan *p, uint64_t n_events, uint64_t n_leaves_out, uint64_t n_sched) {
+    Layout L;
+    L.amp_bytes = p->prec == TQS_C64 ? 8 : 16;
+    L.state_bytes = L.amp_bytes << p->n;
+    uint32_t s = 0;
+    for (size_t l = 0; l < p->chunk.size(); l++) {
+        L.slot_base.push_back(s);
+        s += p->chunk[l];
+    }
+    L.scratch_slot = s;
+    L.slots_total = s + 1;
+    uint64_t o = align256((uint64_t)L.slots_total * L.state_bytes);
+    L.off_meta = o;
+    L.off_mats = o;
+    o = align256(o + p->mats.size() * L.amp_bytes);
+    L.off_ops = o;
+    o = align256(o + p->ops.size() * sizeof(OpDesc));
+    L.off_passes = o;
+    o = align256(o + p->passes.size() * sizeof(PassDesc));
+    L.off_frame0 = o;
+    o = align256(o + p->n_nodes * 8);
+    L.off_evoff = o;
+    o = align256(o + (p->n_nodes + 1) * 4);
+    L.off_evpos = o;
+    o = align256(o + n_events * 4);
+    L.off_evdx = o;
+    o = align256(o + n_events * 4);
+    L.off_evdz = o;
+    o = align256(o + n_events * 4);
+    L.off_leafu = o;
+    o = align256(o + p->n_leaves * 8);
+    L.off_leaffx = o;
+    o = align256(o + p->n_leaves * 4);
+    L.off_sched = o;
+    L.n_sched = n_sched;
+    o = align256(o + n_sched * 4);
+    L.off_sums = o;
+    const uint64_t nblocks = 1ull << (p->n - p->sample_b);
+    o = align256(o + (uint64_t)p->chunk.back() * nblocks * 8);
+    L.off_out = o;
+    o = align256(o + n_leaves_out * 8);
+    L.total = o;
+    return L;
+}
+
+// Chunk task of the depth-first walk: `count` consecutive nodes of `level`
+// starting at local index `first`, with their slot tables at `sched`.
+struct Task {
+    uint32_t level;
+    uint64_t first;
+    uint32_t count;
+    uint64_t sched;  // offset (in u32) of node_ids; src at +count, dst at +2 count
+};
+
+static void build_schedule(const tqs_plan *p, uint64_t first0, uint64_t last0, std::vector<Task> *tasks,
+                           std::vector<uint32_t> *sched, const std::vector<uint32_t> &slot_base) {
+    const uint32_t L = (uint32_t)p->arity.size();
+    // recursive walk with an explicit stack of (level, parent range)
+    struct Frame_ {
+        uint32_t level;
+        uint64_t p0, p1;   // parent range at level-1 (for level 0: subtree range)
+        uint64_t next;     // next child to process (local index at `level`)
+    };
+    std::vector<Frame_> st;
+    st.push_back({0, first0, last0, first0});
+    while (!st.empty()) {
+        Frame_ &f = st.back();
+        const uint32_t l = f.level;
+        const uint64_t A = p->arity[l];
+        const uint64_t c_end = l == 0 ? f.p1 : f.p1 * A;
+        if (f.next >= c_end) {
+            st.pop_back();
+            continue;
+        }
+        const uint64_t c0 = f.next;
+        const uint64_t c1 = std::min<uint64_t>(c_end, c0 + p->chunk[l]);
+        f.next = c1;
+        Task t;
+        t.level = l;
+        t.first = c0;
+        t.count = (uint32_t)(c1 - c0);
+        t.sched = sched->size();
+        for (uint64_t c = c0; c < c1; c++) sched->push_back((uint32_t)(p->level_offset[l] + c));
+        for (uint64_t c = c0; c < c1; c++)
+            sched->push_back(l == 0 ? kInit : slot_base[l - 1] + (uint32_t)(c / A - f.p0));
+        for (uint64_t c = c0; c < c1; c++) sched->push_back(slot_base[l] + (uint32_t)(c - c0));
+        tasks->push_back(t);
+        if (l + 1 < L) st.push_back({l + 1, c0, c1, c0 * p->arity[l + 1]});
+    }
+}
+
+struct HostMeta {
+    std::vector<uint32_t> frame0;  // 2 per node
+    std::vector<uint32_t> ev_off, ev_pos, ev_dx, ev_dz;
+    std::vector<uint32_t> leaf_fx;
+    std::vector<Frame> leaf_frame;
+};
+
+// Map the insertion list onto pass positions and Pauli masks, and compose
+// each node's frame from its parent's (Sec. 3.1: a child continues from a
+// copy of its parent's state, noise included).
+static void build_meta(const tqs_plan *p, const tqs_noise *nz, HostMeta *hm) {
+    const uint64_t N = p->n_nodes;
+    hm->frame0.assign(2 * N, 0);
+    hm->ev_off.assign(N + 1, 0);
+    const uint64_t E = nz->ev_gate.size();
+    hm->ev_pos.resize(E);
+    hm->ev_dx.resize(E);
+    hm->ev_dz.resize(E);
+    hm->leaf_fx.assign(p->n_leaves, 0);
+    hm->leaf_frame.assign(p->n_leaves, Frame());
+    std::vector<Frame> fend(N);
+    const uint32_t L = (uint32_t)p->arity.size();
+    for (uint32_t l = 0; l < L; l++) {
+        const uint64_t I = p->level_nodes[l], off = p->level_offset[l];
+        for (uint64_t m = 0; m < I; m++) {
+            const uint64_t nu = off + m;
+            Frame f;
+            if (l > 0) f = fend[p->level_offset[l - 1] + m / p->arity[l]];
+            hm->frame0[2 * nu] = f.x;
+            hm->frame0[2 * nu + 1] = f.z;
+            for (uint64_t e = nz->node_off[nu]; e < nz->node_off[nu + 1]; e++) {
+                const uint32_t g = nz->ev_gate[e];
+                const uint32_t code = nz->ev_code[e];
+                uint32_t dx = 0, dz = 0, ky = 0;
+                const uint32_t q[2] = {p->gate_q0[g], p->gate_q1[g]};
+                for (uint32_t j = 0; j < p->gate_a[g]; j++) {
+                    const uint32_t cj = (code >> (2 * j)) & 3u;
+                    if (cj == 1 || cj == 2) dx |= 1u << q[j];
+                    if (cj == 3 || cj == 2) dz |= 1u << q[j];
+                    if (cj == 2) ky++;  // Y = i X Z
+                }
+                // the product of the one-qubit factors: X^dx Z^dz up to i^ky
+                hm->ev_pos[e] = (p->gate_pass[g] << 16) | p->gate_pos[g];
+                hm->ev_dx[e] = dx;
+                hm->ev_dz[e] = dz;
+                f = compose(dx, dz, ky, f);
+            }
+            hm->ev_off[nu + 1] = (uint32_t)nz->node_off[nu + 1];
+            fend[nu] = f;
+            if (l == L - 1) {
+                hm->leaf_fx[m] = f.x;
+                hm->leaf_frame[m] = f;
+            }
+        }
+    }
+}
+
+template <typename R>
+static void launch_pass(const tqs_plan *p, const Layout &Ly, unsigned char *ws, hipStream_t s,
+                        const Task &t, uint32_t pass_idx, bool first) {
+    const PassDesc &pd = p->passes[pass_idx];
+    PassArgs<R> a;
+    a.states = reinterpret_cast<cplx<R> *>(ws);
+    a.slot_amps = 1ull << p->n;
+    const uint32_t *sched = reinterpret_cast<const uint32_t *>(ws + Ly.off_sched) + t.sched;
+    a.node_ids = sched;
+    a.src_slot = first ? sched + t.count : sched + 2 * t.count;
+    a.dst_slot = sched + 2 * t.count;
+    a.count = t.count;
+    const uint32_t tiles = 1u << pd.nfree;
+    a.work = t.count * tiles;
+    a.pass_key = pass_idx << 16;
+    a.pass = reinterpret_cast<const PassDesc *>(ws + Ly.off_passes) + pass_idx;
+    a.ops = reinterpret_cast<const OpDesc *>(ws + Ly.off_ops);
+    a.mats = reinterpret_cast<const cplx<R> *>(ws + Ly.off_mats);
+    a.meta.frame0 = reinterpret_cast<const uint32_t *>(ws + Ly.off_frame0);
+    a.meta.ev_off = reinterpret_cast<const uint32_t *>(ws + Ly.off_evoff);
+    a.meta.ev_pos = reinterpret_cast<const uint32_t *>(ws + Ly.off_evpos);
+    a.meta.ev_dx = reinterpret_cast<const uint32_t *>(ws + Ly.off_evdx);
+    a.meta.ev_dz = reinterpret_cast<const uint32_t *>(ws + Ly.off_evdz);
+    const uint32_t grid = (a.work + 7u) & ~7u;
+    const size_t lds = ((size_t)1 << pd.m) * sizeof(cplx<R>) + ((size_t)1 << pd.nh) * 4;
+    hipLaunchKernelGGL(pass_kernel<R>, dim3(grid), dim3(kThreads), lds, s, a);
+}
+
+
+template <typename R>
+static void launch_sample(const tqs_plan *p, const Layout &Ly, unsigned char *ws, hipStream_t s,
+                          const Task &t, uint64_t leaf_first) {
+    const uint32_t b = p->sample_b;
+    const uint32_t nblocks = 1u << (p->n - b);
+    const uint32_t *sched = reinterpret_cast<const uint32_t *>(ws + Ly.off_sched) + t.sched;
+    const cplx<R> *st = reinterpret_cast<const cplx<R> *>(ws);
+    double *sums = reinterpret_cast<double *>(ws + Ly.off_sums);
+    const uint32_t leaf_off = (uint32_t)p->level_offset.back();
+    hipLaunchKernelGGL(block_sums_kernel<R>, dim3(t.count * nblocks), dim3(kThreads), 0, s, st,
+                       1ull << p->n, sched + 2 * t.count, b, nblocks, sums);
+    hipLaunchKernelGGL(sample_kernel<R>, dim3(t.count), dim3(kThreads), 0, s, st, 1ull << p->n,
+                       sched + 2 * t.count, sched, leaf_off, b, nblocks, sums,
+                       reinterpret_cast<const double *>(ws + Ly.off_leafu),
+                       reinterpret_cast<const uint32_t *>(ws + Ly.off_leaffx),
+                       reinterpret_cast<uint64_t *>(ws + Ly.off_out), leaf_first);
+}
+
+static tqs_status check_noise(const tqs_plan *p, const tqs_noise *nz) {
+    if (!nz) return fail(TQS_E_ARG, "noise is NULL");
+    if (nz->n_gates != p->n_gates || nz->arity != p->arity || nz->cut != p->cut)
+        return fail(TQS_E_ARG, "noise list was sampled for another circuit or tree");
+    return TQS_OK;
+}
+
+static hipEvent_t pool_event(tqs_plan *p, size_t i) {
+    while (p->events.size() <= i) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        p->events.push_back((void *)e);
+    }
+    return (hipEvent_t)p->events[i];
+}
+
+struct Capture {
+    const uint64_t *leaves = nullptr;
+    uint64_t n = 0;
+    double *amps = nullptr;
+};
+
+template <typename R>
+static tqs_status run_t(tqs_plan *p, const tqs_noise *nz, unsigned char *ws, uint64_t ws_bytes,
+                        hipStream_t s, uint64_t first, uint64_t last, uint64_t *outcomes,
+                        tqs_run_stats *stats, const Capture &cap) {
+    const auto t0 = std::chrono::steady_clock::now();
+    tqs_status st = check_noise(p, nz);
+    if (st) return st;
+    if (first >= last || last > p->arity[0])
+        return fail(TQS_E_ARG, "subtree range [%llu, %llu) outside [0, %llu)", (unsigned long long)first,
+                    (unsigned long long)last, (unsigned long long)p->arity[0]);
+    if (!outcomes) return fail(TQS_E_ARG, "outcomes is NULL");
+    if (!ws) return fail(TQS_E_WORKSPACE, "workspace is NULL");
+    if (((uintptr_t)ws) & 255) return fail(TQS_E_WORKSPACE, "workspace must be 256-byte aligned");
+    const uint32_t L = (uint32_t)p->arity.size();
+    uint64_t per_subtree = 1;
+    for (uint32_t l = 1; l < L; l++) per_subtree *= p->arity[l];
+    const uint64_t leaf_first = first * per_subtree;
+    const uint64_t n_out = (last - first) * per_subtree;
+
+    HostMeta hm;
+    build_meta(p, nz, &hm);
+    std::vector<Task> tasks;
+    std::vector<uint32_t> sched;
+    Layout Ly0 = make_layout(p, nz->ev_gate.size(), n_out, 0);
+    build_schedule(p, first, last, &tasks, &sched, Ly0.slot_base);
+    Layout Ly = make_layout(p, nz->ev_gate.size(), n_out, sched.size());
+    if (ws_bytes < Ly.total)
+        return fail(TQS_E_WORKSPACE, "workspace has %llu bytes, the run needs %llu",
+                    (unsigned long long)ws_bytes, (unsigned long long)Ly.total);
+
+    // pack the metadata exactly as laid out in the workspace
+    std::vector<unsigned char> hb(Ly.off_sums - Ly.off_meta, 0);
+    auto put = [&](uint64_t off, const void *src, size_t bytes) {
+        if (bytes) std::memcpy(hb.data() + (off - Ly.off_meta), src, bytes);
+    };
+    {
+        std::vector<cplx<R>> mats(p->mats.size());
+        for (size_t i = 0; i < mats.size(); i++) mats[i] = {(R)p->mats[i].real(), (R)p->mats[i].imag()};
+        put(Ly.off_mats, mats.data(), mats.size() * sizeof(cplx<R>));
+    }
+    put(Ly.off_ops, p->ops.data(), p->ops.size() * sizeof(OpDesc));
+    put(Ly.off_passes, p->passes.data(), p->passes.size() * sizeof(PassDesc));
+    put(Ly.off_frame0, hm.frame0.data(), hm.frame0.size() * 4);
+    put(Ly.off_evoff, hm.ev_off.data(), hm.ev_off.size() * 4);
+    put(Ly.off_evpos, hm.ev_pos.data(), hm.ev_pos.size() * 4);
+    put(Ly.off_evdx, hm.ev_dx.data(), hm.ev_dx.size() * 4);
+    put(Ly.off_evdz, hm.ev_dz.data(), hm.ev_dz.size() * 4);
+    put(Ly.off_leafu, nz->leaf_u.data(), nz->leaf_u.size() * 8);
+    put(Ly.off_leaffx, hm.leaf_fx.data(), hm.leaf_fx.size() * 4);
+    put(Ly.off_sched, sched.data(), sched.size() * 4);
+
+    size_t ev_i = 0;
+    hipEvent_t e_begin = nullptr, e_end = nullptr;
+    if (stats) {
+        e_begin = pool_event(p, ev_i++);
+        if (!e_begin) return fail(TQS_E_HIP, "hipEventCreate failed");
+        HIP_TRY(hipEventRecord(e_begin, s), "hipEventRecord");
+    }
+    HIP_TRY(hipMemcpyAsync(ws + Ly.off_meta, hb.data(), hb.size(), hipMemcpyHostToDevice, s),
+            "metadata upload");
+
+    // capture requests: leaf -> capture indices
+    std::vector<std::vector<uint64_t>> cap_of;
+    std::vector<unsigned char> cap_host;
+    if (cap.n) {
+        cap_host.resize(Ly.state_bytes);
+    }
+
+    uint64_t launches = 0, pass_states = 0, bytes_passes = 0, bytes_sample = 0;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pass_ev, samp_ev;
+    const uint64_t state_bytes = Ly.state_bytes;
+    const uint32_t b = p->sample_b;
+    for (const Task &t : tasks) {
+        const tqs::Level &lv = p->levels[t.level];
+        hipEvent_t ea = nullptr, eb = nullptr, ec = nullptr;
+        if (stats) {
+            ea = pool_event(p, ev_i++);
+            eb = pool_event(p, ev_i++);
+            if (!ea || !eb) return fail(TQS_E_HIP, "hipEventCreate failed");
+            HIP_TRY(hipEventRecord(ea, s), "hipEventRecord");
+        }
+        for (uint32_t k = 0; k < lv.pass_count; k++) {
+            launch_pass<R>(p, Ly, ws, s, t, lv.pass_begin + k, k == 0);
+            launches++;
+            pass_states += t.count;
+            const bool init = (k == 0 && t.level == 0);
+            bytes_passes += (uint64_t)t.count * state_bytes * (init ? 1 : 2);
+        }
+        if (stats) {
+            HIP_TRY(hipEventRecord(eb, s), "hipEventRecord");
+            pass_ev.push_back({ea, eb});
+        }
+        if (t.level == L - 1) {
+            launch_sample<R>(p, Ly, ws, s, t, leaf_first);
+            launches += 2;
+            bytes_sample += (uint64_t)t.count * (state_bytes + (Ly.amp_bytes << b));
+            if (stats) {
+                ec = pool_event(p, ev_i++);
+                if (!ec) return fail(TQS_E_HIP, "hipEventCreate failed");
+                HIP_TRY(hipEventRecord(ec, s), "hipEventRecord");
+                samp_ev.push_back({eb, ec});
+            }
+            if (cap.n) {
+                // materialise the frame of requested leaves (standalone Pauli
+                // application into the scratch slot) and copy them out
+                for (uint32_t i = 0; i < t.count; i++) {
+                    const uint64_t lam = t.first + i;
+                    for (uint64_t ci = 0; ci < cap.n; ci++) {
+                        if (cap.leaves[ci] != lam) continue;
+                        const Frame &f = hm.leaf_frame[lam];
+                        const uint32_t slot = Ly.slot_base[L - 1] + i;
+                        const uint64_t amps = 1ull << p->n;
+                        const cplx<R> *in = reinterpret_cast<const cplx<R> *>(ws) + (uint64_t)slot * amps;
+                        cplx<R> *out = reinterpret_cast<cplx<R> *>(ws) + (uint64_t)Ly.scratch_slot * amps;
+                        hipLaunchKernelGGL(frame_apply_kernel<R>, dim3((uint32_t)((amps + kThreads - 1) / kThreads)),
+                                           dim3(kThreads), 0, s, in, out, amps, f.x, f.z, f.k);
+                        HIP_TRY(hipGetLastError(), "frame_apply launch");
+                        HIP_TRY(hipMemcpyAsync(cap_host.data(), out, state_bytes, hipMemcpyDeviceToHost, s),
+                                "capture copy");
+                        HIP_TRY(hipStreamSynchronize(s), "capture sync");
+                        const cplx<R> *h = reinterpret_cast<const cplx<R> *>(cap_host.data());
+                        double *dstp = cap.amps + ci * 2 * amps;
+                        for (uint64_t y = 0; y < amps; y++) {
+                            dstp[2 * y] = (double)h[y].re;
+                            dstp[2 * y + 1] = (double)h[y].im;
+                        }
+                    }
+                }
+            }
+        }
+        HIP_TRY(hipGetLastError(), "kernel launch");
+    }
+    HIP_TRY(hipMemcpyAsync(outcomes, ws + Ly.off_out, n_out * 8, hipMemcpyDeviceToHost, s),
+            "outcome download");
+    if (stats) {
+        e_end = pool_event(p, ev_i++);
+        if (!e_end) return fail(TQS_E_HIP, "hipEventCreate failed");
+        HIP_TRY(hipEventRecord(e_end, s), "hipEventRecord");
+    }
+    HIP_TRY(hipStreamSynchronize(s), "stream synchronize");
+    if (stats) {
+        std::memset(stats, 0, sizeof *stats);
+        float ms = 0;
+        HIP_TRY(hipEventElapsedTime(&ms, e_begin, e_end), "hipEventElapsedTime");
+        stats->ms_device = ms;
+        for (auto &pr : pass_ev) {
+            HIP_TRY(hipEventElapsedTime(&ms, pr.first, pr.second), "hipEventElapsedTime");
+            stats->ms_passes += ms;
+        }
+        for (auto &pr : samp_ev) {
+            HIP_TRY(hipEventElapsedTime(&ms, pr.first, pr.second), "hipEventElapsedTime");
+            stats->ms_sample += ms;
+        }
+        stats->launches = launches;
+        stats->pass_states = pass_states;
+        stats->bytes_passes = bytes_passes;
+        stats->bytes_sample = bytes_sample;
+        stats->events = nz->ev_gate.size();
+        stats->ms_wall =
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return TQS_OK;
+}
+
+static tqs_status run_any(tqs_plan *p, const tqs_noise *nz, void *ws, uint64_t ws_bytes, void *stream,
+                          uint64_t first, uint64_t last, uint64_t *outcomes, tqs_run_stats *stats,
+                          const Capture &cap) {
+    if (!p) return fail(TQS_E_ARG, "plan is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    if (p->prec == TQS_C64)
+        return run_t<float>(p, nz, (unsigned char *)ws, ws_bytes, s, first, last, outcomes, stats, cap);
+    return run_t<double>(p, nz, (unsigned char *)ws, ws_bytes, s, first, last, outcomes, stats, cap);
+}
+
+}  // namespace tqs
+
+using namespace tqs;
+
+tqs_plan::~tqs_plan() {
+    for (void *e : events) hipEventDestroy((hipEvent_t)e);
+}
+
+#define TQS_GUARD_BEGIN try {
+#define TQS_GUARD_END                                         \
+    }                                                         \
+    catch (const std::bad_alloc &) {                          \
+        return fail(TQS_E_OOM, "host allocation failed");     \
+    }                                                         \
+    catch (...) {                                             \
+        return fail(TQS_E_ARG, "unexpected exception");       \
+    }
+
+extern "C" {
+
+tqs_status tqs_workspace_bytes(const tqs_plan *p, const tqs_noise *nz, uint64_t *bytes) {
+    TQS_GUARD_BEGIN
+    if (!p || !bytes) return fail(TQS_E_ARG, "plan or bytes is NULL");
+    uint64_t ev = 0;
+    if (nz) {
+        tqs_status st = check_noise(p, nz);
+        if (st) return st;
+        ev = nz->ev_gate.size();
+    } else {
+        for (size_t l = 0; l < p->arity.size(); l++)
+            ev += p->level_nodes[l] * (uint64_t)(p->cut[l + 1] - p->cut[l]);
+    }
+    Layout Ly = make_layout(p, ev, p->n_leaves, 3 * p->n_nodes);
+    *bytes = Ly.total;
+    return TQS_OK;
+    TQS_GUARD_END
+}
+
+tqs_status tqs_run(tqs_plan *p, const tqs_noise *nz, void *d_workspace, uint64_t ws_bytes, void *stream,
+                   uint64_t *outcomes, tqs_run_stats *stats) {
+    TQS_GUARD_BEGIN
+    if (!p) return fail(TQS_E_ARG, "plan is NULL");
+    return run_any(p, nz, d_workspace, ws_bytes, stream, 0, p->arity[0], outcomes, stats, Capture());
+    TQS_GUARD_END
+}
+
+tqs_status tqs_run_range(tqs_plan *p, const tqs_noise *nz, void *d_workspace, uint64_t ws_bytes,
+                         void *stream, uint64_t first, uint64_t last, uint64_t *outcomes,
+                         tqs_run_stats *stats) {
+    TQS_GUARD_BEGIN
+    return run_any(p, nz, d_workspace, ws_bytes, stream, first, last, outcomes, stats, Capture());
+    TQS_GUARD_END
+}
+
+tqs_status tqs_run_capture(tqs_plan *p, const tqs_noise *nz, void *d_workspace, uint64_t ws_bytes,
+                           void *stream, uint64_t *outcomes, const uint64_t *leaves, uint64_t n,
+                           double *host_amps) {
+    TQS_GUARD_BEGIN
+    if (!p) return fail(TQS_E_ARG, "plan is NULL");
+    if (n && (!leaves || !host_amps)) return fail(TQS_E_ARG, "leaves or host_amps is NULL");
+    for (uint64_t i = 0; i < n; i++)
+        if (leaves[i] >= p->n_leaves) return fail(TQS_E_ARG, "leaf %llu out of range", (unsigned long long)leaves[i]);
+    Capture cap;
+    cap.leaves = leaves;
+    cap.n = n;
+    cap.amps = host_amps;
+    return run_any(p, nz, d_workspace, ws_bytes, stream, 0, p->arity[0], outcomes, nullptr, cap);
+    TQS_GUARD_END
+}
+
+tqs_status tqs_probe_copy(void *d_workspace, uint64_t bytes, uint32_t reps, void *stream, double *gbps) {
+    TQS_GUARD_BEGIN
+    if (!d_workspace || !gbps || reps < 1 || bytes < 4096 || (bytes & 15))
+        return fail(TQS_E_ARG, "bad probe arguments");
+    if (((uintptr_t)d_workspace) & 255) return fail(TQS_E_WORKSPACE, "workspace must be 256-byte aligned");
+    hipStream_t s = (hipStream_t)stream;
+    const uint4 *in = (const uint4 *)d_workspace;
+    uint4 *out = (uint4 *)((unsigned char *)d_workspace + bytes);
+    const uint64_t n16 = bytes / 16;
+    const uint32_t grid = (uint32_t)std::min<uint64_t>((n16 + kThreads - 1) / kThreads, 256u * 16u);
+    hipEvent_t a, b;
+    HIP_TRY(hipEventCreate(&a), "hipEventCreate");
+    HIP_TRY(hipEventCreate(&b), "hipEventCreate");
+    hipLaunchKernelGGL(copy_kernel, dim3(grid), dim3(kThreads), 0, s, in, out, n16);
+    HIP_TRY(hipEventRecord(a, s), "hipEventRecord");
+    for (uint32_t r = 0; r < reps; r++) hipLaunchKernelGGL(copy_kernel, dim3(grid), dim3(kThreads), 0, s, in, out, n16);
+    HIP_TRY(hipEventRecord(b, s), "hipEventRecord");
+    HIP_TRY(hipEventSynchronize(b), "hipEventSynchronize");
+    float ms = 0;
+    HIP_TRY(hipEventElapsedTime(&ms, a, b), "hipEventElapsedTime");
+    hipEventDestroy(a);
+    hipEventDestroy(b);
+    *gbps = 2.0 * (double)bytes * reps / (ms * 1e-3) / 1e9;
+    return TQS_OK;
+    TQS_GUARD_END
+}
+
+}  // extern "C"

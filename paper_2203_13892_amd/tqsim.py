@@ -1,0 +1,328 @@
+"""Python binding of ``libtqsim.so`` (argument marshalling only).
+
+Every simulation step runs in the library's HIP kernels; this module only
+converts arrays, owns the opaque handles and lets PyTorch supply the device
+workspace and the stream.  The library must have been built
+(``python -m paper_2203_13892_amd.build``); importing this module without it
+raises immediately -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtqsim.so")
+
+C64, C128 = 0, 1
+_PREC = {"c64": C64, "c128": C128, C64: C64, C128: C128}
+
+u32, u64, dbl, i32, vp = C.c_uint32, C.c_uint64, C.c_double, C.c_int, C.c_void_p
+P = C.POINTER
+
+
+class TqsTree(C.Structure):
+    _fields_ = [("levels", u32), ("arity", P(u64)), ("cut", P(u32))]
+
+
+class TqsTuning(C.Structure):
+    _fields_ = [("tile_qubits", u32), ("max_ops_per_pass", u32), ("chunk_states", u32),
+                ("sample_block_log", u32)]
+
+
+class TqsRunStats(C.Structure):
+    _fields_ = [("ms_wall", dbl), ("ms_device", dbl), ("ms_passes", dbl), ("ms_sample", dbl),
+                ("launches", u64), ("pass_states", u64), ("bytes_passes", u64),
+                ("bytes_sample", u64), ("events", u64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+# name -> (restype, argtypes): every symbol declared in include/tqsim.h
+SIGNATURES = {
+    "tqs_circuit_create": (i32, [u32, P(vp)]),
+    "tqs_circuit_add_gate": (i32, [vp, u32, P(u32), P(dbl), P(dbl)]),
+    "tqs_circuit_set_depolarizing": (i32, [vp, dbl, dbl]),
+    "tqs_circuit_info": (i32, [vp, P(u32), P(u32)]),
+    "tqs_circuit_destroy": (None, [vp]),
+    "tqs_dcp": (i32, [vp, u64, dbl, dbl, dbl, u32, P(u32), P(u64), P(u32)]),
+    "tqs_noise_sample": (i32, [vp, P(TqsTree), u64, P(vp)]),
+    "tqs_noise_import": (i32, [vp, P(TqsTree), P(u64), P(u32), P(C.c_uint8), P(dbl), P(vp)]),
+    "tqs_noise_view": (i32, [vp, P(P(u64)), P(P(u32)), P(P(C.c_uint8)), P(P(dbl)), P(u64), P(u64)]),
+    "tqs_noise_destroy": (None, [vp]),
+    "tqs_plan_create": (i32, [vp, P(TqsTree), i32, P(TqsTuning), P(vp)]),
+    "tqs_plan_info": (i32, [vp, u32, P(u32), P(u32), P(u32)]),
+    "tqs_workspace_bytes": (i32, [vp, vp, P(u64)]),
+    "tqs_plan_destroy": (None, [vp]),
+    "tqs_run": (i32, [vp, vp, vp, u64, vp, P(u64), P(TqsRunStats)]),
+    "tqs_run_range": (i32, [vp, vp, vp, u64, vp, u64, u64, P(u64), P(TqsRunStats)]),
+    "tqs_run_capture": (i32, [vp, vp, vp, u64, vp, P(u64), P(u64), u64, P(dbl)]),
+    "tqs_histogram": (i32, [P(u64), u64, P(u64), P(u64), P(u64)]),
+    "tqs_probe_copy": (i32, [vp, u64, u32, vp, P(dbl)]),
+    "tqs_last_error": (C.c_char_p, []),
+    "tqs_version": (C.c_char_p, []),
+}
+
+STATUS = {0: "TQS_OK", -1: "TQS_E_ARG", -2: "TQS_E_SHAPE", -3: "TQS_E_WORKSPACE",
+          -4: "TQS_E_HIP", -5: "TQS_E_OOM", -6: "TQS_E_UNSUPPORTED"}
+
+
+class TqsError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS.get(status, status), msg))
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libtqsim.so is not built (%s); run python -m paper_2203_13892_amd.build"
+                          % LIB_PATH)
+    L = C.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    return L
+
+
+lib = _load()
+
+
+def _check(st):
+    if st != 0:
+        raise TqsError(st, lib.tqs_last_error().decode())
+
+
+def _ptr(a, ct):
+    return a.ctypes.data_as(P(ct))
+
+
+def version() -> str:
+    return lib.tqs_version().decode()
+
+
+# ----------------------------------------------------------------- circuit --
+
+class Circuit:
+    """Owned tqs_circuit handle."""
+
+    def __init__(self, n: int):
+        h = vp()
+        _check(lib.tqs_circuit_create(n, C.byref(h)))
+        self.h = h
+        self.n = n
+
+    def add_gate(self, qubits, mat, probs=None):
+        q = np.ascontiguousarray(np.asarray(qubits, np.uint32))
+        m = np.ascontiguousarray(np.asarray(mat, np.complex128)).view(np.float64)
+        p = None if probs is None else np.ascontiguousarray(np.asarray(probs, np.float64))
+        _check(lib.tqs_circuit_add_gate(self.h, q.size, _ptr(q, u32), _ptr(m, dbl),
+                                        None if p is None else _ptr(p, dbl)))
+        return self
+
+    def set_depolarizing(self, p1: float, p2: float):
+        _check(lib.tqs_circuit_set_depolarizing(self.h, p1, p2))
+        return self
+
+    @property
+    def n_gates(self) -> int:
+        n, g = u32(), u32()
+        _check(lib.tqs_circuit_info(self.h, C.byref(n), C.byref(g)))
+        return g.value
+
+    @classmethod
+    def from_workload(cls, wc) -> "Circuit":
+        """From a ``workloads.Circuit`` (gates with matrices and probabilities)."""
+        c = cls(wc.n)
+        for q, m, p in wc.gates:
+            c.add_gate(q, m, p)
+        return c
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            lib.tqs_circuit_destroy(h)
+            self.h = vp()
+
+
+class _Tree:
+    def __init__(self, arity, cut):
+        self.A = np.ascontiguousarray(np.asarray(arity, np.uint64))
+        self.cut = np.ascontiguousarray(np.asarray(cut, np.uint32))
+        self.s = TqsTree(self.A.size, _ptr(self.A, u64), _ptr(self.cut, u32))
+
+
+def dcp(circuit: Circuit, shots: int, z: float = 1.96, eps: float = 0.01, copy_cost: float = 1.0,
+        max_levels: int = 16):
+    """Dynamic Circuit Partition; returns (arity list, cut list)."""
+    lv = u32()
+    A = np.zeros(max_levels, np.uint64)
+    cut = np.zeros(max_levels + 1, np.uint32)
+    _check(lib.tqs_dcp(circuit.h, shots, z, eps, copy_cost, max_levels, C.byref(lv),
+                       _ptr(A, u64), _ptr(cut, u32)))
+    k = lv.value
+    return [int(a) for a in A[:k]], [int(c) for c in cut[:k + 1]]
+
+
+# ------------------------------------------------------------------- noise --
+
+class Noise:
+    """Owned tqs_noise handle (insertion list + leaf uniforms)."""
+
+    def __init__(self, h):
+        self.h = h
+
+    @classmethod
+    def sample(cls, circuit: Circuit, tree, seed: int) -> "Noise":
+        t = _Tree(*tree)
+        h = vp()
+        _check(lib.tqs_noise_sample(circuit.h, C.byref(t.s), seed, C.byref(h)))
+        return cls(h)
+
+    @classmethod
+    def from_arrays(cls, circuit: Circuit, tree, node_off, ev_gate, ev_code, leaf_u) -> "Noise":
+        t = _Tree(*tree)
+        no = np.ascontiguousarray(np.asarray(node_off, np.uint64))
+        eg = np.ascontiguousarray(np.asarray(ev_gate, np.uint32))
+        ec = np.ascontiguousarray(np.asarray(ev_code, np.uint8))
+        lu = np.ascontiguousarray(np.asarray(leaf_u, np.float64))
+        if eg.size == 0:
+            eg, ec = np.zeros(1, np.uint32), np.zeros(1, np.uint8)
+        h = vp()
+        _check(lib.tqs_noise_import(circuit.h, C.byref(t.s), _ptr(no, u64), _ptr(eg, u32),
+                                    _ptr(ec, C.c_uint8), _ptr(lu, dbl), C.byref(h)))
+        return cls(h)
+
+    def arrays(self):
+        """Copies of (node_off, ev_gate, ev_code, leaf_u)."""
+        no, eg, ec, lu = P(u64)(), P(u32)(), P(C.c_uint8)(), P(dbl)()
+        nn, nl = u64(), u64()
+        _check(lib.tqs_noise_view(self.h, C.byref(no), C.byref(eg), C.byref(ec), C.byref(lu),
+                                  C.byref(nn), C.byref(nl)))
+        node_off = np.ctypeslib.as_array(no, (nn.value + 1,)).copy()
+        ne = int(node_off[-1])
+        ev_gate = np.ctypeslib.as_array(eg, (ne,)).copy() if ne else np.zeros(0, np.uint32)
+        ev_code = np.ctypeslib.as_array(ec, (ne,)).copy() if ne else np.zeros(0, np.uint8)
+        leaf_u = np.ctypeslib.as_array(lu, (nl.value,)).copy()
+        return node_off, ev_gate, ev_code, leaf_u
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            lib.tqs_noise_destroy(h)
+            self.h = vp()
+
+
+# -------------------------------------------------------------------- plan --
+
+class Plan:
+    """Owned tqs_plan handle."""
+
+    def __init__(self, circuit: Circuit, tree, precision="c64", tuning=None):
+        t = _Tree(*tree)
+        self.tree = (list(map(int, t.A)), list(map(int, t.cut)))
+        tu = None
+        if tuning:
+            tu = TqsTuning(**{k: int(v) for k, v in tuning.items()})
+        h = vp()
+        _check(lib.tqs_plan_create(circuit.h, C.byref(t.s), _PREC[precision],
+                                   C.byref(tu) if tu is not None else None, C.byref(h)))
+        self.h = h
+        self.n = circuit.n
+        self.precision = _PREC[precision]
+        self.n_leaves = int(np.prod(self.tree[0], dtype=object))
+
+    def info(self, level: int = 0):
+        a, b, c = u32(), u32(), u32()
+        _check(lib.tqs_plan_info(self.h, level, C.byref(a), C.byref(b), C.byref(c)))
+        return {"passes_level": a.value, "passes_total": b.value, "chunk_states": c.value}
+
+    def workspace_bytes(self, noise: Noise = None) -> int:
+        b = u64()
+        _check(lib.tqs_workspace_bytes(self.h, noise.h if noise is not None else None, C.byref(b)))
+        return b.value
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            lib.tqs_plan_destroy(h)
+            self.h = vp()
+
+
+# --------------------------------------------------------------------- run --
+
+class Workspace:
+    """Device workspace owned by a torch uint8 tensor, 256-byte aligned."""
+
+    def __init__(self, nbytes: int, device="cuda"):
+        import torch
+        self.tensor = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        base = self.tensor.data_ptr()
+        self.ptr = (base + 255) & ~255
+        self.nbytes = nbytes
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return vp(stream.cuda_stream)
+
+
+def run(plan: Plan, noise: Noise, workspace: Workspace = None, stream=None, stats: bool = False,
+        subtrees=None):
+    """Simulate the tree; returns outcomes (uint64 per leaf) and, with
+    ``stats``, a dict of device timings and byte counts."""
+    need = plan.workspace_bytes(noise)
+    if workspace is None:
+        workspace = Workspace(need)
+    st = TqsRunStats() if stats else None
+    s = _stream(stream)
+    if subtrees is None:
+        out = np.zeros(plan.n_leaves, np.uint64)
+        _check(lib.tqs_run(plan.h, noise.h, vp(workspace.ptr), workspace.nbytes, s,
+                           _ptr(out, u64), C.byref(st) if st is not None else None))
+    else:
+        first, last = subtrees
+        per = plan.n_leaves // plan.tree[0][0]
+        out = np.zeros((last - first) * per, np.uint64)
+        _check(lib.tqs_run_range(plan.h, noise.h, vp(workspace.ptr), workspace.nbytes, s,
+                                 first, last, _ptr(out, u64),
+                                 C.byref(st) if st is not None else None))
+    return (out, st.as_dict()) if stats else out
+
+
+def run_capture(plan: Plan, noise: Noise, leaves, workspace: Workspace = None, stream=None):
+    """Outcomes of all leaves plus the final complex128 amplitudes of
+    ``leaves`` (noise frame applied)."""
+    need = plan.workspace_bytes(noise)
+    if workspace is None:
+        workspace = Workspace(need)
+    lv = np.ascontiguousarray(np.asarray(leaves, np.uint64))
+    amps = np.zeros((lv.size, 1 << plan.n), np.complex128)
+    out = np.zeros(plan.n_leaves, np.uint64)
+    _check(lib.tqs_run_capture(plan.h, noise.h, vp(workspace.ptr), workspace.nbytes, _stream(stream),
+                               _ptr(out, u64), _ptr(lv, u64), lv.size,
+                               amps.view(np.float64).ctypes.data_as(P(dbl))))
+    return out, amps
+
+
+def histogram(outcomes):
+    o = np.ascontiguousarray(np.asarray(outcomes, np.uint64))
+    n = o.size
+    vals = np.zeros(max(n, 1), np.uint64)
+    cnts = np.zeros(max(n, 1), np.uint64)
+    nu = u64()
+    _check(lib.tqs_histogram(_ptr(o, u64), n, _ptr(vals, u64), _ptr(cnts, u64), C.byref(nu)))
+    return vals[:nu.value], cnts[:nu.value]
+
+
+def probe_copy(nbytes: int, reps: int = 10, stream=None) -> float:
+    """Device copy bandwidth (GB/s, read + write) of the library's streaming kernel."""
+    ws = Workspace(2 * nbytes)
+    g = dbl()
+    _check(lib.tqs_probe_copy(vp(ws.ptr), nbytes, reps, _stream(stream), C.byref(g)))
+    return g.value

@@ -1,0 +1,232 @@
+"""GPU parity: the HIP path against the CPU oracle, element by element.
+
+Both sides read the same seeded circuit; each side draws the noise
+insertion list with its own implementation of the same counter-based
+generator (bit-identity of the two lists is a host test), or both read an
+explicit list written by the test.  Amplitudes agree to 1e-5 (complex64)
+and 1e-12 (complex128) max-abs; outcomes are identical except at leaves
+whose FP64 CDF passes within delta * T of the threshold u * T (delta 1e-6
+for complex64, 1e-12 for complex128), which are counted, not failed.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2203_13892_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"c64": 1e-5, "c128": 1e-12}
+DELTA = {"c64": 1e-6, "c128": 1e-12}
+
+
+@pytest.fixture(scope="module")
+def T():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2203_13892_amd import tqsim
+    return tqsim
+
+
+def boundary_ok(psi, u, delta):
+    p = np.abs(psi) ** 2
+    tot = p.sum()
+    pre = np.cumsum(p)
+    return np.min(np.abs(pre - u * tot)) < delta * tot
+
+
+def check_outcomes(got, want, states, leaf_u, delta):
+    """Identical outcomes except at CDF-boundary leaves; returns their count."""
+    bad = np.nonzero(got != want)[0]
+    for i in bad:
+        assert boundary_ok(states[i], leaf_u[i], delta), (int(i), int(got[i]), int(want[i]))
+    return bad.size
+
+
+def run_both(T, wc, tree, seed, prec, leaves, tuning=None, noise_arrays=None):
+    c = T.Circuit.from_workload(wc)
+    if noise_arrays is None:
+        nz = T.Noise.sample(c, tree, seed)
+        onz = oracle.sample_noise(wc.gates, tree, seed)
+    else:
+        nz = T.Noise.from_arrays(c, tree, *noise_arrays)
+        onz = oracle.Noise(*[np.asarray(a) for a in noise_arrays])
+    plan = T.Plan(c, tree, prec, tuning)
+    out, amps = T.run_capture(plan, nz, leaves)
+    oout, ost = oracle.run_leaves(wc.n, wc.gates, tree, onz, leaves, states=True)
+    return out, amps, oout, ost, onz
+
+
+def event_arrays(wc, tree, rng, rate=0.3):
+    """An explicit insertion list with events on a fraction of gate slots."""
+    A, cut = tree
+    node_off, eg, ec = [0], [], []
+    for l in range(len(A)):
+        I = int(np.prod(A[:l + 1]))
+        for _ in range(I):
+            for g in range(cut[l], cut[l + 1]):
+                if rng.random() < rate:
+                    eg.append(g)
+                    ec.append(int(rng.integers(1, 4 ** len(wc.gates[g][0]))))
+            node_off.append(len(eg))
+    leaves = int(np.prod(A))
+    return (np.array(node_off, np.uint64), np.array(eg, np.uint32), np.array(ec, np.uint8),
+            rng.random(leaves))
+
+
+def mixed_gates(n, count, rng):
+    """Every op class: dense 1q, diagonal 1q/2q, controlled, dense 2q, swap,
+    on low / high / mixed qubit positions."""
+    c = W.Circuit(n)
+    for i in range(count):
+        kind = i % 7
+        if kind == 0:
+            c.add((int(rng.integers(n)),), W.haar_unitary(2, rng))
+        elif kind == 1:
+            c.add((int(rng.integers(n)),), W.phase(float(rng.uniform(0, 6))))
+        else:
+            a, b = [int(x) for x in rng.choice(n, 2, replace=False)]
+            if kind == 2:
+                c.add((a, b), W.cphase(float(rng.uniform(0, 6))))
+            elif kind == 3:
+                c.add((a, b), W.cx())
+            elif kind == 4:
+                c.add((a, b), W.haar_unitary(4, rng))
+            elif kind == 5:
+                c.add((a, b), W.swap())
+            else:
+                c.add((a, b), W.rzz(float(rng.uniform(0, 6))))
+    return c
+
+
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+@pytest.mark.parametrize("n", [1, 2, 5, 9, 14])
+def test_every_op_class_with_forced_noise(T, prec, n):
+    rng = np.random.default_rng(100 + n)
+    wc = mixed_gates(n, 60, rng) if n > 1 else W.Circuit(1, [((0,), W.haar_unitary(2, rng), None)] * 3)
+    if n == 1:
+        wc.add((0,), W.phase(0.3))
+    tree = ([6], [0, len(wc)])
+    arr = event_arrays(wc, tree, rng)
+    out, amps, oout, ost, _ = run_both(T, wc, tree, 0, prec, np.arange(6), noise_arrays=arr)
+    assert np.max(np.abs(amps - ost)) < TOL[prec]
+    check_outcomes(out, oout, ost, arr[3], DELTA[prec])
+
+
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+def test_tree_levels_ragged_chunks(T, prec):
+    rng = np.random.default_rng(7)
+    n = 13
+    wc = mixed_gates(n, 45, rng)
+    tree = ([3, 4, 5], [0, 10, 27, 45])
+    arr = event_arrays(wc, tree, rng, rate=0.15)
+    leaves = np.arange(60)
+    out, amps, oout, ost, _ = run_both(T, wc, tree, 0, prec, leaves,
+                                       tuning={"chunk_states": 7, "max_ops_per_pass": 5},
+                                       noise_arrays=arr)
+    assert np.max(np.abs(amps - ost)) < TOL[prec]
+    check_outcomes(out, oout, ost, arr[3], DELTA[prec])
+
+
+def test_c1_qft10_per_shot_c128_all_leaves(T):
+    # 10-qubit QFT, depolarizing 1e-3 / 1e-2, 1000 shots, per-shot, seed 0
+    wc = W.qft(10).with_depolarizing(1e-3, 1e-2)
+    tree = ([1000], [0, len(wc)])
+    leaves = np.arange(1000)
+    out, amps, oout, ost, onz = run_both(T, wc, tree, 0, "c128", leaves)
+    assert np.max(np.abs(amps - ost)) < 1e-12
+    nb = check_outcomes(out, oout, ost, onz.leaf_u, DELTA["c128"])
+    assert nb <= 2
+
+
+def test_c1_qft10_per_shot_c64(T):
+    wc = W.qft(10).with_depolarizing(1e-3, 1e-2)
+    tree = ([1000], [0, len(wc)])
+    leaves = np.arange(0, 1000, 7)
+    out, amps, oout, ost, onz = run_both(T, wc, tree, 0, "c64", leaves)
+    assert np.max(np.abs(amps - ost)) < 1e-5
+    check_outcomes(out[leaves], oout, ost, onz.leaf_u[leaves], DELTA["c64"])
+
+
+def test_outcomes_all_leaves_c64_small(T):
+    # every leaf's outcome at complex64 against the oracle (boundary leaves counted)
+    wc = W.concat(W.ghz(8), W.random_circuit(8, 30, seed=3)).with_depolarizing(0.01, 0.05)
+    tree = ([8, 4, 4], [0, 12, 25, len(wc)])
+    c = T.Circuit.from_workload(wc)
+    nz = T.Noise.sample(c, tree, 11)
+    out = T.run(T.Plan(c, tree, "c64"), nz)
+    onz = oracle.sample_noise(wc.gates, tree, 11)
+    oout, ost = oracle.run_leaves(8, wc.gates, tree, onz, states=True)
+    nb = check_outcomes(out, oout, ost, onz.leaf_u, DELTA["c64"])
+    assert nb <= 3
+
+
+@pytest.mark.parametrize("family", ["qft", "bw"])
+def test_c2_20q_tree_sampled_leaves(T, family):
+    # 20 qubits, 16384 leaves of the (16, 32, 32) tree, complex64; the
+    # oracle recomputes a sample of leaves (all of level-0 subtree 0's first
+    # sibling group plus random ones)
+    if family == "qft":
+        wc = W.qft(20).with_depolarizing(1e-3, 1e-2)
+    else:
+        wc = W.brickwall(20, 20, seed=1).with_depolarizing(1e-3, 1e-2)
+    G = len(wc)
+    tree = ([16, 32, 32], [0, G // 3, 2 * G // 3, G])
+    rng = np.random.default_rng(5)
+    leaves = np.unique(np.concatenate([np.arange(8), rng.choice(16384, 16, replace=False)]))
+    out, amps, oout, ost, onz = run_both(T, wc, tree, 0, "c64", leaves)
+    assert np.max(np.abs(amps - ost)) < 1e-5
+    check_outcomes(out[leaves], oout, ost, onz.leaf_u[leaves], DELTA["c64"])
+
+
+def test_range_runs_equal_full_run(T):
+    wc = W.qft(12).with_depolarizing(0.01, 0.03)
+    tree = ([6, 5, 4], [0, 30, 60, len(wc)])
+    c = T.Circuit.from_workload(wc)
+    nz = T.Noise.sample(c, tree, 2)
+    plan = T.Plan(c, tree, "c64", {"chunk_states": 9})
+    full = T.run(plan, nz)
+    parts = [T.run(plan, nz, subtrees=(a, b)) for a, b in [(0, 1), (1, 4), (4, 6)]]
+    assert np.array_equal(np.concatenate(parts), full)
+
+
+def test_deterministic(T):
+    wc = W.brickwall(16, 8, seed=3).with_depolarizing(0.01, 0.02)
+    tree = ([8, 16], [0, 30, len(wc)])
+    c = T.Circuit.from_workload(wc)
+    nz = T.Noise.sample(c, tree, 4)
+    plan = T.Plan(c, tree, "c64")
+    a = T.run(plan, nz)
+    b = T.run(plan, nz)
+    assert np.array_equal(a, b)
+
+
+def test_noiseless_ghz_outcomes(T):
+    # closed form: every outcome is 0..0 or 1..1
+    n = 16
+    wc = W.ghz(n)
+    c = T.Circuit.from_workload(wc)
+    tree = ([64, 8], [0, 5, n])
+    out = T.run(T.Plan(c, tree), T.Noise.sample(c, tree, 0))
+    assert set(np.unique(out).tolist()) <= {0, (1 << n) - 1}
+    frac = np.mean(out == 0)
+    assert abs(frac - 0.5) < 4 * math.sqrt(0.25 / out.size)
+
+
+def test_tree_histogram_vs_density_matrix(T):
+    # statistics: tree estimate of the outcome distribution within a clustered
+    # bound of the exact density-matrix distribution
+    from oracle import density, tree as otree
+    n = 4
+    wc = W.concat(W.ghz(n), W.random_circuit(n, 8, seed=2)).with_depolarizing(0.05, 0.1)
+    p_dm = np.real(np.diag(density.dm_run(n, wc.gates)))
+    A = [256, 4, 4]
+    tree = (A, [0, 5, 9, len(wc)])
+    c = T.Circuit.from_workload(wc)
+    out = T.run(T.Plan(c, tree), T.Noise.sample(c, tree, 1))
+    p_hat = otree.hist_probs(out, n)
+    bound = 0.5 * np.sum(np.sqrt(p_dm * (1 - p_dm) / A[0]))
+    assert otree.tv_distance(p_hat, p_dm) < 3 * bound
