@@ -96,6 +96,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--forms", default="tree,pershot,tree4a,tree4b")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--tile", type=int, default=0, help="tile qubits (0 = library default)")
+    ap.add_argument("--pass-cost", type=int, default=0, help="per-pass work bound (0 = default)")
+    ap.add_argument("--chunk", type=int, default=0, help="live states per level (0 = default)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -123,7 +126,10 @@ def main():
     results = {}
     for name in args.forms.split(","):
         tree = forms[name]
-        sps, ms, agg, _ = time_form(T, torch, circuit, tree, args.seed, args.steps, args.warmup)
+        tuning = {k: v for k, v in (("tile_qubits", args.tile), ("pass_cost", args.pass_cost),
+                                     ("chunk_states", args.chunk)) if v}
+        sps, ms, agg, _ = time_form(T, torch, circuit, tree, args.seed, args.steps, args.warmup,
+                                    tuning or None)
         results[name] = {"shots_per_s": sps, "ms_per_step": ms, "shape": tree[0], "cut": tree[1],
                          "pass_GBps": agg["bytes_passes"] / (agg["ms_passes"] * 1e-3) / 1e9,
                          "ms_passes": agg["ms_passes"] / args.steps,

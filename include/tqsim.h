@@ -82,10 +82,14 @@ typedef struct {
 
 /* Planner and executor knobs; zero fields take the defaults. */
 typedef struct {
-    uint32_t tile_qubits;      /* qubits staged per workgroup tile (default 12 c64, 11 c128) */
-    uint32_t max_ops_per_pass; /* gate ops applied per HBM pass (default 24) */
+    uint32_t tile_qubits;      /* qubits per one-wave tile: 6 lane + register qubits
+                                  (10..12 at complex64, default 12; 10..11 at complex128,
+                                  default 11) */
+    uint32_t max_ops_per_pass; /* gates applied per HBM pass (default 1024) */
     uint32_t chunk_states;     /* live states per tree level (default 256) */
     uint32_t sample_block_log; /* log2 amplitudes per sampling block (default 12) */
+    uint32_t pass_cost;        /* estimated lane instructions per amplitude allowed in one
+                                  pass before a new pass starts (default 80) */
 } tqs_tuning;
 
 /* Timing and traffic of one run. */

@@ -42,7 +42,15 @@ __device__ __forceinline__ cplx<R> cmac(cplx<R> acc, cplx<R> a, cplx<R> b) {
 
 template <typename R>
 __device__ __forceinline__ cplx<R> cneg_if(cplx<R> a, uint32_t neg) {
-    return neg ? cplx<R>{-a.re, -a.im} : a;
+    // sign flip as an integer xor, so uniform values stay in scalar registers
+    if constexpr (sizeof(R) == 4) {
+        const uint32_t m = neg ? 0x80000000u : 0u;
+        return {__uint_as_float(__float_as_uint(a.re) ^ m), __uint_as_float(__float_as_uint(a.im) ^ m)};
+    } else {
+        const unsigned long long m = neg ? 0x8000000000000000ull : 0ull;
+        return {__longlong_as_double((long long)((unsigned long long)__double_as_longlong(a.re) ^ m)),
+                __longlong_as_double((long long)((unsigned long long)__double_as_longlong(a.im) ^ m))};
+    }
 }
 
 // Per-node noise metadata in device memory.
@@ -54,196 +62,11 @@ struct NodeMeta {
     const uint32_t *ev_dz;
 };
 
-template <typename R>
-struct PassArgs {
-    cplx<R> *states;
-    uint64_t slot_amps;
-    const uint32_t *node_ids;
-    const uint32_t *src_slot;
-    const uint32_t *dst_slot;
-    uint32_t count;
-    uint32_t work;  // count * tiles (unpadded)
-    uint32_t pass_key;
-    const PassDesc *pass;
-    const OpDesc *ops;
-    const cplx<R> *mats;
-    NodeMeta meta;
-};
+}  // namespace tqs
 
-__device__ __forceinline__ uint32_t insert_zero(uint32_t p, uint32_t t) {
-    const uint32_t lo = p & ((1u << t) - 1u);
-    return ((p >> t) << (t + 1)) | lo;
-}
+#include "pass_kernel.h"
 
-// The gate-apply pass: one workgroup stages one tile (2^m amplitudes: a
-// contiguous run of 2^c plus the staged high qubits) of one trajectory in
-// LDS, applies the pass's ops in order with the trajectory's Pauli frame,
-// and writes the tile back.  Each amplitude is read and written once per
-// pass.  Work items are laid out so each XCD gets a contiguous range:
-// neighbouring items are sibling trajectories on the same tile, which share
-// a parent state on a branching pass.
-template <typename R>
-__global__ __launch_bounds__(kThreads) void pass_kernel(PassArgs<R> a) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    const uint32_t nwg = gridDim.x;
-    const uint32_t bid = blockIdx.x;
-    const uint32_t w = (bid & 7u) * (nwg >> 3) + (bid >> 3);
-    if (w >= a.work) return;
-    const uint32_t traj = w % a.count;
-    const uint32_t tile = w / a.count;
-    const uint32_t tid = threadIdx.x;
-
-    const PassDesc *pd = a.pass;
-    const uint32_t m = pd->m, c = pd->c, nh = pd->nh, nfree = pd->nfree;
-    const uint32_t M = 1u << m;
-
-    cplx<R> *buf = reinterpret_cast<cplx<R> *>(smem);
-    uint32_t *hoff = reinterpret_cast<uint32_t *>(smem + (size_t)M * sizeof(cplx<R>));
-
-    // tile base: tile-index bits deposited on the free qubits
-    uint32_t base = 0;
-    for (uint32_t i = 0; i < nfree; i++) base |= ((tile >> i) & 1u) << pd->fbits[i];
-    for (uint32_t h = tid; h < (1u << nh); h += kThreads) {
-        uint32_t o = 0;
-        for (uint32_t b = 0; b < nh; b++) o |= ((h >> b) & 1u) << pd->hbits[b];
-        hoff[h] = o;
-    }
-
-    // frame at the start of this pass
-    const uint32_t node = a.node_ids[traj];
-    uint32_t fx = a.meta.frame0[2 * node], fz = a.meta.frame0[2 * node + 1];
-    uint32_t e = a.meta.ev_off[node];
-    const uint32_t e1 = a.meta.ev_off[node + 1];
-    while (e < e1 && a.meta.ev_pos[e] < a.pass_key) {
-        fx ^= a.meta.ev_dx[e];
-        fz ^= a.meta.ev_dz[e];
-        e++;
-    }
-    __syncthreads();
-
-    const uint32_t src_s = a.src_slot[traj];
-    const cplx<R> *src = src_s == kInit ? nullptr : a.states + (uint64_t)src_s * a.slot_amps;
-    cplx<R> *dst = a.states + (uint64_t)a.dst_slot[traj] * a.slot_amps;
-    const uint32_t cmask = (1u << c) - 1u;
-    for (uint32_t l = tid; l < M; l += kThreads) {
-        const uint32_t g = base + hoff[l >> c] + (l & cmask);
-        cplx<R> v;
-        if (src) {
-            v = src[g];
-        } else {
-            v.re = g == 0 ? R(1) : R(0);
-            v.im = R(0);
-        }
-        buf[l] = v;
-    }
-    __syncthreads();
-
-    for (uint32_t j = 0; j < pd->op_count; j++) {
-        const uint32_t key = a.pass_key | j;
-        while (e < e1 && a.meta.ev_pos[e] <= key) {
-            fx ^= a.meta.ev_dx[e];
-            fz ^= a.meta.ev_dz[e];
-            e++;
-        }
-        const OpDesc o = a.ops[pd->op_begin + j];
-        uint32_t xl = (fx >> o.phys[0]) & 1u, zl = (fz >> o.phys[0]) & 1u;
-        if (o.nq == 2) {
-            xl |= ((fx >> o.phys[1]) & 1u) << 1;
-            zl |= ((fz >> o.phys[1]) & 1u) << 1;
-        }
-        const cplx<R> *G = a.mats + o.mat;
-        if (o.kind == OP_DENSE1) {
-            // F^dagger G F: entries G[r^x][c^x] with sign (-1)^{z.r + z.c}
-            cplx<R> g00 = G[(0 ^ xl) * 2 + (0 ^ xl)], g01 = G[(0 ^ xl) * 2 + (1 ^ xl)];
-            cplx<R> g10 = G[(1 ^ xl) * 2 + (0 ^ xl)], g11 = G[(1 ^ xl) * 2 + (1 ^ xl)];
-            g01 = cneg_if(g01, zl);
-            g10 = cneg_if(g10, zl);
-            const uint32_t t = o.loc[0];
-            for (uint32_t p = tid; p < (M >> 1); p += kThreads) {
-                const uint32_t i0 = insert_zero(p, t), i1 = i0 | (1u << t);
-                const cplx<R> x0 = buf[i0], x1 = buf[i1];
-                buf[i0] = cmac(cmul(g00, x0), g01, x1);
-                buf[i1] = cmac(cmul(g10, x0), g11, x1);
-            }
-        } else if (o.kind == OP_DIAG) {
-            // diagonal: d'(r) = d(r ^ x); qubits outside the tile are fixed
-            cplx<R> d[4];
-            const uint32_t k = 1u << o.nq;
-            for (uint32_t r = 0; r < 4; r++) d[r] = G[(r & (k - 1u)) ^ xl];
-            uint32_t rfix = 0;
-            int l0 = -1, l1 = -1;
-            if (o.loc[0] == kNotLocal) rfix |= (base >> o.phys[0]) & 1u; else l0 = o.loc[0];
-            if (o.nq == 2) {
-                if (o.loc[1] == kNotLocal) rfix |= ((base >> o.phys[1]) & 1u) << 1; else l1 = o.loc[1];
-            }
-            for (uint32_t l = tid; l < M; l += kThreads) {
-                uint32_t r = rfix;
-                if (l0 >= 0) r |= (l >> l0) & 1u;
-                if (l1 >= 0) r |= ((l >> l1) & 1u) << 1;
-                const cplx<R> lo = (r & 1u) ? d[1] : d[0];
-                const cplx<R> hi = (r & 1u) ? d[3] : d[2];
-                buf[l] = cmul((r & 2u) ? hi : lo, buf[l]);
-            }
-        } else if (o.kind == OP_CTRL) {
-            // block-diagonal in gate qubit o.ctrl, dense in the other
-            const uint32_t jc = o.ctrl, jt = 1u - jc;
-            const uint32_t t = jt ? o.loc[1] : o.loc[0];
-            cplx<R> blk[2][4];
-            for (uint32_t bc = 0; bc < 2; bc++)
-                for (uint32_t rr = 0; rr < 2; rr++)
-                    for (uint32_t cc = 0; cc < 2; cc++) {
-                        const uint32_t r = (bc << jc) | (rr << jt), cl = (bc << jc) | (cc << jt);
-                        cplx<R> v = G[(r ^ xl) * 4 + (cl ^ xl)];
-                        v = cneg_if(v, (__builtin_popcount(zl & r) + __builtin_popcount(zl & cl)) & 1u);
-                        blk[bc][rr * 2 + cc] = v;
-                    }
-            const uint32_t locc = jc ? o.loc[1] : o.loc[0], physc = jc ? o.phys[1] : o.phys[0];
-            const int lc = locc == kNotLocal ? -1 : (int)locc;
-            const uint32_t cfix = (base >> physc) & 1u;
-            for (uint32_t p = tid; p < (M >> 1); p += kThreads) {
-                const uint32_t i0 = insert_zero(p, t), i1 = i0 | (1u << t);
-                const uint32_t bc = lc >= 0 ? ((i0 >> lc) & 1u) : cfix;
-                const cplx<R> b0 = bc ? blk[1][0] : blk[0][0], b1 = bc ? blk[1][1] : blk[0][1];
-                const cplx<R> b2 = bc ? blk[1][2] : blk[0][2], b3 = bc ? blk[1][3] : blk[0][3];
-                const cplx<R> x0 = buf[i0], x1 = buf[i1];
-                buf[i0] = cmac(cmul(b0, x0), b1, x1);
-                buf[i1] = cmac(cmul(b2, x0), b3, x1);
-            }
-        } else {  // OP_DENSE2
-            cplx<R> g[16];
-            for (uint32_t r = 0; r < 4; r++)
-                for (uint32_t cl = 0; cl < 4; cl++) {
-                    cplx<R> v = G[(r ^ xl) * 4 + (cl ^ xl)];
-                    g[r * 4 + cl] =
-                        cneg_if(v, (__builtin_popcount(zl & r) + __builtin_popcount(zl & cl)) & 1u);
-                }
-            const uint32_t t0 = o.loc[0], t1 = o.loc[1];
-            const uint32_t lo = t0 < t1 ? t0 : t1, hi = t0 < t1 ? t1 : t0;
-            for (uint32_t p = tid; p < (M >> 2); p += kThreads) {
-                const uint32_t i = insert_zero(insert_zero(p, lo), hi);
-                uint32_t idx[4];
-                cplx<R> x[4];
-                for (uint32_t r = 0; r < 4; r++) {
-                    idx[r] = i | ((r & 1u) << t0) | (((r >> 1) & 1u) << t1);
-                    x[r] = buf[idx[r]];
-                }
-                for (uint32_t r = 0; r < 4; r++) {
-                    cplx<R> acc = cmul(g[r * 4], x[0]);
-                    acc = cmac(acc, g[r * 4 + 1], x[1]);
-                    acc = cmac(acc, g[r * 4 + 2], x[2]);
-                    acc = cmac(acc, g[r * 4 + 3], x[3]);
-                    buf[idx[r]] = acc;
-                }
-            }
-        }
-        __syncthreads();
-    }
-
-    for (uint32_t l = tid; l < M; l += kThreads) {
-        const uint32_t g = base + hoff[l >> c] + (l & cmask);
-        dst[g] = buf[l];
-    }
-}
+namespace tqs {
 
 // FP64 sums of |psi|^2 over blocks of 2^b consecutive amplitudes.
 template <typename R>
@@ -440,8 +263,8 @@ struct Layout {
     uint32_t slots_total;
     std::vector<uint32_t> slot_base;  // per level
     uint32_t scratch_slot;
-    uint64_t off_meta, off_mats, off_ops, off_passes, off_frame0, off_evoff, off_evpos, off_evdx,
-        off_evdz, off_leafu, off_leaffx, off_sched, off_sums, off_out, total;
+    uint64_t off_meta, off_mats, off_ops, off_passes, off_terms, off_dgates, off_expt, off_frame0, off_evoff,
+        off_evpos, off_evdx, off_evdz, off_leafu, off_leaffx, off_sched, off_sums, off_out, total;
     uint64_t n_sched;
 };
 
@@ -464,6 +287,12 @@ static Layout make_layout(const tqs_plan *p, uint64_t n_events, uint64_t n_leave
     o = align256(o + p->ops.size() * sizeof(OpDesc));
     L.off_passes = o;
     o = align256(o + p->passes.size() * sizeof(PassDesc));
+    L.off_terms = o;
+    o = align256(o + p->terms.size() * sizeof(DiagTerm));
+    L.off_dgates = o;
+    o = align256(o + p->dgates.size() * sizeof(DiagGate));
+    L.off_expt = o;
+    o = align256(o + 256 * L.amp_bytes);
     L.off_frame0 = o;
     o = align256(o + p->n_nodes * 8);
     L.off_evoff = o;
@@ -616,9 +445,31 @@ static void launch_pass(const tqs_plan *p, const Layout &Ly, unsigned char *ws, 
     a.meta.ev_pos = reinterpret_cast<const uint32_t *>(ws + Ly.off_evpos);
     a.meta.ev_dx = reinterpret_cast<const uint32_t *>(ws + Ly.off_evdx);
     a.meta.ev_dz = reinterpret_cast<const uint32_t *>(ws + Ly.off_evdz);
+    a.terms = reinterpret_cast<const DiagTerm *>(ws + Ly.off_terms);
+    a.dgates = reinterpret_cast<const DiagGate *>(ws + Ly.off_dgates);
+    a.expt = reinterpret_cast<const cplx<R> *>(ws + Ly.off_expt);
     const uint32_t grid = (a.work + 7u) & ~7u;
-    const size_t lds = ((size_t)1 << pd.m) * sizeof(cplx<R>) + ((size_t)1 << pd.nh) * 4;
-    hipLaunchKernelGGL(pass_kernel<R>, dim3(grid), dim3(kThreads), lds, s, a);
+    // one wave per workgroup; the register-qubit count is a compile-time tile width
+    const bool d2 = pd.has_d2 != 0;
+    const size_t lds = 0;
+#define TQS_LAUNCH(RB)                                                                        \
+    do {                                                                                       \
+        if (d2) hipLaunchKernelGGL((pass_kernel<R, RB, true>), dim3(grid), dim3(64), lds, s, a); \
+        else hipLaunchKernelGGL((pass_kernel<R, RB, false>), dim3(grid), dim3(64), lds, s, a);   \
+    } while (0)
+    if constexpr (sizeof(R) == 4) {
+        switch (p->reg_bits) {
+            case 4: TQS_LAUNCH(4); break;
+            case 5: TQS_LAUNCH(5); break;
+            default: TQS_LAUNCH(6); break;
+        }
+    } else {
+        switch (p->reg_bits) {
+            case 4: TQS_LAUNCH(4); break;
+            default: TQS_LAUNCH(5); break;
+        }
+    }
+#undef TQS_LAUNCH
 }
 
 
@@ -704,6 +555,17 @@ static tqs_status run_t(tqs_plan *p, const tqs_noise *nz, unsigned char *ws, uin
     }
     put(Ly.off_ops, p->ops.data(), p->ops.size() * sizeof(OpDesc));
     put(Ly.off_passes, p->passes.data(), p->passes.size() * sizeof(PassDesc));
+    put(Ly.off_terms, p->terms.data(), p->terms.size() * sizeof(DiagTerm));
+    put(Ly.off_dgates, p->dgates.data(), p->dgates.size() * sizeof(DiagGate));
+    {
+        // e^{2 pi i k / 256} for the phase-run exponentials
+        std::vector<cplx<R>> et(256);
+        for (int k = 0; k < 256; k++) {
+            const double ang = 2.0 * 3.14159265358979323846 * k / 256.0;
+            et[k] = {(R)std::cos(ang), (R)std::sin(ang)};
+        }
+        put(Ly.off_expt, et.data(), et.size() * sizeof(cplx<R>));
+    }
     put(Ly.off_frame0, hm.frame0.data(), hm.frame0.size() * 4);
     put(Ly.off_evoff, hm.ev_off.data(), hm.ev_off.size() * 4);
     put(Ly.off_evpos, hm.ev_pos.data(), hm.ev_pos.size() * 4);

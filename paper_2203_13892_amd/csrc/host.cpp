@@ -393,204 +393,6 @@ void tqs_noise_destroy(tqs_noise *nz) { delete nz; }
 
 }  // extern "C"
 
-// ---------------------------------------------------------------- planner --
-
-static bool is_zero(const cd &v) { return v.real() == 0.0 && v.imag() == 0.0; }
-
-// Gate structure: diagonal, or block-diagonal in one qubit (that qubit's
-// value never changes, so it need not be staged in the tile).
-static OpKind classify(const Gate &g, uint8_t *ctrl) {
-    const int k = 1 << g.a;
-    bool diag = true;
-    for (int r = 0; r < k; r++)
-        for (int c = 0; c < k; c++)
-            if (r != c && !is_zero(g.m[r * k + c])) diag = false;
-    if (diag) return OP_DIAG;
-    if (g.a == 1) return OP_DENSE1;
-    for (int j = 0; j < 2; j++) {
-        bool blk = true;
-        for (int r = 0; r < 4; r++)
-            for (int c = 0; c < 4; c++)
-                if (((r >> j) & 1) != ((c >> j) & 1) && !is_zero(g.m[r * 4 + c])) blk = false;
-        if (blk) {
-            *ctrl = (uint8_t)j;
-            return OP_CTRL;
-        }
-    }
-    return OP_DENSE2;
-}
-
-// Qubits that must be staged in the tile for this gate.
-static uint32_t active_mask(const Gate &g, OpKind k, uint8_t ctrl) {
-    switch (k) {
-        case OP_DIAG: return 0;
-        case OP_DENSE1: return 1u << g.q[0];
-        case OP_DENSE2: return (1u << g.q[0]) | (1u << g.q[1]);
-        case OP_CTRL: return 1u << g.q[1 - ctrl];
-    }
-    return 0;
-}
-
-static uint32_t popc(uint32_t x) { return (uint32_t)__builtin_popcount(x); }
-
-extern "C" tqs_status tqs_plan_create(const tqs_circuit *c, const tqs_tree *tree, tqs_precision prec,
-                                      const tqs_tuning *tuning, tqs_plan **out) {
-    TQS_GUARD_BEGIN
-    if (!c || !out) return fail(TQS_E_ARG, "circuit or out is NULL");
-    *out = nullptr;
-    if (prec != TQS_C64 && prec != TQS_C128) return fail(TQS_E_ARG, "unknown precision %d", (int)prec);
-    std::vector<uint64_t> A;
-    std::vector<uint32_t> cut;
-    tqs_status st = validate_tree(tree, (uint32_t)c->gates.size(), &A, &cut);
-    if (st) return st;
-    tqs_tuning tu{};
-    if (tuning) tu = *tuning;
-    if (!tu.tile_qubits) tu.tile_qubits = prec == TQS_C64 ? 12 : 11;
-    if (!tu.max_ops_per_pass) tu.max_ops_per_pass = 24;
-    if (!tu.chunk_states) tu.chunk_states = 256;
-    if (!tu.sample_block_log) tu.sample_block_log = 12;
-    if (tu.tile_qubits < 8 || tu.tile_qubits > kMaxTile)
-        return fail(TQS_E_ARG, "tile_qubits must be in 8..%u", kMaxTile);
-    if (prec == TQS_C128 && tu.tile_qubits > 11)
-        return fail(TQS_E_ARG, "tile_qubits must be <= 11 at complex128 (LDS size)");
-    if (tu.sample_block_log < 8 || tu.sample_block_log > 16)
-        return fail(TQS_E_ARG, "sample_block_log must be in 8..16");
-    if (tu.max_ops_per_pass > 4096) return fail(TQS_E_ARG, "max_ops_per_pass too large");
-
-    tqs_plan *p = new tqs_plan;
-    p->n = c->n;
-    p->prec = prec;
-    p->tune = tu;
-    p->arity = A;
-    p->cut = cut;
-    p->n_gates = (uint32_t)c->gates.size();
-    const uint32_t L = (uint32_t)A.size();
-    uint64_t off = 0;
-    for (uint32_t l = 0; l < L; l++) {
-        p->level_offset.push_back(off);
-        p->level_nodes.push_back(level_nodes(A, l));
-        off += p->level_nodes.back();
-    }
-    p->n_nodes = off;
-    p->n_leaves = p->level_nodes.back();
-    p->sample_b = std::min(c->n, tu.sample_block_log);
-    p->gate_pass.assign(p->n_gates, 0);
-    p->gate_pos.assign(p->n_gates, 0);
-    p->gate_q0.assign(p->n_gates, 0);
-    p->gate_q1.assign(p->n_gates, 0);
-    p->gate_a.assign(p->n_gates, 0);
-
-    const uint32_t n = c->n;
-    const uint32_t m = std::min(n, tu.tile_qubits);
-    const uint32_t cmin = std::min(n, kMinContig);
-    const uint32_t lowmask = cmin >= 32 ? 0xFFFFFFFFu : ((1u << cmin) - 1u);
-
-    struct Pending {
-        uint32_t active = 0;
-        std::vector<std::pair<uint32_t, uint8_t>> ops;  // gate, ctrl | kind << 4
-    };
-
-    auto emit = [&](Pending &pd) {
-        PassDesc d;
-        std::memset(&d, 0, sizeof d);
-        // tile: low run + the active qubits, then grown by the lowest free qubits
-        uint32_t T = lowmask | pd.active;
-        for (uint32_t b = 0; b < n && popc(T) < m; b++) T |= 1u << b;
-        uint32_t cc = 0;
-        while (cc < n && ((T >> cc) & 1)) cc++;
-        d.m = popc(T);
-        d.c = cc;
-        d.nh = 0;
-        uint8_t local_of[32];
-        std::memset(local_of, kNotLocal, sizeof local_of);
-        for (uint32_t b = 0; b < cc; b++) local_of[b] = (uint8_t)b;
-        for (uint32_t b = cc; b < n; b++)
-            if ((T >> b) & 1) {
-                local_of[b] = (uint8_t)(cc + d.nh);
-                d.hbits[d.nh++] = (uint8_t)b;
-            }
-        d.nfree = 0;
-        for (uint32_t b = 0; b < n; b++)
-            if (!((T >> b) & 1)) d.fbits[d.nfree++] = (uint8_t)b;
-        d.op_begin = (uint32_t)p->ops.size();
-        d.op_count = (uint32_t)pd.ops.size();
-        for (auto &pr : pd.ops) {
-            const Gate &g = c->gates[pr.first];
-            OpDesc o;
-            std::memset(&o, 0, sizeof o);
-            o.kind = pr.second >> 4;
-            o.ctrl = pr.second & 0xF;
-            o.nq = (uint8_t)g.a;
-            for (uint32_t j = 0; j < g.a; j++) {
-                o.phys[j] = (uint8_t)g.q[j];
-                o.loc[j] = local_of[g.q[j]];
-            }
-            if (g.a == 1) {
-                o.phys[1] = 0;
-                o.loc[1] = kNotLocal;
-            }
-            o.mat = (uint32_t)p->mats.size();
-            const int k = 1 << g.a;
-            if (o.kind == OP_DIAG) {
-                for (int i = 0; i < k; i++) p->mats.push_back(g.m[i * k + i]);
-            } else {
-                for (int i = 0; i < k * k; i++) p->mats.push_back(g.m[i]);
-            }
-            p->ops.push_back(o);
-        }
-        p->passes.push_back(d);
-        pd = Pending();
-    };
-
-    for (uint32_t l = 0; l < L; l++) {
-        tqs::Level lv;
-        lv.pass_begin = (uint32_t)p->passes.size();
-        lv.g0 = cut[l];
-        lv.g1 = cut[l + 1];
-        Pending pd;
-        for (uint32_t gi = cut[l]; gi < cut[l + 1]; gi++) {
-            const Gate &g = c->gates[gi];
-            uint8_t ctrl = 0;
-            OpKind k = classify(g, &ctrl);
-            const uint32_t act = active_mask(g, k, ctrl);
-            const uint32_t need = popc(lowmask | pd.active | act);
-            if (!pd.ops.empty() && (need > m || pd.ops.size() >= tu.max_ops_per_pass)) emit(pd);
-            pd.active |= act;
-            pd.ops.push_back({gi, (uint8_t)(ctrl | (k << 4))});
-            p->gate_pass[gi] = (uint32_t)p->passes.size();  // index of the pass being built
-            p->gate_pos[gi] = (uint32_t)pd.ops.size();
-            p->gate_a[gi] = g.a;
-            p->gate_q0[gi] = g.q[0];
-            p->gate_q1[gi] = g.a == 2 ? g.q[1] : g.q[0];
-        }
-        emit(pd);
-        lv.pass_count = (uint32_t)p->passes.size() - lv.pass_begin;
-        p->levels.push_back(lv);
-    }
-    if (p->passes.size() >= (1u << 16)) {
-        delete p;
-        return fail(TQS_E_UNSUPPORTED, "too many passes (%zu)", p->passes.size());
-    }
-    // live states per level
-    for (uint32_t l = 0; l < L; l++)
-        p->chunk.push_back((uint32_t)std::min<uint64_t>(p->level_nodes[l], tu.chunk_states));
-    *out = p;
-    return TQS_OK;
-    TQS_GUARD_END
-}
-
-extern "C" tqs_status tqs_plan_info(const tqs_plan *p, uint32_t level, uint32_t *passes_level,
-                                    uint32_t *passes_total, uint32_t *chunk_states) {
-    if (!p) return fail(TQS_E_ARG, "plan is NULL");
-    if (level >= p->levels.size()) return fail(TQS_E_ARG, "level %u out of range", level);
-    if (passes_level) *passes_level = p->levels[level].pass_count;
-    if (passes_total) *passes_total = (uint32_t)p->passes.size();
-    if (chunk_states) *chunk_states = p->chunk[level];
-    return TQS_OK;
-}
-
-extern "C" void tqs_plan_destroy(tqs_plan *p) { delete p; }
-
 // -------------------------------------------------------------- histogram --
 
 extern "C" tqs_status tqs_histogram(const uint64_t *outcomes, uint64_t n, uint64_t *values,

@@ -1,0 +1,703 @@
+// Gate-apply pass kernel for gfx950: one wave per workgroup, one tile of
+// one trajectory per wave, the whole tile held in registers.
+//
+// Tile layout: lane L (0..63) holds the amplitudes whose physical qubits
+// 0..nl-1 spell L, register index j (0..2^RB-1) spells the register qubits
+// rq[0..nr-1], and the free qubits are fixed by the tile index.  Each
+// register index is one fully coalesced wave load / store (64 consecutive
+// amplitudes).  Gates on register qubits are in-register butterflies, gates
+// on lane qubits exchange partners with cross-lane shuffles, diagonal gates
+// need no exchange at all.  Nothing goes through LDS and the wave never
+// waits on a barrier; every amplitude is read once and written once.
+//
+// Noise is carried by the trajectory's Pauli frame (x, z): a gate G acts on
+// the stored state as F^dagger G F, i.e. G[r ^ x][c ^ x] (-1)^{z.r + z.c} on
+// the gate's local indices.  Frame updates are events placed between gate
+// slots of the pass.
+#pragma once
+
+#include <type_traits>
+#include <utility>
+
+namespace tqs {
+
+template <typename R>
+struct PassArgs {
+    cplx<R> *states;
+    uint64_t slot_amps;
+    const uint32_t *node_ids;
+    const uint32_t *src_slot;
+    const uint32_t *dst_slot;
+    uint32_t count;
+    uint32_t work;  // count * tiles (unpadded)
+    uint32_t pass_key;
+    const PassDesc *pass;
+    const OpDesc *ops;
+    const cplx<R> *mats;
+    const DiagTerm *terms;
+    const DiagGate *dgates;
+    const cplx<R> *expt;  // e^{2 pi i k / 256}, k = 0..255
+    NodeMeta meta;
+};
+
+template <typename R>
+__device__ __forceinline__ cplx<R> csel(bool c, cplx<R> a, cplx<R> b) {
+    return c ? a : b;
+}
+
+template <typename R>
+__device__ __forceinline__ cplx<R> shfl_xor_c(cplx<R> v, uint32_t mask) {
+    return {__shfl_xor(v.re, (int)mask), __shfl_xor(v.im, (int)mask)};
+}
+
+// Real-coefficient products (the matrix entry's imaginary part is zero).
+template <typename R>
+__device__ __forceinline__ cplx<R> rmul(cplx<R> m, cplx<R> x) {
+    return {m.re * x.re, m.re * x.im};
+}
+template <typename R>
+__device__ __forceinline__ cplx<R> rmac(cplx<R> acc, cplx<R> m, cplx<R> x) {
+    return {acc.re + m.re * x.re, acc.im + m.re * x.im};
+}
+
+// Bounds how many cross-lane exchanges the scheduler keeps in flight (each
+// holds result registers until consumed): a fence after every 4th index.
+template <int J>
+__device__ __forceinline__ void shuffle_fence() {
+    if constexpr ((J & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+}
+
+// Value of lane `lane` (a compile-time constant) broadcast to the wave.
+__device__ __forceinline__ float bcast_lane(float x, int lane) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), lane));
+}
+__device__ __forceinline__ double bcast_lane(double x, int lane) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xFFFFFFFFll), lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// e^{2 pi i t} for fixed-point turns t: the nearest of 256 table points
+// times the Taylor series of the remaining angle |x| <= pi / 256 (truncation
+// error below 3e-12 in single, 1e-22 in double precision).
+__device__ __forceinline__ cplx<float> expi_turns(uint32_t t, const cplx<float> *tab) {
+    const uint32_t k = ((t + (1u << 23)) >> 24) & 255u;
+    const int32_t r = (int32_t)(t - (k << 24));
+    const float x = (float)r * 1.4629180792671596e-09f;  // 2 pi / 2^32
+    const float x2 = x * x;
+    const float s = x * (1.0f - x2 * (1.0f / 6.0f));
+    const float c = 1.0f - x2 * (0.5f - x2 * (1.0f / 24.0f));
+    const cplx<float> e = tab[k];
+    return {e.re * c - e.im * s, e.re * s + e.im * c};
+}
+__device__ __forceinline__ cplx<double> expi_turns(uint64_t t, const cplx<double> *tab) {
+    const uint64_t k = ((t + (1ull << 55)) >> 56) & 255u;
+    const int64_t r = (int64_t)(t - (k << 56));
+    const double x = (double)r * 3.4061215800865545e-19;  // 2 pi / 2^64
+    const double x2 = x * x;
+    const double s = x * (1.0 - x2 / 6.0 * (1.0 - x2 / 20.0 * (1.0 - x2 / 42.0 * (1.0 - x2 / 72.0))));
+    const double c = 1.0 - x2 / 2.0 * (1.0 - x2 / 12.0 * (1.0 - x2 / 30.0 * (1.0 - x2 / 56.0)));
+    const cplx<double> e = tab[k];
+    return {e.re * c - e.im * s, e.re * s + e.im * c};
+}
+
+// Phase accumulator type: 32-bit turns at complex64, 64-bit at complex128.
+template <typename R>
+struct Turns;
+template <>
+struct Turns<float> {
+    using T = uint32_t;
+};
+template <>
+struct Turns<double> {
+    using T = uint64_t;
+};
+
+template <int N>
+using IC = std::integral_constant<int, N>;
+
+// Compile-time loop: f(IC<0>{}), .., f(IC<N-1>{}) -- every register index
+// stays a constant, so the tile never leaves registers.
+template <typename F, int... Is>
+__device__ __forceinline__ void sfor_impl(F &&f, std::integer_sequence<int, Is...>) {
+    (f(IC<Is>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void sfor(F &&f) {
+    sfor_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// Call f(IC<i>) for a runtime register bit i < RB.
+template <int RB, typename F>
+__device__ __forceinline__ void with_reg(uint32_t i, F &&f) {
+    switch (i) {
+        case 0: if constexpr (RB > 0) f(IC<0>{}); break;
+        case 1: if constexpr (RB > 1) f(IC<1>{}); break;
+        case 2: if constexpr (RB > 2) f(IC<2>{}); break;
+        case 3: if constexpr (RB > 3) f(IC<3>{}); break;
+        case 4: if constexpr (RB > 4) f(IC<4>{}); break;
+        case 5: if constexpr (RB > 5) f(IC<5>{}); break;
+        default: break;
+    }
+}
+
+// Frame-conjugated 2x2 / 4x4 entry: G[(r^x) * k + (c^x)] (-1)^{z.r + z.c}
+template <typename R>
+__device__ __forceinline__ cplx<R> conj_entry(const cplx<R> *G, uint32_t k, uint32_t r, uint32_t c,
+                                              uint32_t xl, uint32_t zl) {
+    const cplx<R> v = G[(r ^ xl) * k + (c ^ xl)];
+    return cneg_if(v, (__builtin_popcount(zl & r) + __builtin_popcount(zl & c)) & 1u);
+}
+
+// ---------------------------------------------------------------- DENSE1 --
+// 2x2 on the target qubit; with nq == 2 the gate is block-diagonal in the
+// other (control) qubit and the control's value selects the block.
+template <bool REAL, typename R>
+__device__ __forceinline__ cplx<R> mmul(cplx<R> m, cplx<R> x) {
+    if constexpr (REAL) return rmul(m, x);
+    else return cmul(m, x);
+}
+template <bool REAL, typename R>
+__device__ __forceinline__ cplx<R> mmac(cplx<R> a, cplx<R> m, cplx<R> x) {
+    if constexpr (REAL) return rmac(a, m, x);
+    else return cmac(a, m, x);
+}
+
+// Target on register bit I: one 2x2 M for every pair (M wave-uniform, or
+// per lane when a lane qubit controls it).
+template <typename R, int RB, bool REAL, int I>
+__device__ __forceinline__ void d1_reg(cplx<R> (&v)[1 << RB], const cplx<R> (&M)[4]) {
+    sfor<(1 << RB)>([&](auto Jc) __attribute__((always_inline)) {
+        constexpr int j = decltype(Jc)::value;
+        if constexpr (!(j & (1 << I))) {
+            const cplx<R> x0 = v[j], x1 = v[j | (1 << I)];
+            v[j] = mmac<REAL>(mmul<REAL>(M[0], x0), M[1], x1);
+            v[j | (1 << I)] = mmac<REAL>(mmul<REAL>(M[2], x0), M[3], x1);
+        }
+    });
+}
+
+// Target on register bit I, control on register bit cpos: the block of each
+// pair is chosen by a wave-uniform bit of its register index.
+template <typename R, int RB, bool REAL, int I>
+__device__ __forceinline__ void d1_reg_ctrl(cplx<R> (&v)[1 << RB], const cplx<R> (&B)[2][4], uint32_t cpos) {
+    sfor<(1 << RB)>([&](auto Jc) __attribute__((always_inline)) {
+        constexpr int j = decltype(Jc)::value;
+        if constexpr (!(j & (1 << I))) {
+            const bool cb = (((uint32_t)j >> cpos) & 1u) != 0;
+            const cplx<R> x0 = v[j], x1 = v[j | (1 << I)];
+            const cplx<R> m0 = csel(cb, B[1][0], B[0][0]), m1 = csel(cb, B[1][1], B[0][1]);
+            const cplx<R> m2 = csel(cb, B[1][2], B[0][2]), m3 = csel(cb, B[1][3], B[0][3]);
+            v[j] = mmac<REAL>(mmul<REAL>(m0, x0), m1, x1);
+            v[j | (1 << I)] = mmac<REAL>(mmul<REAL>(m2, x0), m3, x1);
+        }
+    });
+}
+
+// Target on a lane bit: own row b, partner (lane ^ mask) column 1 - b; with
+// a register control the row pair (a, c) comes from block 0 or 1 per index.
+template <typename R, int RB, bool REAL, bool CREG>
+__device__ __forceinline__ void d1_lane(cplx<R> (&v)[1 << RB], uint32_t mask, cplx<R> a0, cplx<R> c0,
+                                        cplx<R> a1, cplx<R> c1, uint32_t cpos) {
+    sfor<(1 << RB)>([&](auto Jc) __attribute__((always_inline)) {
+        constexpr int j = decltype(Jc)::value;
+        const cplx<R> p = shfl_xor_c(v[j], mask);
+        cplx<R> a = a0, c = c0;
+        if constexpr (CREG) {
+            const bool cb = (((uint32_t)j >> cpos) & 1u) != 0;
+            a = csel(cb, a1, a0);
+            c = csel(cb, c1, c0);
+        }
+        v[j] = mmac<REAL>(mmul<REAL>(a, v[j]), c, p);
+        shuffle_fence<j>();
+    });
+}
+
+template <typename R, int RB, bool REAL>
+__device__ __forceinline__ void dense1_apply(cplx<R> (&v)[1 << RB], const cplx<R> (&B)[2][4], uint32_t crole,
+                                             uint32_t cpos, uint32_t base, uint32_t trole, uint32_t tpos,
+                                             uint32_t L) {
+    const bool creg = crole == ROLE_REG;
+    if (trole == ROLE_REG) {
+        if (creg) {
+            with_reg<RB>(tpos, [&](auto Ic) __attribute__((always_inline)) {
+                d1_reg_ctrl<R, RB, REAL, decltype(Ic)::value>(v, B, cpos);
+            });
+        } else {
+            // no control, or a control fixed for the tile / the lane
+            uint32_t cb = 0;
+            if (crole == ROLE_FIXED) cb = (base >> cpos) & 1u;
+            else if (crole == ROLE_LANE) cb = (L >> cpos) & 1u;
+            cplx<R> M[4];
+#pragma unroll
+            for (int e = 0; e < 4; e++) M[e] = csel(cb != 0, B[1][e], B[0][e]);
+            with_reg<RB>(tpos, [&](auto Ic) __attribute__((always_inline)) {
+                d1_reg<R, RB, REAL, decltype(Ic)::value>(v, M);
+            });
+        }
+    } else {
+        const uint32_t b = (L >> tpos) & 1u;
+        cplx<R> a0 = csel(b != 0, B[0][3], B[0][0]), c0 = csel(b != 0, B[0][2], B[0][1]);
+        const cplx<R> a1 = csel(b != 0, B[1][3], B[1][0]), c1 = csel(b != 0, B[1][2], B[1][1]);
+        if (creg) {
+            d1_lane<R, RB, REAL, true>(v, 1u << tpos, a0, c0, a1, c1, cpos);
+        } else {
+            uint32_t cb = 0;
+            if (crole == ROLE_FIXED) cb = (base >> cpos) & 1u;
+            else if (crole == ROLE_LANE) cb = (L >> cpos) & 1u;
+            a0 = csel(cb != 0, a1, a0);
+            c0 = csel(cb != 0, c1, c0);
+            d1_lane<R, RB, REAL, false>(v, 1u << tpos, a0, c0, a1, c1, 0);
+        }
+    }
+}
+
+template <typename R, int RB>
+__device__ __forceinline__ void op_dense1(cplx<R> (&v)[1 << RB], const OpDesc &o, const cplx<R> *G,
+                                          uint32_t xl, uint32_t zl, uint32_t L, uint32_t base) {
+    const uint32_t tq = o.nq == 2 ? o.tq : 0u, cq = 1u - tq;
+    const uint32_t k = 1u << o.nq;
+    cplx<R> B[2][4];
+#pragma unroll
+    for (uint32_t cb = 0; cb < 2; cb++)
+#pragma unroll
+        for (uint32_t rr = 0; rr < 2; rr++)
+#pragma unroll
+            for (uint32_t cc = 0; cc < 2; cc++) {
+                uint32_t r = rr << tq, c = cc << tq;
+                if (o.nq == 2) {
+                    r |= cb << cq;
+                    c |= cb << cq;
+                }
+                B[cb][rr * 2 + cc] = conj_entry(G, k, r, c, xl, zl);
+            }
+    // control role: none (one-qubit gate: both blocks are the gate), a
+    // register, lane or tile-fixed qubit
+    const uint32_t crole = o.nq == 2 ? (cq ? o.role[1] : o.role[0]) : 0xFFu;
+    const uint32_t cpos = cq ? o.pos[1] : o.pos[0];
+    const uint32_t trole = tq ? o.role[1] : o.role[0];
+    const uint32_t tpos = tq ? o.pos[1] : o.pos[0];
+    if (o.real) dense1_apply<R, RB, true>(v, B, crole, cpos, base, trole, tpos, L);
+    else dense1_apply<R, RB, false>(v, B, crole, cpos, base, trole, tpos, L);
+}
+
+// ---------------------------------------------------------------- DENSE2 --
+// 4x4 on register bits A < B (normalised qubit order).
+template <typename R, int RB, int A, int Bb>
+__device__ __forceinline__ void dense2_rr(cplx<R> (&v)[1 << RB], const cplx<R> (&M)[16]) {
+    sfor<(1 << RB)>([&](auto Jc) __attribute__((always_inline)) {
+        constexpr int j = decltype(Jc)::value;
+        if constexpr (!(j & ((1 << A) | (1 << Bb)))) {
+            constexpr int i0 = j, i1 = j | (1 << A), i2 = j | (1 << Bb);
+            constexpr int i3 = j | (1 << A) | (1 << Bb);
+            const cplx<R> x0 = v[i0], x1 = v[i1], x2 = v[i2], x3 = v[i3];
+            v[i0] = cmac(cmac(cmac(cmul(M[0], x0), M[1], x1), M[2], x2), M[3], x3);
+            v[i1] = cmac(cmac(cmac(cmul(M[4], x0), M[5], x1), M[6], x2), M[7], x3);
+            v[i2] = cmac(cmac(cmac(cmul(M[8], x0), M[9], x1), M[10], x2), M[11], x3);
+            v[i3] = cmac(cmac(cmac(cmul(M[12], x0), M[13], x1), M[14], x2), M[15], x3);
+        }
+    });
+}
+
+template <typename R, int RB, int A>
+__device__ __forceinline__ void dense2_rr_b(cplx<R> (&v)[1 << RB], const cplx<R> (&M)[16], uint32_t b) {
+    switch (b) {
+        case 1: if constexpr (RB > 1 && A < 1) dense2_rr<R, RB, A, 1>(v, M); break;
+        case 2: if constexpr (RB > 2 && A < 2) dense2_rr<R, RB, A, 2>(v, M); break;
+        case 3: if constexpr (RB > 3 && A < 3) dense2_rr<R, RB, A, 3>(v, M); break;
+        case 4: if constexpr (RB > 4 && A < 4) dense2_rr<R, RB, A, 4>(v, M); break;
+        case 5: if constexpr (RB > 5 && A < 5) dense2_rr<R, RB, A, 5>(v, M); break;
+        default: break;
+    }
+}
+
+template <typename R, int RB>
+__device__ __forceinline__ void dense2_rr_dispatch(cplx<R> (&v)[1 << RB], const cplx<R> (&M)[16],
+                                                   uint32_t a, uint32_t b) {
+    switch (a) {
+        case 0: dense2_rr_b<R, RB, 0>(v, M, b); break;
+        case 1: dense2_rr_b<R, RB, 1>(v, M, b); break;
+        case 2: dense2_rr_b<R, RB, 2>(v, M, b); break;
+        case 3: dense2_rr_b<R, RB, 3>(v, M, b); break;
+        case 4: dense2_rr_b<R, RB, 4>(v, M, b); break;
+        default: break;
+    }
+}
+
+template <typename R, int RB>
+__device__ __forceinline__ void op_dense2(cplx<R> (&v)[1 << RB], const OpDesc &o, const cplx<R> *G,
+                                          uint32_t xl, uint32_t zl, uint32_t L) {
+    constexpr int NJ = 1 << RB;
+    // M[r][c] in the gate's qubit order, frame-conjugated
+    const bool r0 = o.role[0] == ROLE_REG, r1 = o.role[1] == ROLE_REG;
+    // normalised order: first qubit = the register one (or lower register bit)
+    bool swapq = false;
+    if (r0 && r1) swapq = o.pos[0] > o.pos[1];
+    else if (!r0 && r1) swapq = true;
+    cplx<R> M[16];
+#pragma unroll
+    for (uint32_t r = 0; r < 4; r++)
+#pragma unroll
+        for (uint32_t c = 0; c < 4; c++) {
+            const uint32_t rs = swapq ? ((r >> 1) | ((r & 1u) << 1)) : r;
+            const uint32_t cs = swapq ? ((c >> 1) | ((c & 1u) << 1)) : c;
+            M[r * 4 + c] = conj_entry(G, 4, rs, cs, xl, zl);
+        }
+    const uint32_t p0 = swapq ? o.pos[1] : o.pos[0];
+    const uint32_t p1 = swapq ? o.pos[0] : o.pos[1];
+    if (r0 && r1) {
+        dense2_rr_dispatch<R, RB>(v, M, p0, p1);
+    } else if (r0 || r1) {
+        // qubit 0 (normalised) in register bit p0, qubit 1 on lane bit p1:
+        // own rows 2b, 2b+1; columns own (2b, 2b+1), partner (2-2b, 3-2b)
+        const uint32_t b = (L >> p1) & 1u, mask = 1u << p1;
+        cplx<R> k0[4], k1[4];
+#pragma unroll
+        for (uint32_t cc = 0; cc < 4; cc++) {
+            const cplx<R> e0_b0 = M[0 * 4 + (cc == 0 ? 0 : cc == 1 ? 1 : cc == 2 ? 2 : 3)];
+            const cplx<R> e0_b1 = M[2 * 4 + (cc == 0 ? 2 : cc == 1 ? 3 : cc == 2 ? 0 : 1)];
+            const cplx<R> e1_b0 = M[1 * 4 + (cc == 0 ? 0 : cc == 1 ? 1 : cc == 2 ? 2 : 3)];
+            const cplx<R> e1_b1 = M[3 * 4 + (cc == 0 ? 2 : cc == 1 ? 3 : cc == 2 ? 0 : 1)];
+            k0[cc] = csel(b != 0, e0_b1, e0_b0);
+            k1[cc] = csel(b != 0, e1_b1, e1_b0);
+        }
+        with_reg<RB>(p0, [&](auto Ia) __attribute__((always_inline)) {
+            constexpr int A = decltype(Ia)::value;
+            sfor<NJ>([&](auto Jc) __attribute__((always_inline)) {
+                constexpr int j = decltype(Jc)::value;
+                if constexpr (j & (1 << A)) return;
+                const cplx<R> a0 = v[j], a1 = v[j | (1 << A)];
+                const cplx<R> q0 = shfl_xor_c(a0, mask), q1 = shfl_xor_c(a1, mask);
+                cplx<R> n0, n1;
+                if (o.real) {
+                    n0 = rmac(rmac(rmac(rmul(k0[0], a0), k0[1], a1), k0[2], q0), k0[3], q1);
+                    n1 = rmac(rmac(rmac(rmul(k1[0], a0), k1[1], a1), k1[2], q0), k1[3], q1);
+                } else {
+                    n0 = cmac(cmac(cmac(cmul(k0[0], a0), k0[1], a1), k0[2], q0), k0[3], q1);
+                    n1 = cmac(cmac(cmac(cmul(k1[0], a0), k1[1], a1), k1[2], q0), k1[3], q1);
+                }
+                v[j] = n0;
+                v[j | (1 << A)] = n1;
+                shuffle_fence<j>();
+            });
+        });
+    } else {
+        // both on lanes: own index r = b0 + 2 b1, partners r^1, r^2, r^3
+        const uint32_t b0 = (L >> p0) & 1u, b1 = (L >> p1) & 1u;
+        const uint32_t m0 = 1u << p0, m1 = 1u << p1;
+        const uint32_t r = b0 | (b1 << 1);
+        cplx<R> k[4];
+#pragma unroll
+        for (uint32_t d = 0; d < 4; d++) {
+            const cplx<R> e0 = M[0 * 4 + (0 ^ d)], e1 = M[1 * 4 + (1 ^ d)];
+            const cplx<R> e2 = M[2 * 4 + (2 ^ d)], e3 = M[3 * 4 + (3 ^ d)];
+            k[d] = csel(r == 3, e3, csel(r == 2, e2, csel(r == 1, e1, e0)));
+        }
+        sfor<NJ>([&](auto Jc) __attribute__((always_inline)) {
+            constexpr int j = decltype(Jc)::value;
+            const cplx<R> q1 = shfl_xor_c(v[j], m0);
+            const cplx<R> q2 = shfl_xor_c(v[j], m1);
+            const cplx<R> q3 = shfl_xor_c(v[j], m0 | m1);
+            v[j] = cmac(cmac(cmac(cmul(k[0], v[j]), k[1], q1), k[2], q2), k[3], q3);
+            shuffle_fence<j>();
+        });
+    }
+}
+
+// ------------------------------------------------------------ DIAG gates --
+// One diagonal gate, gate-by-gate path: d'(r) = d(r ^ x).
+template <typename R, int RB>
+__device__ __forceinline__ void op_diag_one(cplx<R> (&v)[1 << RB], const DiagGate &dg, const cplx<R> *D,
+                                            uint32_t fx, uint32_t L, uint32_t base) {
+    constexpr int NJ = 1 << RB;
+    uint32_t xl = (fx >> dg.phys[0]) & 1u;
+    if (dg.nq == 2) xl |= ((fx >> dg.phys[1]) & 1u) << 1;
+    const uint32_t nd = 1u << dg.nq;
+    cplx<R> d[4];
+#pragma unroll
+    for (uint32_t r = 0; r < 4; r++) d[r] = D[(r & (nd - 1u)) ^ xl];
+    uint32_t rb = 0;  // bits that do not depend on j
+    uint32_t regpos[2] = {0, 0};
+    bool isreg[2] = {false, false};
+#pragma unroll
+    for (uint32_t q = 0; q < 2; q++) {
+        if (q >= dg.nq) break;
+        const uint32_t role = q ? dg.role[1] : dg.role[0];
+        const uint32_t pos = q ? dg.pos[1] : dg.pos[0];
+        if (role == ROLE_LANE) rb |= ((L >> pos) & 1u) << q;
+        else if (role == ROLE_FIXED) rb |= ((base >> pos) & 1u) << q;
+        else {
+            isreg[q] = true;
+            regpos[q] = pos;
+        }
+    }
+    sfor<NJ>([&](auto Jc) __attribute__((always_inline)) {
+        constexpr int j = decltype(Jc)::value;
+        uint32_t r = rb;
+        if (isreg[0]) r |= ((uint32_t)j >> regpos[0]) & 1u;
+        if (isreg[1]) r |= (((uint32_t)j >> regpos[1]) & 1u) << 1;
+        const cplx<R> lo = csel((r & 1u) != 0, d[1], d[0]);
+        const cplx<R> hi = csel((r & 1u) != 0, d[3], d[2]);
+        v[j] = cmul(csel((r & 2u) != 0, hi, lo), v[j]);
+    });
+}
+
+// A run of diagonal gates as one phase polynomial (all its gates commute).
+// With y = index ^ frame-x, the run's phase (in turns) is
+//   C(lane, fixed bits) + sum_i lam_i(lane, fixed bits) y_reg_i + P(y_reg).
+// Gates on register qubits only form the table T = e^{2 pi i P} (host side);
+// the other terms arrive grouped: fixed-only and fixed+register terms give
+// wave-uniform contributions, lane and lane+register terms per-lane ones.
+template <typename R, int RB>
+__device__ __forceinline__ void op_diag_run(cplx<R> (&v)[1 << RB], const OpDesc &o, const cplx<R> *T,
+                                            const DiagTerm *tm, const cplx<R> *expt, uint32_t fx,
+                                            uint32_t L, uint32_t base, const PassDesc *pd) {
+    using A = typename Turns<R>::T;
+    constexpr int NJ = 1 << RB;
+    constexpr int LO = RB < 3 ? RB : 3;
+    constexpr int HI = RB - LO;
+    const uint32_t yfix = base ^ fx;  // frame-adjusted fixed bits (uniform)
+    const uint32_t ylane = L ^ fx;    // frame-adjusted lane bits (lane qubits are physical 0..5)
+    // wave-uniform part
+    A Cu = 0;
+    A lamu[RB];
+#pragma unroll
+    for (int i = 0; i < RB; i++) lamu[i] = 0;
+    const DiagTerm *p = tm;
+    for (uint32_t k = 0; k < o.n_fix; k++) {
+        const DiagTerm &t = p[k];
+        const uint32_t y0 = (yfix >> t.phys[0]) & 1u;
+        const uint32_t y1 = t.nq == 2 ? (yfix >> t.phys[1]) & 1u : 0u;
+        const A t0 = (A)t.th[0], t1 = (A)t.th[1], t2 = (A)t.th[2], t3 = (A)t.th[3];
+        const A lo = y0 ? t1 : t0, hi = y0 ? t3 : t2;
+        Cu += y1 ? hi : lo;
+    }
+    p += o.n_fix;
+    sfor<RB>([&](auto Ic) __attribute__((always_inline)) {
+        constexpr int i = decltype(Ic)::value;
+        const uint32_t cnt = o.n_fixreg[i];
+        A cs = 0, ls = 0;
+        for (uint32_t k = 0; k < cnt; k++) {
+            const DiagTerm &t = p[k];
+            const uint32_t y = (yfix >> t.phys[0]) & 1u;
+            const A t0 = (A)t.th[0], t1 = (A)t.th[1], t2 = (A)t.th[2], t3 = (A)t.th[3];
+            const A a0 = y ? t1 : t0, a1 = y ? t3 : t2;
+            cs += a0;
+            ls += a1 - a0;
+        }
+        Cu += cs;
+        lamu[i] += ls;
+        p += cnt;
+    });
+    // per-lane part
+    A C = Cu;
+    A lam[RB];
+#pragma unroll
+    for (int i = 0; i < RB; i++) lam[i] = lamu[i];
+#pragma unroll 2
+    for (uint32_t k = 0; k < o.n_lane; k++) {
+        const DiagTerm &t = p[k];
+        const uint32_t y0 = (ylane >> t.phys[0]) & 1u;
+        const A t0 = (A)t.th[0], t1 = (A)t.th[1], t2 = (A)t.th[2], t3 = (A)t.th[3];
+        if (t.nq == 1) {
+            C += y0 ? t1 : t0;
+        } else {
+            const uint32_t y1 = t.role[1] == ROLE_LANE ? (ylane >> t.phys[1]) & 1u : (yfix >> t.phys[1]) & 1u;
+            const A lo = y0 ? t1 : t0, hi = y0 ? t3 : t2;
+            C += y1 ? hi : lo;
+        }
+    }
+    p += o.n_lane;
+    sfor<RB>([&](auto Ic) __attribute__((always_inline)) {
+        constexpr int i = decltype(Ic)::value;
+        const uint32_t cnt = o.n_lanereg[i];
+#pragma unroll 2
+        for (uint32_t k = 0; k < cnt; k++) {
+            const DiagTerm &t = p[k];
+            const uint32_t y = (ylane >> t.phys[0]) & 1u;
+            const A a0 = y ? (A)t.th[1] : (A)t.th[0];
+            const A a1 = y ? (A)t.th[3] : (A)t.th[2];
+            C += a0;
+            lam[i] += a1 - a0;
+        }
+        p += cnt;
+    });
+    // register bits: y_i = x_i ^ f_i, so lam_i y_i = f_i lam_i + (-1)^{f_i} lam_i x_i
+    uint32_t fr = 0;
+    sfor<RB>([&](auto Ic) __attribute__((always_inline)) {
+        constexpr int i = decltype(Ic)::value;
+        if ((uint32_t)i < pd->nr) {
+            const uint32_t f = (fx >> pd->rq[i]) & 1u;
+            fr |= f << i;
+            if (f) {
+                C += lam[i];
+                lam[i] = (A)0 - lam[i];
+            }
+        }
+    });
+    // subset products over the low and high register bits
+    cplx<R> wlo[1 << LO], whi[1 << HI];
+    wlo[0] = expi_turns(C, expt);
+    sfor<LO>([&](auto Ic) __attribute__((always_inline)) {
+        constexpr int i = decltype(Ic)::value;
+        const cplx<R> e = expi_turns(lam[i], expt);
+        sfor<(1 << i)>([&](auto Sc) __attribute__((always_inline)) {
+            constexpr int s = decltype(Sc)::value;
+            wlo[s | (1 << i)] = cmul(wlo[s], e);
+        });
+    });
+    whi[0] = cplx<R>{R(1), R(0)};
+    sfor<HI>([&](auto Ic) __attribute__((always_inline)) {
+        constexpr int i = decltype(Ic)::value;
+        const cplx<R> e = expi_turns(lam[LO + i], expt);
+        sfor<(1 << i)>([&](auto Sc) __attribute__((always_inline)) {
+            constexpr int s = decltype(Sc)::value;
+            whi[s | (1 << i)] = cmul(whi[s], e);
+        });
+    });
+    if (o.has_t) {
+        // lane l holds table entry l ^ f_reg; register index j reads it from lane j
+        const uint32_t tl = L & (NJ - 1);
+        const cplx<R> tv = T[(tl ^ fr) & ((1u << pd->nr) - 1u)];
+        sfor<NJ>([&](auto Jc) __attribute__((always_inline)) {
+            constexpr int j = decltype(Jc)::value;
+            const cplx<R> t = {bcast_lane(tv.re, j), bcast_lane(tv.im, j)};
+            const cplx<R> w = cmul(cmul(wlo[j & ((1 << LO) - 1)], whi[j >> LO]), t);
+            v[j] = cmul(w, v[j]);
+        });
+    } else {
+        sfor<NJ>([&](auto Jc) __attribute__((always_inline)) {
+            constexpr int j = decltype(Jc)::value;
+            const cplx<R> w = HI ? cmul(wlo[j & ((1 << LO) - 1)], whi[j >> LO]) : wlo[j & ((1 << LO) - 1)];
+            v[j] = cmul(w, v[j]);
+        });
+    }
+}
+
+// ------------------------------------------------------------------ kernel --
+// D2: the pass contains 4x4 ops (a separate instantiation keeps the
+// register budget of the common passes small).
+template <typename R, int RB, bool D2>
+__global__ __launch_bounds__(64) void pass_kernel(PassArgs<R> a) {
+    constexpr int NJ = 1 << RB;
+    const uint32_t nwg = gridDim.x, bid = blockIdx.x;
+    const uint32_t w = (bid & 7u) * (nwg >> 3) + (bid >> 3);
+    if (w >= a.work) return;
+    const uint32_t traj = w % a.count, tile = w / a.count;
+    const uint32_t L = threadIdx.x;
+    const PassDesc *pd = a.pass;
+    const uint32_t nl = pd->nl, nr = pd->nr, nfree = pd->nfree;
+
+    // tile loads go out first; the noise metadata is fetched behind them
+    const uint32_t src_s = a.src_slot[traj];
+    const uint32_t dst_s = a.dst_slot[traj];
+    uint32_t base = 0;
+    for (uint32_t i = 0; i < nfree; i++) base |= ((tile >> i) & 1u) << pd->fbits[i];
+    uint32_t rq[RB];
+#pragma unroll
+    for (int i = 0; i < RB; i++) rq[i] = (uint32_t)i < nr ? pd->rq[i] : 0u;
+    const bool lane_ok = L < (1u << nl);
+    const uint32_t jmax = 1u << nr;
+    const bool init = src_s == kInit;
+    const cplx<R> *src = a.states + (uint64_t)(init ? 0u : src_s) * a.slot_amps + base;
+
+    // a full tile (64 lanes, RB register qubits) loads without predication:
+    // scalar base of each register index plus the lane offset
+    const bool full = nl == kLaneBits && nr == (uint32_t)RB;
+    // (branches sit outside the unrolled loops so all loads issue back to back)
+    auto reg_off = [&](auto Jc) __attribute__((always_inline)) {
+        constexpr int j = decltype(Jc)::value;
+        uint32_t off = 0;
+        sfor<RB>([&](auto Ic) __attribute__((always_inline)) {
+            constexpr int i = decltype(Ic)::value;
+            if constexpr ((j >> i) & 1) off |= 1u << rq[i];
+        });
+        return off;
+    };
+    cplx<R> v[NJ];
+    if (init) {
+        sfor<NJ>([&](auto Jc) __attribute__((always_inline)) {
+            constexpr int j = decltype(Jc)::value;
+            const uint32_t off = reg_off(Jc);
+            v[j] = cplx<R>{(uint32_t)j < jmax && (base + off + L) == 0 ? R(1) : R(0), R(0)};
+        });
+    } else if (full) {
+        sfor<NJ>([&](auto Jc) __attribute__((always_inline)) {
+            constexpr int j = decltype(Jc)::value;
+            v[j] = (src + reg_off(Jc))[L];
+        });
+    } else {
+        sfor<NJ>([&](auto Jc) __attribute__((always_inline)) {
+            constexpr int j = decltype(Jc)::value;
+            v[j] = cplx<R>{R(0), R(0)};
+            if ((uint32_t)j < jmax && lane_ok) v[j] = (src + reg_off(Jc))[L];
+        });
+    }
+
+    // frame at the start of this pass
+    const uint32_t node = a.node_ids[traj];
+    uint32_t fx = a.meta.frame0[2 * node], fz = a.meta.frame0[2 * node + 1];
+    uint32_t e = a.meta.ev_off[node];
+    const uint32_t e1 = a.meta.ev_off[node + 1];
+    while (e < e1 && a.meta.ev_pos[e] < a.pass_key) {
+        fx ^= a.meta.ev_dx[e];
+        fz ^= a.meta.ev_dz[e];
+        e++;
+    }
+
+    for (uint32_t oi = 0; oi < pd->op_count; oi++) {
+        const OpDesc &o = a.ops[pd->op_begin + oi];
+        while (e < e1 && a.meta.ev_pos[e] <= (a.pass_key | o.slot0)) {
+            fx ^= a.meta.ev_dx[e];
+            fz ^= a.meta.ev_dz[e];
+            e++;
+        }
+        if (o.kind == OP_DIAGRUN) {
+            const bool inside = e < e1 && a.meta.ev_pos[e] < (a.pass_key | o.slot1);
+            if (!inside) {
+                op_diag_run<R, RB>(v, o, a.mats + o.mat, a.terms + o.terms, a.expt, fx, L, base, pd);
+            } else {
+                // an event inside the run: gate by gate with frame updates
+                for (uint32_t k = 0; k < o.ngates; k++) {
+                    while (e < e1 && a.meta.ev_pos[e] <= (a.pass_key | (o.slot0 + k))) {
+                        fx ^= a.meta.ev_dx[e];
+                        fz ^= a.meta.ev_dz[e];
+                        e++;
+                    }
+                    const DiagGate &dg = a.dgates[o.gates + k];
+                    op_diag_one<R, RB>(v, dg, a.mats + dg.d, fx, L, base);
+                }
+            }
+            continue;
+        }
+        uint32_t xl = (fx >> o.phys[0]) & 1u, zl = (fz >> o.phys[0]) & 1u;
+        if (o.nq == 2) {
+            xl |= ((fx >> o.phys[1]) & 1u) << 1;
+            zl |= ((fz >> o.phys[1]) & 1u) << 1;
+        }
+        const cplx<R> *G = a.mats + o.mat;
+        if constexpr (D2) {
+            if (o.kind == OP_DENSE2) {
+                op_dense2<R, RB>(v, o, G, xl, zl, L);
+                continue;
+            }
+        }
+        op_dense1<R, RB>(v, o, G, xl, zl, L, base);
+    }
+
+    cplx<R> *dst = a.states + (uint64_t)dst_s * a.slot_amps + base;
+    if (full) {
+        sfor<NJ>([&](auto Jc) __attribute__((always_inline)) {
+            constexpr int j = decltype(Jc)::value;
+            (dst + reg_off(Jc))[L] = v[j];
+        });
+    } else {
+        sfor<NJ>([&](auto Jc) __attribute__((always_inline)) {
+            constexpr int j = decltype(Jc)::value;
+            if ((uint32_t)j < jmax && lane_ok) (dst + reg_off(Jc))[L] = v[j];
+        });
+    }
+}
+
+}  // namespace tqs

@@ -1,0 +1,417 @@
+// Pass planner: groups each subcircuit's gates into HBM passes over
+// one-wave register tiles and prepares the per-op data the kernels read.
+//
+// A tile holds 2^(nl + nr) amplitudes of one trajectory: lane L of the wave
+// owns the amplitudes whose physical qubits 0..nl-1 spell L (so every load
+// and store of the wave is one contiguous run), and its register index j
+// spells the nr register qubits.  A gate can run inside a pass when every
+// qubit it changes is a lane or register qubit; a diagonal gate changes no
+// qubit and runs anywhere.  Consecutive diagonal gates become one phase run:
+// the product of diagonal unitaries is a phase polynomial of degree two in
+// the index bits, evaluated per lane in fixed-point turns.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "tqs_internal.h"
+
+namespace tqs {
+
+static bool is_zero(const cd &v) { return v.real() == 0.0 && v.imag() == 0.0; }
+
+enum GateClass { GC_DIAG, GC_DENSE1, GC_CTRL, GC_DENSE2 };
+
+// Diagonal, block-diagonal in one qubit (a control: its value never changes),
+// or dense.
+static GateClass classify(const Gate &g, uint32_t *ctrl) {
+    const int k = 1 << g.a;
+    bool diag = true;
+    for (int r = 0; r < k; r++)
+        for (int c = 0; c < k; c++)
+            if (r != c && !is_zero(g.m[r * k + c])) diag = false;
+    if (diag) return GC_DIAG;
+    if (g.a == 1) return GC_DENSE1;
+    for (int j = 0; j < 2; j++) {
+        bool blk = true;
+        for (int r = 0; r < 4; r++)
+            for (int c = 0; c < 4; c++)
+                if (((r >> j) & 1) != ((c >> j) & 1) && !is_zero(g.m[r * 4 + c])) blk = false;
+        if (blk) {
+            *ctrl = (uint32_t)j;
+            return GC_CTRL;
+        }
+    }
+    return GC_DENSE2;
+}
+
+// Qubits a gate changes (must be lane or register qubits of its pass).
+static uint32_t changed_mask(const Gate &g, GateClass gc, uint32_t ctrl) {
+    switch (gc) {
+        case GC_DIAG: return 0;
+        case GC_DENSE1: return 1u << g.q[0];
+        case GC_CTRL: return 1u << g.q[1 - ctrl];
+        case GC_DENSE2: return (1u << g.q[0]) | (1u << g.q[1]);
+    }
+    return 0;
+}
+
+// Phase of a unit complex number as 64-bit fixed-point turns.
+static uint64_t turns_fixed(const cd &z) {
+    long double t = std::atan2((long double)z.imag(), (long double)z.real()) /
+                    (2.0L * 3.141592653589793238462643383279502884L);  // (-1/2, 1/2]
+    if (t < 0) t += 1.0L;                                             // [0, 1)
+    long double s = std::ldexp(t, 62);
+    uint64_t v = (uint64_t)llroundl(s);
+    return v << 2;  // wraps modulo one turn
+}
+
+struct PendingGate {
+    uint32_t g;
+    GateClass gc;
+    uint32_t ctrl;
+};
+
+// Estimated lane instructions per amplitude of each op (used to bound the
+// work of one pass to about what its HBM traffic takes).
+static double op_cost(GateClass gc, bool lane_target, bool lane_other) {
+    switch (gc) {
+        case GC_DENSE1: return lane_target ? 10 : 5;
+        case GC_CTRL: return lane_target ? 11 : 7;
+        case GC_DENSE2: return lane_target && lane_other ? 26 : (lane_target || lane_other ? 20 : 17);
+        case GC_DIAG: return 0;
+    }
+    return 0;
+}
+
+}  // namespace tqs
+
+using namespace tqs;
+
+#define TQS_GUARD_BEGIN try {
+#define TQS_GUARD_END                                         \
+    }                                                         \
+    catch (const std::bad_alloc &) {                          \
+        return fail(TQS_E_OOM, "host allocation failed");     \
+    }                                                         \
+    catch (...) {                                             \
+        return fail(TQS_E_ARG, "unexpected exception");       \
+    }
+
+extern "C" tqs_status tqs_plan_create(const tqs_circuit *c, const tqs_tree *tree, tqs_precision prec,
+                                      const tqs_tuning *tuning, tqs_plan **out) {
+    TQS_GUARD_BEGIN
+    if (!c || !out) return fail(TQS_E_ARG, "circuit or out is NULL");
+    *out = nullptr;
+    if (prec != TQS_C64 && prec != TQS_C128) return fail(TQS_E_ARG, "unknown precision %d", (int)prec);
+    std::vector<uint64_t> A;
+    std::vector<uint32_t> cut;
+    tqs_status st = validate_tree(tree, (uint32_t)c->gates.size(), &A, &cut);
+    if (st) return st;
+    tqs_tuning tu{};
+    if (tuning) tu = *tuning;
+    if (!tu.tile_qubits) tu.tile_qubits = prec == TQS_C64 ? 12 : 11;
+    if (!tu.max_ops_per_pass) tu.max_ops_per_pass = 1024;
+    if (!tu.chunk_states) tu.chunk_states = 256;
+    if (!tu.sample_block_log) tu.sample_block_log = 12;
+    if (!tu.pass_cost) tu.pass_cost = 80;
+    const uint32_t tmax = prec == TQS_C64 ? 12 : 11;
+    if (tu.tile_qubits < 10 || tu.tile_qubits > tmax)
+        return fail(TQS_E_ARG, "tile_qubits must be in 10..%u at this precision", tmax);
+    if (tu.sample_block_log < 8 || tu.sample_block_log > 16)
+        return fail(TQS_E_ARG, "sample_block_log must be in 8..16");
+    if (tu.max_ops_per_pass > 60000) return fail(TQS_E_ARG, "max_ops_per_pass must be <= 60000");
+
+    tqs_plan *p = new tqs_plan;
+    p->n = c->n;
+    p->prec = prec;
+    p->tune = tu;
+    p->arity = A;
+    p->cut = cut;
+    p->n_gates = (uint32_t)c->gates.size();
+    p->reg_bits = tu.tile_qubits - kLaneBits;
+    const uint32_t L = (uint32_t)A.size();
+    uint64_t off = 0;
+    for (uint32_t l = 0; l < L; l++) {
+        p->level_offset.push_back(off);
+        p->level_nodes.push_back(level_nodes(A, l));
+        off += p->level_nodes.back();
+    }
+    p->n_nodes = off;
+    p->n_leaves = p->level_nodes.back();
+    p->sample_b = std::min(c->n, tu.sample_block_log);
+    p->gate_pass.assign(p->n_gates, 0);
+    p->gate_pos.assign(p->n_gates, 0);
+    p->gate_q0.assign(p->n_gates, 0);
+    p->gate_q1.assign(p->n_gates, 0);
+    p->gate_a.assign(p->n_gates, 0);
+
+    const uint32_t n = c->n;
+    const uint32_t nl = std::min(n, kLaneBits);
+    const uint32_t nr_max = std::min(n - nl, p->reg_bits);
+    const uint32_t lane_mask = (1u << nl) - 1u;
+
+    std::vector<PendingGate> pend;
+    uint32_t pend_changed = 0;  // changed qubits >= nl (need register slots)
+    double pend_cost = 4.0;     // load + store
+    uint32_t pend_lds = 0;      // bytes of the pass's staged op data
+    const uint32_t amp_bytes = prec == TQS_C64 ? 8 : 16;
+
+    auto emit = [&]() {
+        PassDesc d;
+        std::memset(&d, 0, sizeof d);
+        d.nl = (uint8_t)nl;
+        // register qubits: the changed high qubits, then the lowest others
+        uint32_t regs = pend_changed;
+        for (uint32_t b = nl; b < n && (uint32_t)__builtin_popcount(regs) < nr_max; b++) regs |= 1u << b;
+        uint8_t role[32], pos[32];
+        for (uint32_t b = 0; b < n; b++) {
+            role[b] = ROLE_FIXED;
+            pos[b] = (uint8_t)b;
+        }
+        for (uint32_t b = 0; b < nl; b++) {
+            role[b] = ROLE_LANE;
+            pos[b] = (uint8_t)b;
+        }
+        d.nr = 0;
+        for (uint32_t b = nl; b < n; b++)
+            if ((regs >> b) & 1) {
+                role[b] = ROLE_REG;
+                pos[b] = d.nr;
+                d.rq[d.nr++] = (uint8_t)b;
+            }
+        d.nfree = 0;
+        for (uint32_t b = 0; b < n; b++)
+            if (role[b] == ROLE_FIXED) d.fbits[d.nfree++] = (uint8_t)b;
+        d.op_begin = (uint32_t)p->ops.size();
+        d.mat_begin = (uint32_t)p->mats.size();
+        d.term_begin = (uint32_t)p->terms.size();
+        const uint32_t pass_idx = (uint32_t)p->passes.size();
+
+        size_t i = 0;
+        while (i < pend.size()) {
+            const Gate &g0 = c->gates[pend[i].g];
+            OpDesc o;
+            std::memset(&o, 0, sizeof o);
+            o.slot0 = (uint16_t)i;
+            if (pend[i].gc == GC_DIAG) {
+                // maximal run of consecutive diagonal gates
+                size_t j = i;
+                while (j < pend.size() && pend[j].gc == GC_DIAG) j++;
+                o.kind = OP_DIAGRUN;
+                o.slot1 = (uint16_t)j;
+                o.mat = (uint32_t)p->mats.size();
+                o.terms = (uint32_t)p->terms.size();
+                o.gates = (uint32_t)p->dgates.size();
+                // register-only gates fold into a table over the register
+                // index; the others become phase terms, normalised so that
+                // qubit 0 is the fixed or lane one and, for a term with a
+                // register qubit, r = y0 + 2 x_reg, then grouped by role
+                const uint32_t nt = 1u << d.nr;
+                std::vector<cd> tab(nt, cd(1.0, 0.0));
+                bool has_t = false;
+                std::vector<DiagTerm> g_fix, g_lane, g_fixreg[kMaxRegBits], g_lanereg[kMaxRegBits];
+                auto phase_fixed = [&](const cd &z) {
+                    const uint64_t t64 = turns_fixed(z);
+                    // complex64 runs keep 32-bit turns (rounded), complex128 runs 64-bit
+                    return prec == TQS_C64 ? (uint64_t)(uint32_t)((t64 + 0x80000000ull) >> 32) : t64;
+                };
+                for (size_t k = i; k < j; k++) {
+                    const Gate &g = c->gates[pend[k].g];
+                    const uint32_t nd = 1u << g.a;
+                    DiagGate dg;
+                    std::memset(&dg, 0, sizeof dg);
+                    dg.nq = (uint8_t)g.a;
+                    uint32_t nreg = 0, nlane = 0;
+                    for (uint32_t q = 0; q < g.a; q++) {
+                        dg.role[q] = role[g.q[q]];
+                        dg.pos[q] = pos[g.q[q]];
+                        dg.phys[q] = (uint8_t)g.q[q];
+                        if (role[g.q[q]] == ROLE_REG) nreg++;
+                        if (role[g.q[q]] == ROLE_LANE) nlane++;
+                    }
+                    p->dgates.push_back(dg);
+                    if (nreg == g.a) {
+                        for (uint32_t t = 0; t < nt; t++) {
+                            uint32_t r = 0;
+                            for (uint32_t q = 0; q < g.a; q++) r |= ((t >> pos[g.q[q]]) & 1u) << q;
+                            tab[t] *= g.m[r * nd + r];
+                        }
+                        has_t = true;
+                        continue;
+                    }
+                    DiagTerm tm;
+                    std::memset(&tm, 0, sizeof tm);
+                    tm.nq = (uint8_t)g.a;
+                    // order: qubit 0 = a lane qubit if any, else a fixed one
+                    uint32_t q0 = 0;
+                    if (g.a == 2) {
+                        const uint32_t r0 = role[g.q[0]], r1 = role[g.q[1]];
+                        if (r0 == ROLE_REG || (r0 == ROLE_FIXED && r1 == ROLE_LANE)) q0 = 1;
+                    }
+                    const uint32_t q1 = 1 - q0;
+                    tm.role[0] = role[g.q[q0]];
+                    tm.pos[0] = pos[g.q[q0]];
+                    tm.phys[0] = (uint8_t)g.q[q0];
+                    if (g.a == 2) {
+                        tm.role[1] = role[g.q[q1]];
+                        tm.pos[1] = pos[g.q[q1]];
+                        tm.phys[1] = (uint8_t)g.q[q1];
+                    }
+                    for (uint32_t r = 0; r < nd; r++) {
+                        // r in the normalised order -> index in the gate's order
+                        uint32_t rg = r;
+                        if (g.a == 2 && q0 == 1) rg = ((r & 1u) << 1) | (r >> 1);
+                        tm.th[r] = phase_fixed(g.m[rg * nd + rg]);
+                    }
+                    const bool reg1 = g.a == 2 && tm.role[1] == ROLE_REG;
+                    if (nlane == 0) {
+                        if (reg1) g_fixreg[tm.pos[1]].push_back(tm);
+                        else g_fix.push_back(tm);
+                    } else {
+                        if (reg1) g_lanereg[tm.pos[1]].push_back(tm);
+                        else g_lane.push_back(tm);
+                    }
+                }
+                o.has_t = has_t ? 1 : 0;
+                o.n_fix = (uint16_t)g_fix.size();
+                o.n_lane = (uint16_t)g_lane.size();
+                for (const DiagTerm &tm : g_fix) p->terms.push_back(tm);
+                for (uint32_t b = 0; b < kMaxRegBits; b++) {
+                    o.n_fixreg[b] = (uint16_t)g_fixreg[b].size();
+                    for (const DiagTerm &tm : g_fixreg[b]) p->terms.push_back(tm);
+                }
+                for (const DiagTerm &tm : g_lane) p->terms.push_back(tm);
+                for (uint32_t b = 0; b < kMaxRegBits; b++) {
+                    o.n_lanereg[b] = (uint16_t)g_lanereg[b].size();
+                    for (const DiagTerm &tm : g_lanereg[b]) p->terms.push_back(tm);
+                }
+                o.nterms = (uint32_t)(p->terms.size() - o.terms);
+                o.ngates = (uint32_t)(j - i);
+                for (uint32_t t = 0; t < nt; t++) p->mats.push_back(tab[t]);
+                // per-gate diagonal entries for the gate-by-gate path
+                for (size_t k = i; k < j; k++) {
+                    const Gate &g = c->gates[pend[k].g];
+                    const uint32_t nd = 1u << g.a;
+                    p->dgates[o.gates + (k - i)].d = (uint32_t)p->mats.size();
+                    for (uint32_t r = 0; r < nd; r++) p->mats.push_back(g.m[r * nd + r]);
+                }
+                i = j;
+            } else {
+                const Gate &g = g0;
+                o.slot1 = (uint16_t)(i + 1);
+                o.nq = (uint8_t)g.a;
+                for (uint32_t q = 0; q < g.a; q++) {
+                    o.role[q] = role[g.q[q]];
+                    o.pos[q] = pos[g.q[q]];
+                    o.phys[q] = (uint8_t)g.q[q];
+                }
+                o.kind = pend[i].gc == GC_DENSE2 ? OP_DENSE2 : OP_DENSE1;
+                o.tq = pend[i].gc == GC_CTRL ? (uint8_t)(1 - pend[i].ctrl) : 0;
+                o.mat = (uint32_t)p->mats.size();
+                const uint32_t nd = 1u << g.a;
+                o.real = 1;
+                for (uint32_t r = 0; r < nd * nd; r++) {
+                    p->mats.push_back(g.m[r]);
+                    if (g.m[r].imag() != 0.0) o.real = 0;
+                }
+                i++;
+            }
+            p->ops.push_back(o);
+        }
+        d.op_count = (uint32_t)p->ops.size() - d.op_begin;
+        d.mat_count = (uint32_t)p->mats.size() - d.mat_begin;
+        d.term_count = (uint32_t)p->terms.size() - d.term_begin;
+        d.has_d2 = 0;
+        for (uint32_t k = d.op_begin; k < (uint32_t)p->ops.size(); k++)
+            if (p->ops[k].kind == OP_DENSE2) d.has_d2 = 1;
+        (void)pass_idx;
+        p->passes.push_back(d);
+        pend.clear();
+        pend_changed = 0;
+        pend_cost = 4.0;
+        pend_lds = 0;
+    };
+
+    for (uint32_t l = 0; l < L; l++) {
+        tqs::Level lv;
+        lv.pass_begin = (uint32_t)p->passes.size();
+        lv.g0 = cut[l];
+        lv.g1 = cut[l + 1];
+        bool in_diag_run = false;
+        uint32_t run_terms = 0;
+        for (uint32_t gi = cut[l]; gi < cut[l + 1]; gi++) {
+            const Gate &g = c->gates[gi];
+            uint32_t ctrl = 0;
+            const GateClass gc = classify(g, &ctrl);
+            const uint32_t ch = changed_mask(g, gc, ctrl) & ~lane_mask;
+            const uint32_t need = (uint32_t)__builtin_popcount(pend_changed | ch);
+            double cost;
+            if (gc == GC_DIAG) {
+                // a new run pays its per-amplitude evaluation; each term adds
+                // per-lane work spread over the lane's amplitudes
+                cost = (in_diag_run ? 0.0 : 14.0 + 0.7 * (nr_max + 1)) + 0.2;
+                run_terms++;
+            } else {
+                const uint32_t tq = gc == GC_CTRL ? 1 - ctrl : 0;
+                const bool lt = g.q[tq] < nl;
+                const bool lo = g.a == 2 && g.q[1 - tq] < nl;
+                cost = op_cost(gc, lt, lo);
+            }
+            // staged bytes: op record, matrix or diagonal, phase term, run table
+            uint32_t lds = 0;
+            if (gc == GC_DIAG)
+                lds = (uint32_t)(sizeof(DiagTerm) + 4 * amp_bytes) +
+                      (in_diag_run ? 0u : (uint32_t)sizeof(OpDesc) + (amp_bytes << nr_max));
+            else
+                lds = (uint32_t)sizeof(OpDesc) + (g.a == 2 ? 16u : 4u) * amp_bytes;
+            if (!pend.empty() && (need > nr_max || pend_cost + cost > tu.pass_cost ||
+                                  pend_lds + lds > kPassLdsBytes ||
+                                  pend.size() >= tu.max_ops_per_pass || pend.size() >= 60000)) {
+                emit();
+                run_terms = 0;
+                if (gc == GC_DIAG && in_diag_run) {
+                    // the run restarts in the new pass: it pays its set-up again
+                    cost = 14.0 + 0.7 * (nr_max + 1) + 0.2;
+                    lds += (uint32_t)sizeof(OpDesc) + (amp_bytes << nr_max);
+                }
+                in_diag_run = false;
+            }
+            in_diag_run = (gc == GC_DIAG);
+            pend_changed |= ch;
+            pend_cost += cost;
+            pend_lds += lds;
+            pend.push_back({gi, gc, ctrl});
+            p->gate_pass[gi] = (uint32_t)p->passes.size();
+            p->gate_pos[gi] = (uint32_t)pend.size();  // slot after this gate
+            p->gate_a[gi] = g.a;
+            p->gate_q0[gi] = g.q[0];
+            p->gate_q1[gi] = g.a == 2 ? g.q[1] : g.q[0];
+        }
+        (void)run_terms;
+        emit();
+        lv.pass_count = (uint32_t)p->passes.size() - lv.pass_begin;
+        p->levels.push_back(lv);
+    }
+    if (p->passes.size() >= (1u << 16)) {
+        delete p;
+        return fail(TQS_E_UNSUPPORTED, "too many passes (%zu)", p->passes.size());
+    }
+    for (uint32_t l = 0; l < L; l++)
+        p->chunk.push_back((uint32_t)std::min<uint64_t>(p->level_nodes[l], tu.chunk_states));
+    *out = p;
+    return TQS_OK;
+    TQS_GUARD_END
+}
+
+extern "C" tqs_status tqs_plan_info(const tqs_plan *p, uint32_t level, uint32_t *passes_level,
+                                    uint32_t *passes_total, uint32_t *chunk_states) {
+    if (!p) return fail(TQS_E_ARG, "plan is NULL");
+    if (level >= p->levels.size()) return fail(TQS_E_ARG, "level %u out of range", level);
+    if (passes_level) *passes_level = p->levels[level].pass_count;
+    if (passes_total) *passes_total = (uint32_t)p->passes.size();
+    if (chunk_states) *chunk_states = p->chunk[level];
+    return TQS_OK;
+}
+
+extern "C" void tqs_plan_destroy(tqs_plan *p) { delete p; }

@@ -230,3 +230,63 @@ def test_tree_histogram_vs_density_matrix(T):
     p_hat = otree.hist_probs(out, n)
     bound = 0.5 * np.sum(np.sqrt(p_dm * (1 - p_dm) / A[0]))
     assert otree.tv_distance(p_hat, p_dm) < 3 * bound
+
+
+@pytest.mark.parametrize("prec,tile", [("c64", 10), ("c64", 11), ("c64", 12), ("c128", 10), ("c128", 11)])
+def test_qft_closed_form_every_tile(T, prec, tile):
+    # noiseless QFT|x> against the DFT closed form, with qubits outside the
+    # tile (fixed per tile) at several widths and pass splits
+    for n in (11, 13, 16, 20):
+        if n < tile:
+            continue
+        x = (0x5A5A5 >> (20 - n)) & ((1 << n) - 1)
+        wc = W.concat(W.basis_prep(n, x), W.qft(n))
+        c = T.Circuit.from_workload(wc)
+        tree = ([1], [0, len(wc)])
+        y = np.arange(1 << n)
+        want = np.exp(2j * np.pi * x * y / (1 << n)) / math.sqrt(1 << n)
+        for cost in (80, 100000):
+            plan = T.Plan(c, tree, prec, {"tile_qubits": tile, "pass_cost": cost})
+            _, amps = T.run_capture(plan, T.Noise.sample(c, tree, 0), [0])
+            assert np.max(np.abs(amps[0] - want)) < TOL[prec], (n, cost)
+
+
+def _diag_case(n, gates, rng):
+    c = W.Circuit(n)
+    for q in range(n):
+        c.add((q,), W.haar_unitary(2, rng))
+    for q, m in gates:
+        c.add(q, m)
+    return c
+
+
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+def test_phase_run_term_groups(T, prec):
+    # n = 12 with 10-qubit tiles: the second pass has register qubits
+    # 6, 7, 10, 11, fixed qubits 8, 9 and lanes 0..5, so these runs exercise
+    # every term group, several terms per register bit included
+    rng = np.random.default_rng(0)
+
+    def rd(k):
+        return np.diag(np.exp(1j * rng.uniform(-np.pi, np.pi, k)))
+
+    def cp(m, j):
+        return ((m, j), W.cphase(np.pi / 2 ** (j - m)))
+
+    cases = [
+        [((9, 11), rd(4)), ((8, 11), rd(4))],                 # two fixed+register, same bit
+        [((11, 9), rd(4)), ((8, 10), rd(4)), ((9, 10), rd(4))],
+        [cp(m, 11) for m in range(10, -1, -1)],                # a whole QFT row
+        [((8, 9), rd(4)), ((9,), rd(2)), ((8, 9), rd(4))],     # fixed only
+        [((2, 9), rd(4)), ((9, 3), rd(4)), ((1, 4), rd(4)), ((5,), rd(2))],   # lane terms
+        [((1, 7), rd(4)), ((2, 7), rd(4)), ((7, 3), rd(4))],   # lane+register, same bit
+        [((6, 7), rd(4)), ((10,), rd(2)), ((11, 6), rd(4))],   # register only (table)
+    ]
+    for k, gates in enumerate(cases):
+        wc = _diag_case(12, gates, rng)
+        c = T.Circuit.from_workload(wc)
+        tree = ([1], [0, len(wc)])
+        plan = T.Plan(c, tree, prec, {"tile_qubits": 10, "pass_cost": 100000})
+        _, amps = T.run_capture(plan, T.Noise.sample(c, tree, 0), [0])
+        _, ref = oracle.run_events(12, wc.gates)
+        assert np.max(np.abs(amps[0] - ref)) < TOL[prec], k

@@ -168,8 +168,9 @@ def test_plan_passes_respect_tile_capacity():
     wc = W.qft(20)
     c = T.Circuit.from_workload(wc)
     tree = ([4], [0, len(wc)])
-    p10 = T.Plan(c, tree, tuning={"tile_qubits": 10, "max_ops_per_pass": 4096}).info(0)
-    p12 = T.Plan(c, tree, tuning={"tile_qubits": 12, "max_ops_per_pass": 4096}).info(0)
+    big = 1 << 30   # no work bound: passes limited by tile capacity only
+    p10 = T.Plan(c, tree, tuning={"tile_qubits": 10, "pass_cost": big}).info(0)
+    p12 = T.Plan(c, tree, tuning={"tile_qubits": 12, "pass_cost": big}).info(0)
     assert p12["passes_level"] <= p10["passes_level"]
     p1 = T.Plan(c, tree, tuning={"max_ops_per_pass": 1}).info(0)
     assert p1["passes_level"] == len(wc)
