@@ -23,6 +23,23 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "pass_kernel_qft20_tree16x32x32_traffic.json")
+
+
+def measured_traffic():
+    """HBM bytes per pass launch from the committed rocprofv3 FETCH/WRITE
+    counts, or None when the kernel or planner sources changed since."""
+    import hashlib
+    try:
+        rec = json.load(open(TRAFFIC_JSON))
+        h = hashlib.sha256()
+        for s in rec["sources"]:
+            h.update(open(os.path.join(ROOT, s), "rb").read())
+        if h.hexdigest() != rec["sources_sha256"]:
+            return None
+        return rec["hbm_read_bytes_per_launch"] + rec["hbm_write_bytes_per_launch"]
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def equal_cuts(G, levels):
@@ -52,6 +69,7 @@ def time_form(T, torch, circuit, tree, seed, steps, warmup, tuning=None):
         agg["bytes_sample"] += st["bytes_sample"]
         agg["ms_device"] += st["ms_device"]
         agg["launches"] += st["launches"]
+        agg["pass_launches"] += st["pass_launches"]
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     passes_total = sum(plan.info(l)["passes_level"] * int(__import__("numpy").prod(tree[0][:l + 1]))
@@ -135,7 +153,10 @@ def main():
                          "ms_passes": agg["ms_passes"] / args.steps,
                          "ms_sample": agg["ms_sample"] / args.steps,
                          "launches": agg["launches"] // args.steps,
-                         "pass_launches_per_step": agg["pass_launches_per_step"]}
+                         "pass_launches_per_step": agg["pass_launches_per_step"],
+                         "pass_launches": agg["pass_launches"],
+                         "bytes_per_launch": agg["bytes_passes"] / max(agg["pass_launches"], 1),
+                         "us_per_launch": agg["ms_passes"] * 1e3 / max(agg["pass_launches"], 1)}
         print("# %s: %.1f shots/s, %.2f ms/step, pass %.0f GB/s" %
               (name, sps, ms, results[name]["pass_GBps"]), file=sys.stderr, flush=True)
     head = "tree" if "tree" in results else list(results)[0]
@@ -158,8 +179,10 @@ def main():
                    "x".join(map(str, h["shape"])), "qubits": 20, "gates": G, "shots": shots,
                    "tree": h["shape"], "cut": h["cut"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "pass_kernel<float>"},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
+                     "kernel": "pass_kernel<float>",
+                     "algorithmic_bytes_per_launch": h["bytes_per_launch"],
+                     "us_per_launch": h["us_per_launch"], "launches": h["pass_launches"]},
         "forms": {k: {kk: v[kk] for kk in ("shots_per_s", "ms_per_step", "pass_GBps", "shape")}
                   for k, v in results.items()},
     }

@@ -83,13 +83,13 @@ typedef struct {
 /* Planner and executor knobs; zero fields take the defaults. */
 typedef struct {
     uint32_t tile_qubits;      /* qubits per one-wave tile: 6 lane + register qubits
-                                  (10..12 at complex64, default 12; 10..11 at complex128,
-                                  default 11) */
+                                  (10..12 at complex64, default 11; 10..11 at complex128,
+                                  default 10) */
     uint32_t max_ops_per_pass; /* gates applied per HBM pass (default 1024) */
     uint32_t chunk_states;     /* live states per tree level (default 256) */
     uint32_t sample_block_log; /* log2 amplitudes per sampling block (default 12) */
     uint32_t pass_cost;        /* estimated lane instructions per amplitude allowed in one
-                                  pass before a new pass starts (default 80) */
+                                  pass before a new pass starts (default 240) */
 } tqs_tuning;
 
 /* Timing and traffic of one run. */
@@ -99,6 +99,7 @@ typedef struct {
     double ms_passes;          /* device time of the gate-apply passes */
     double ms_sample;          /* device time of the sampling kernels */
     uint64_t launches;         /* kernels launched */
+    uint64_t pass_launches;    /* of which gate-apply passes */
     uint64_t pass_states;      /* sum over pass launches of states processed */
     uint64_t bytes_passes;     /* algorithmic HBM bytes of the passes (read + write) */
     uint64_t bytes_sample;     /* algorithmic HBM bytes of sampling */

@@ -592,7 +592,7 @@ static tqs_status run_t(tqs_plan *p, const tqs_noise *nz, unsigned char *ws, uin
         cap_host.resize(Ly.state_bytes);
     }
 
-    uint64_t launches = 0, pass_states = 0, bytes_passes = 0, bytes_sample = 0;
+    uint64_t launches = 0, pass_launches = 0, pass_states = 0, bytes_passes = 0, bytes_sample = 0;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pass_ev, samp_ev;
     const uint64_t state_bytes = Ly.state_bytes;
     const uint32_t b = p->sample_b;
@@ -608,6 +608,7 @@ static tqs_status run_t(tqs_plan *p, const tqs_noise *nz, unsigned char *ws, uin
         for (uint32_t k = 0; k < lv.pass_count; k++) {
             launch_pass<R>(p, Ly, ws, s, t, lv.pass_begin + k, k == 0);
             launches++;
+            pass_launches++;
             pass_states += t.count;
             const bool init = (k == 0 && t.level == 0);
             bytes_passes += (uint64_t)t.count * state_bytes * (init ? 1 : 2);
@@ -678,6 +679,7 @@ static tqs_status run_t(tqs_plan *p, const tqs_noise *nz, unsigned char *ws, uin
             stats->ms_sample += ms;
         }
         stats->launches = launches;
+        stats->pass_launches = pass_launches;
         stats->pass_states = pass_states;
         stats->bytes_passes = bytes_passes;
         stats->bytes_sample = bytes_sample;

@@ -110,11 +110,11 @@ extern "C" tqs_status tqs_plan_create(const tqs_circuit *c, const tqs_tree *tree
     if (st) return st;
     tqs_tuning tu{};
     if (tuning) tu = *tuning;
-    if (!tu.tile_qubits) tu.tile_qubits = prec == TQS_C64 ? 12 : 11;
+    if (!tu.tile_qubits) tu.tile_qubits = prec == TQS_C64 ? 11 : 10;
     if (!tu.max_ops_per_pass) tu.max_ops_per_pass = 1024;
     if (!tu.chunk_states) tu.chunk_states = 256;
     if (!tu.sample_block_log) tu.sample_block_log = 12;
-    if (!tu.pass_cost) tu.pass_cost = 80;
+    if (!tu.pass_cost) tu.pass_cost = 240;
     const uint32_t tmax = prec == TQS_C64 ? 12 : 11;
     if (tu.tile_qubits < 10 || tu.tile_qubits > tmax)
         return fail(TQS_E_ARG, "tile_qubits must be in 10..%u at this precision", tmax);

@@ -34,7 +34,7 @@ class TqsTuning(C.Structure):
 
 class TqsRunStats(C.Structure):
     _fields_ = [("ms_wall", dbl), ("ms_device", dbl), ("ms_passes", dbl), ("ms_sample", dbl),
-                ("launches", u64), ("pass_states", u64), ("bytes_passes", u64),
+                ("launches", u64), ("pass_launches", u64), ("pass_states", u64), ("bytes_passes", u64),
                 ("bytes_sample", u64), ("events", u64)]
 
     def as_dict(self):
