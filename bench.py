@@ -80,6 +80,37 @@ def time_form(T, torch, circuit, tree, seed, steps, warmup, tuning=None):
     return plan.n_leaves * steps / dt, dt * 1000 / steps, agg, out
 
 
+def fidelity_loss(T, W, torch, seeds, n=20, shots=16384):
+    """Normalised fidelity (F_s of a peaked ideal distribution, normalised
+    against the uniform one) of the 20-qubit QFT round trip from a basis state,
+    tree (16, 32, 32) against per-shot, over noise seeds; difference +- its
+    standard error."""
+    import numpy as np
+    x = 0x5A5A5 & ((1 << n) - 1)
+    wc = W.concat(W.basis_prep(n, x), W.qft(n), W.inverse(W.qft(n))).with_depolarizing(1e-3, 1e-2)
+    G = len(wc)
+    c = T.Circuit.from_workload(wc)
+    u = 2.0 ** -n
+    out = {}
+    for name, tree in (("pershot", ([shots], [0, G])), ("tree", ([16, 32, 32], equal_cuts(G, 3)))):
+        plan = T.Plan(c, tree, "c64")
+        ws = None
+        vals = []
+        for s in range(seeds):
+            nz = T.Noise.sample(c, tree, s)
+            if ws is None:
+                ws = T.Workspace(plan.workspace_bytes(None))
+            o = T.run(plan, nz, ws)
+            fs = float(np.mean(o == x))          # F_s with P_ideal = delta_x
+            vals.append((fs - u) / (1 - u))
+        out[name] = np.array(vals)
+    d = out["tree"] - out["pershot"]
+    return {"workload": "qft%d round trip from |x>, depolarizing(1e-3,1e-2), %d shots" % (n, shots),
+            "F_pershot": float(out["pershot"].mean()), "F_tree": float(out["tree"].mean()),
+            "delta_F": float(d.mean()), "delta_F_se": float(d.std(ddof=1) / np.sqrt(len(d))),
+            "seeds": seeds}
+
+
 def cpu_baseline(wc, seed, budget_s=15.0):
     """The oracle (per-shot, complex128, threads over shots) on a bounded
     sample of the same workload's shots."""
@@ -117,6 +148,9 @@ def main():
     ap.add_argument("--tile", type=int, default=0, help="tile qubits (0 = library default)")
     ap.add_argument("--pass-cost", type=int, default=0, help="per-pass work bound (0 = default)")
     ap.add_argument("--chunk", type=int, default=0, help="live states per level (0 = default)")
+    ap.add_argument("--fidelity", action="store_true",
+                    help="also report the tree's fidelity loss against per-shot sampling")
+    ap.add_argument("--fid-seeds", type=int, default=10)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -141,6 +175,18 @@ def main():
         "tree4a": ([32, 8, 8, 8], equal_cuts(G, 4)),
         "tree4b": ([8, 8, 16, 16], equal_cuts(G, 4)),
     }
+    # state copy in gate-equivalents on this GPU (the DCP copy-cost input):
+    # one state's read + write at the streaming-copy rate, against the average
+    # time per gate execution of a per-shot run
+    copy_gbps = T.probe_copy(1 << 30, 10)
+    copy_us = 2 * 8 * (1 << 20) / (copy_gbps * 1e3)
+    sps_ps, _, agg_ps, _ = time_form(T, torch, circuit, forms["pershot"], args.seed, 1, 1)
+    gate_us = agg_ps["ms_passes"] * 1e3 / (shots * G)
+    copy_cost = copy_us / gate_us
+    dcp_shape = T.dcp(circuit, shots, 1.96, 0.01, copy_cost, 8)
+    forms["dcp"] = dcp_shape
+    if "dcp" not in args.forms.split(","):
+        args.forms += ",dcp"
     results = {}
     for name in args.forms.split(","):
         tree = forms[name]
@@ -188,6 +234,12 @@ def main():
     }
     if "pershot" in results and head != "pershot":
         line["tree_speedup_vs_pershot"] = h["shots_per_s"] / results["pershot"]["shots_per_s"]
+    line["copy_cost_gates"] = copy_cost
+    line["copy_GBps"] = copy_gbps
+    line["dcp"] = {"tree": dcp_shape[0], "cut": dcp_shape[1], "z": 1.96, "eps": 0.01,
+                   "copy_cost_gates": copy_cost}
+    if args.fidelity:
+        line["fidelity_loss"] = fidelity_loss(T, W, torch, args.fid_seeds)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(wc, args.seed, args.cpu_budget)
     print(json.dumps(line), flush=True)

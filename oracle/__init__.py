@@ -98,7 +98,7 @@ def flatten(gates) -> Flat:
         a = len(q)
         arity[g] = a
         qubits[2 * g:2 * g + a] = q
-        m = np.asarray(m, np.complex128).reshape(1 << a, 1 << a)
+        m = np.ascontiguousarray(np.asarray(m, np.complex128).reshape(1 << a, 1 << a))
         mats.append(m.view(np.float64).ravel())
         mat_off[g] = mo
         mo += 2 * (1 << (2 * a))

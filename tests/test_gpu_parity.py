@@ -290,3 +290,29 @@ def test_phase_run_term_groups(T, prec):
         _, amps = T.run_capture(plan, T.Noise.sample(c, tree, 0), [0])
         _, ref = oracle.run_events(12, wc.gates)
         assert np.max(np.abs(amps[0] - ref)) < TOL[prec], k
+
+
+def test_tree_fidelity_loss_is_small(T):
+    # the tree's normalised fidelity against per-shot sampling on a peaked
+    # output (QFT round trip from a basis state), over noise seeds: the mean
+    # difference stays within the paper's worst case (0.016) plus 3 SE
+    from oracle import tree as otree
+    n, shots = 12, 4096
+    x = 0xA5A & ((1 << n) - 1)
+    wc = W.concat(W.basis_prep(n, x), W.qft(n), W.inverse(W.qft(n))).with_depolarizing(5e-4, 5e-3)
+    G = len(wc)
+    c = T.Circuit.from_workload(wc)
+    p_ideal = np.zeros(1 << n)
+    p_ideal[x] = 1.0
+    F = {}
+    for name, tree in (("pershot", ([shots], [0, G])), ("tree", ([16, 16, 16], [0, G // 3, 2 * G // 3, G]))):
+        plan = T.Plan(c, tree, "c64")
+        vals = []
+        for s in range(6):
+            o = T.run(plan, T.Noise.sample(c, tree, s))
+            vals.append(otree.fidelity_norm(p_ideal, otree.hist_probs(o, n)))
+        F[name] = np.array(vals)
+    d = F["tree"] - F["pershot"]
+    se = d.std(ddof=1) / math.sqrt(d.size)
+    assert 0.2 < F["pershot"].mean() < 0.99
+    assert abs(d.mean()) <= 0.016 + 3 * se, (d.mean(), se)
