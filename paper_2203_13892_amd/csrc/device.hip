@@ -68,40 +68,114 @@ struct NodeMeta {
 
 namespace tqs {
 
-// FP64 sums of |psi|^2 over blocks of 2^b consecutive amplitudes.
+// Sampling reads the state in logical index order y (bit q of y is
+// logical qubit q) while the stored state s is indexed by physical
+// positions: logical qubit q sits at bit lay[q], so y maps to
+// P(y) = sum_q y_q 2^lay[q].  Blocks are the 2^b logical indices that share
+// their high bits; their FP64 masses come from two kernels: per chunk of
+// 2^c physically consecutive amplitudes (coalesced reads) the sums per
+// block the chunk touches, then per block the sum over its chunks.
+struct SampleMap {
+    uint32_t n, b, c;   // qubits, block log, chunk log
+    uint32_t kc;        // block bits among the chunk's c low positions
+    uint32_t part_log;  // log2 partial sums per state: (n - c) + kc
+    uint32_t cmask;     // positions of logical qubits b..n-1 (block bits)
+    uint32_t smask;     // positions of logical qubits 0..b-1
+    uint8_t lay[32];    // logical qubit -> physical position
+};
+
+// Partial masses: one workgroup per (state, chunk).  Inside a chunk the
+// amplitude at offset o belongs to the block spelled by o's block-bit
+// positions; o goes to LDS slot (pext(o, block bits) << sbits) | pext(o,
+// other bits), and each run of 2^sbits slots is summed pairwise.
 template <typename R>
-__global__ __launch_bounds__(kThreads) void block_sums_kernel(const cplx<R> *states, uint64_t slot_amps,
-                                                              const uint32_t *slots, uint32_t b,
-                                                              uint32_t nblocks, double *sums) {
-    __shared__ double red[kThreads];
-    const uint32_t k = blockIdx.x / nblocks, B = blockIdx.x % nblocks;
-    const cplx<R> *psi = states + (uint64_t)slots[k] * slot_amps + ((uint64_t)B << b);
-    double acc = 0.0;
-    for (uint32_t i = threadIdx.x; i < (1u << b); i += kThreads) {
-        const cplx<R> v = psi[i];
-        acc += (double)v.re * (double)v.re + (double)v.im * (double)v.im;
+__global__ __launch_bounds__(kThreads) void block_partials_kernel(const cplx<R> *states, uint64_t slot_amps,
+                                                                  const uint32_t *slots, SampleMap m,
+                                                                  double *part) {
+    __shared__ double buf[1u << 12];
+    __shared__ uint32_t tab[2][64];
+    const uint32_t nch = 1u << (m.n - m.c);
+    const uint32_t k = blockIdx.x / nch, ch = blockIdx.x % nch;
+    const uint32_t cl = (1u << m.c) - 1u;
+    const uint32_t cm = m.cmask & cl;
+    const uint32_t sbits = m.c - m.kc;
+    if (threadIdx.x < 128) {
+        const uint32_t h = threadIdx.x >> 6;
+        const uint32_t v = (threadIdx.x & 63u) << (6 * h);
+        uint32_t ci = 0, si = 0, nc = 0, ns = 0;
+        for (uint32_t bit = 0; bit < m.c; bit++) {
+            const uint32_t one = (v >> bit) & 1u;
+            if ((cm >> bit) & 1u) {
+                ci |= one << nc;
+                nc++;
+            } else {
+                si |= one << ns;
+                ns++;
+            }
+        }
+        tab[h][threadIdx.x & 63u] = (ci << sbits) | si;
     }
-    red[threadIdx.x] = acc;
     __syncthreads();
-    for (uint32_t s = kThreads / 2; s > 0; s >>= 1) {
-        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    const cplx<R> *s = states + (uint64_t)slots[k] * slot_amps + ((uint64_t)ch << m.c);
+    for (uint32_t i = threadIdx.x; i <= cl; i += kThreads) {
+        const cplx<R> v = s[i];
+        buf[tab[0][i & 63u] | tab[1][(i >> 6) & 63u]] = (double)v.re * (double)v.re + (double)v.im * (double)v.im;
+    }
+    __syncthreads();
+    for (uint32_t h = 1; h < (1u << sbits); h <<= 1) {
+        for (uint32_t i = threadIdx.x; i < ((1u << m.c) >> 1) / h; i += kThreads) {
+            const uint32_t e = i * 2 * h;
+            buf[e] += buf[e + h];
+        }
         __syncthreads();
     }
-    if (threadIdx.x == 0) sums[(uint64_t)k * nblocks + B] = red[0];
+    double *out = part + ((uint64_t)k << m.part_log) + ((uint64_t)ch << m.kc);
+    for (uint32_t j = threadIdx.x; j < (1u << m.kc); j += kThreads) out[j] = buf[j << sbits];
 }
 
-// Inverse-CDF sampling of one leaf per workgroup, in the index order of the
-// true state psi = F s: psi's block B_L is s's block B_L ^ (x >> b) and
-// inside it index y is s's (y ^ x) low bits.  The outcome is
-// min { y : sum_{y' <= y} |psi_y'|^2 > u T } with FP64 sums.
+// Block masses in logical block order: block B's amplitudes lie in the
+// chunks spelled by P(B 2^b) plus any value of the in-block positions above
+// the chunk, at the same partial index in each.
+__global__ __launch_bounds__(kThreads) void block_gather_kernel(SampleMap m, const double *part,
+                                                                uint32_t count, double *sums) {
+    const uint32_t nblocks = 1u << (m.n - m.b);
+    const uint64_t gid = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (gid >= (uint64_t)count * nblocks) return;
+    const uint32_t k = (uint32_t)(gid / nblocks), B = (uint32_t)(gid % nblocks);
+    uint32_t pb = 0;
+    for (uint32_t q = m.b; q < m.n; q++) pb |= ((B >> (q - m.b)) & 1u) << m.lay[q];
+    uint32_t j = 0, nc = 0;
+    for (uint32_t bit = 0; bit < m.c; bit++)
+        if ((m.cmask >> bit) & 1u) {
+            j |= ((pb >> bit) & 1u) << nc;
+            nc++;
+        }
+    const uint32_t chunk0 = pb >> m.c;
+    const uint32_t sh = m.smask >> m.c;
+    const double *pk = part + ((uint64_t)k << m.part_log);
+    double acc = 0.0;
+    uint32_t sub = 0;
+    do {
+        acc += pk[((uint64_t)(chunk0 | sub) << m.kc) | j];
+        sub = (sub - sh) & sh;  // next subset of sh, increasing
+    } while (sub != 0);
+    sums[gid] = acc;
+}
+
+// Inverse-CDF sampling of one leaf per workgroup, in the logical index
+// order of the true state psi = F s: with the frame's X bits in logical
+// order xl, psi's block B_L is s's block B_L ^ (xl >> b) and inside it
+// index y is s's (y ^ xl) low bits, read at physical position P(.).  The
+// outcome is min { y : sum_{y' <= y} |psi_y'|^2 > u T } with FP64 sums.
 template <typename R>
 __global__ __launch_bounds__(kThreads) void sample_kernel(const cplx<R> *states, uint64_t slot_amps,
                                                           const uint32_t *slots, const uint32_t *node_ids,
                                                           uint32_t leaf_off, uint32_t b, uint32_t nblocks,
                                                           const double *sums,
                                                           const double *leaf_u, const uint32_t *leaf_fx,
-                                                          uint64_t *outcomes, uint64_t leaf_first) {
+                                                          uint64_t *outcomes, uint64_t leaf_first, SampleMap m) {
     __shared__ double part[kThreads];
+    __shared__ uint32_t ptab[3][64];  // P of the in-block index, by 6-bit digit
     __shared__ double pre[kThreads];
     __shared__ uint32_t hit;
     __shared__ double tsh, cum_sh;
@@ -112,6 +186,14 @@ __global__ __launch_bounds__(kThreads) void sample_kernel(const cplx<R> *states,
     const uint32_t xb = x >> b, xlow = x & ((1u << b) - 1u);
     const double *S = sums + (uint64_t)k * nblocks;
     const cplx<R> *psi = states + (uint64_t)slots[k] * slot_amps;
+    if (tid < 192) {
+        const uint32_t h = tid >> 6;
+        const uint32_t v = (tid & 63u) << (6 * h);
+        uint32_t pv = 0;
+        for (uint32_t q = 0; q < b; q++) pv |= ((v >> q) & 1u) << m.lay[q];
+        ptab[h][tid & 63u] = pv;
+    }
+    auto plow = [&](uint32_t v) { return ptab[0][v & 63u] | ptab[1][(v >> 6) & 63u] | ptab[2][(v >> 12) & 63u]; };
 
     // logical block prefix: thread t owns blocks [t*seg, (t+1)*seg)
     const uint32_t seg = (nblocks + kThreads - 1) / kThreads;
@@ -164,13 +246,15 @@ __global__ __launch_bounds__(kThreads) void sample_kernel(const cplx<R> *states,
     }
     __syncthreads();
     const uint32_t Bp = BL ^ xb;
-    const cplx<R> *blk = psi + ((uint64_t)Bp << b);
+    uint32_t pB = 0;
+    for (uint32_t q = b; q < m.n; q++) pB |= ((Bp >> (q - b)) & 1u) << m.lay[q];
+    const cplx<R> *blk = psi + pB;
     const uint32_t nb = 1u << b;
     const uint32_t iseg = (nb + kThreads - 1) / kThreads;
     const uint32_t y0 = tid * iseg, y1 = min(nb, y0 + iseg);
     s = 0.0;
     for (uint32_t y = y0; y < y1; y++) {
-        const cplx<R> v = blk[y ^ xlow];
+        const cplx<R> v = blk[plow(y ^ xlow)];
         s += (double)v.re * (double)v.re + (double)v.im * (double)v.im;
     }
     part[tid] = s;
@@ -186,7 +270,7 @@ __global__ __launch_bounds__(kThreads) void sample_kernel(const cplx<R> *states,
     {
         double run = pre[tid];
         for (uint32_t y = y0; y < y1; y++) {
-            const cplx<R> v = blk[y ^ xlow];
+            const cplx<R> v = blk[plow(y ^ xlow)];
             run += (double)v.re * (double)v.re + (double)v.im * (double)v.im;
             if (run > t) {
                 atomicMin(&hit, y);
@@ -200,7 +284,7 @@ __global__ __launch_bounds__(kThreads) void sample_kernel(const cplx<R> *states,
         if (y == 0xFFFFFFFFu) {
             y = 0;
             for (uint32_t i = 0; i < nb; i++) {
-                const cplx<R> v = blk[i ^ xlow];
+                const cplx<R> v = blk[plow(i ^ xlow)];
                 if ((double)v.re * v.re + (double)v.im * v.im > 0.0) y = i;
             }
         }
@@ -208,15 +292,18 @@ __global__ __launch_bounds__(kThreads) void sample_kernel(const cplx<R> *states,
     }
 }
 
-// Standalone Pauli application: out(y) = i^k (-1)^{z.(y^x)} in(y ^ x),
-// i.e. the frame F = i^k X^x Z^z applied to a stored state.
+// Standalone Pauli application in logical order: out(y) = i^k (-1)^{z.w}
+// in(w) with w = P(y) ^ x, i.e. the frame F = i^k X^x Z^z applied to a
+// stored state, read out with logical qubit q at bit q.
 template <typename R>
 __global__ __launch_bounds__(kThreads) void frame_apply_kernel(const cplx<R> *in, cplx<R> *out,
                                                                uint64_t amps, uint32_t x, uint32_t z,
-                                                               uint32_t k) {
+                                                               uint32_t k, SampleMap m) {
     const uint64_t y = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
     if (y >= amps) return;
-    const uint32_t w = (uint32_t)y ^ x;
+    uint32_t py = 0;
+    for (uint32_t q = 0; q < m.n; q++) py |= (((uint32_t)y >> q) & 1u) << m.lay[q];
+    const uint32_t w = py ^ x;
     cplx<R> v = in[w];
     v = cneg_if(v, __builtin_popcount(z & w) & 1u);
     for (uint32_t i = 0; i < (k & 3u); i++) v = cplx<R>{-v.im, v.re};
@@ -264,7 +351,7 @@ struct Layout {
     std::vector<uint32_t> slot_base;  // per level
     uint32_t scratch_slot;
     uint64_t off_meta, off_mats, off_ops, off_passes, off_terms, off_dgates, off_expt, off_frame0, off_evoff,
-        off_evpos, off_evdx, off_evdz, off_leafu, off_leaffx, off_sched, off_sums, off_out, total;
+        off_evpos, off_evdx, off_evdz, off_leafu, off_leaffx, off_sched, off_sums, off_part, off_out, total;
     uint64_t n_sched;
 };
 
@@ -313,6 +400,8 @@ static Layout make_layout(const tqs_plan *p, uint64_t n_events, uint64_t n_leave
     L.off_sums = o;
     const uint64_t nblocks = 1ull << (p->n - p->sample_b);
     o = align256(o + (uint64_t)p->chunk.back() * nblocks * 8);
+    L.off_part = o;
+    o = align256(o + ((uint64_t)p->chunk.back() << p->part_log) * 8);
     L.off_out = o;
     o = align256(o + n_leaves_out * 8);
     L.total = o;
@@ -375,6 +464,8 @@ struct HostMeta {
 // Map the insertion list onto pass positions and Pauli masks, and compose
 // each node's frame from its parent's (Sec. 3.1: a child continues from a
 // copy of its parent's state, noise included).
+static uint32_t to_logical(const tqs_plan *p, uint32_t x);
+
 static void build_meta(const tqs_plan *p, const tqs_noise *nz, HostMeta *hm) {
     const uint64_t N = p->n_nodes;
     hm->frame0.assign(2 * N, 0);
@@ -386,6 +477,7 @@ static void build_meta(const tqs_plan *p, const tqs_noise *nz, HostMeta *hm) {
     hm->leaf_fx.assign(p->n_leaves, 0);
     hm->leaf_frame.assign(p->n_leaves, Frame());
     std::vector<Frame> fend(N);
+    std::vector<std::pair<uint32_t, uint64_t>> ord;
     const uint32_t L = (uint32_t)p->arity.size();
     for (uint32_t l = 0; l < L; l++) {
         const uint64_t I = p->level_nodes[l], off = p->level_offset[l];
@@ -395,7 +487,20 @@ static void build_meta(const tqs_plan *p, const tqs_noise *nz, HostMeta *hm) {
             if (l > 0) f = fend[p->level_offset[l - 1] + m / p->arity[l]];
             hm->frame0[2 * nu] = f.x;
             hm->frame0[2 * nu + 1] = f.z;
-            for (uint64_t e = nz->node_off[nu]; e < nz->node_off[nu + 1]; e++) {
+            // the node's events in the order the passes meet them (gates that
+            // share no qubit may run out of circuit order)
+            const uint64_t e0 = nz->node_off[nu], e1 = nz->node_off[nu + 1];
+            ord.clear();
+            for (uint64_t e = e0; e < e1; e++) {
+                const uint32_t g = nz->ev_gate[e];
+                ord.push_back({(p->gate_pass[g] << 16) | p->gate_pos[g], e});
+            }
+            std::stable_sort(ord.begin(), ord.end(),
+                             [](const std::pair<uint32_t, uint64_t> &a, const std::pair<uint32_t, uint64_t> &b) {
+                                 return a.first < b.first;
+                             });
+            for (uint64_t i = 0; i < ord.size(); i++) {
+                const uint64_t e = ord[i].second, o = e0 + i;
                 const uint32_t g = nz->ev_gate[e];
                 const uint32_t code = nz->ev_code[e];
                 uint32_t dx = 0, dz = 0, ky = 0;
@@ -407,15 +512,15 @@ static void build_meta(const tqs_plan *p, const tqs_noise *nz, HostMeta *hm) {
                     if (cj == 2) ky++;  // Y = i X Z
                 }
                 // the product of the one-qubit factors: X^dx Z^dz up to i^ky
-                hm->ev_pos[e] = (p->gate_pass[g] << 16) | p->gate_pos[g];
-                hm->ev_dx[e] = dx;
-                hm->ev_dz[e] = dz;
+                hm->ev_pos[o] = ord[i].first;
+                hm->ev_dx[o] = dx;
+                hm->ev_dz[o] = dz;
                 f = compose(dx, dz, ky, f);
             }
             hm->ev_off[nu + 1] = (uint32_t)nz->node_off[nu + 1];
             fend[nu] = f;
             if (l == L - 1) {
-                hm->leaf_fx[m] = f.x;
+                hm->leaf_fx[m] = to_logical(p, f.x);
                 hm->leaf_frame[m] = f;
             }
         }
@@ -473,22 +578,50 @@ static void launch_pass(const tqs_plan *p, const Layout &Ly, unsigned char *ws, 
 }
 
 
+static SampleMap sample_map(const tqs_plan *p) {
+    SampleMap m;
+    std::memset(&m, 0, sizeof m);
+    m.n = p->n;
+    m.b = p->sample_b;
+    m.c = std::min<uint32_t>(p->n, 12u);
+    for (uint32_t q = 0; q < p->n; q++) {
+        m.lay[q] = (uint8_t)p->lay_final[q];
+        if (q >= m.b) m.cmask |= 1u << p->lay_final[q];
+        else m.smask |= 1u << p->lay_final[q];
+    }
+    m.kc = (uint32_t)__builtin_popcount(m.cmask & ((1u << m.c) - 1u));
+    m.part_log = p->part_log;
+    return m;
+}
+
+// logical-order bits of a physical mask
+static uint32_t to_logical(const tqs_plan *p, uint32_t x) {
+    uint32_t r = 0;
+    for (uint32_t q = 0; q < p->n; q++) r |= ((x >> p->lay_final[q]) & 1u) << q;
+    return r;
+}
+
 template <typename R>
 static void launch_sample(const tqs_plan *p, const Layout &Ly, unsigned char *ws, hipStream_t s,
                           const Task &t, uint64_t leaf_first) {
+    const SampleMap m = sample_map(p);
     const uint32_t b = p->sample_b;
     const uint32_t nblocks = 1u << (p->n - b);
     const uint32_t *sched = reinterpret_cast<const uint32_t *>(ws + Ly.off_sched) + t.sched;
     const cplx<R> *st = reinterpret_cast<const cplx<R> *>(ws);
     double *sums = reinterpret_cast<double *>(ws + Ly.off_sums);
+    double *part = reinterpret_cast<double *>(ws + Ly.off_part);
     const uint32_t leaf_off = (uint32_t)p->level_offset.back();
-    hipLaunchKernelGGL(block_sums_kernel<R>, dim3(t.count * nblocks), dim3(kThreads), 0, s, st,
-                       1ull << p->n, sched + 2 * t.count, b, nblocks, sums);
+    hipLaunchKernelGGL(block_partials_kernel<R>, dim3(t.count << (p->n - m.c)), dim3(kThreads), 0, s, st,
+                       1ull << p->n, sched + 2 * t.count, m, part);
+    const uint64_t nsum = (uint64_t)t.count * nblocks;
+    hipLaunchKernelGGL(block_gather_kernel, dim3((uint32_t)((nsum + kThreads - 1) / kThreads)), dim3(kThreads),
+                       0, s, m, part, t.count, sums);
     hipLaunchKernelGGL(sample_kernel<R>, dim3(t.count), dim3(kThreads), 0, s, st, 1ull << p->n,
                        sched + 2 * t.count, sched, leaf_off, b, nblocks, sums,
                        reinterpret_cast<const double *>(ws + Ly.off_leafu),
                        reinterpret_cast<const uint32_t *>(ws + Ly.off_leaffx),
-                       reinterpret_cast<uint64_t *>(ws + Ly.off_out), leaf_first);
+                       reinterpret_cast<uint64_t *>(ws + Ly.off_out), leaf_first, m);
 }
 
 static tqs_status check_noise(const tqs_plan *p, const tqs_noise *nz) {
@@ -619,7 +752,7 @@ static tqs_status run_t(tqs_plan *p, const tqs_noise *nz, unsigned char *ws, uin
         }
         if (t.level == L - 1) {
             launch_sample<R>(p, Ly, ws, s, t, leaf_first);
-            launches += 2;
+            launches += 3;
             bytes_sample += (uint64_t)t.count * (state_bytes + (Ly.amp_bytes << b));
             if (stats) {
                 ec = pool_event(p, ev_i++);
@@ -640,7 +773,7 @@ static tqs_status run_t(tqs_plan *p, const tqs_noise *nz, unsigned char *ws, uin
                         const cplx<R> *in = reinterpret_cast<const cplx<R> *>(ws) + (uint64_t)slot * amps;
                         cplx<R> *out = reinterpret_cast<cplx<R> *>(ws) + (uint64_t)Ly.scratch_slot * amps;
                         hipLaunchKernelGGL(frame_apply_kernel<R>, dim3((uint32_t)((amps + kThreads - 1) / kThreads)),
-                                           dim3(kThreads), 0, s, in, out, amps, f.x, f.z, f.k);
+                                           dim3(kThreads), 0, s, in, out, amps, f.x, f.z, f.k, sample_map(p));
                         HIP_TRY(hipGetLastError(), "frame_apply launch");
                         HIP_TRY(hipMemcpyAsync(cap_host.data(), out, state_bytes, hipMemcpyDeviceToHost, s),
                                 "capture copy");

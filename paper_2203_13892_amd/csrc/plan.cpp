@@ -9,6 +9,15 @@
 // qubit and runs anywhere.  Consecutive diagonal gates become one phase run:
 // the product of diagonal unitaries is a phase polynomial of degree two in
 // the index bits, evaluated per lane in fixed-point turns.
+//
+// Logical qubits sit at physical bit positions that change along the
+// circuit: a swap gate only exchanges two positions (no data moves), and
+// at the end of a pass the planner may exchange lane and register positions
+// (a swap op inside the tile) so that the qubits the next gates change sit
+// in lanes.  Gates are taken out of order when they commute: a gate may run
+// before an earlier one that it shares no qubit with.  A noise event acts
+// right after its gate in the order the pass runs, which is the circuit's
+// own order on the gate's qubits, so every trajectory is unchanged.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -66,11 +75,27 @@ static uint64_t turns_fixed(const cd &z) {
     return v << 2;  // wraps modulo one turn
 }
 
+constexpr uint32_t kNoGate = 0xFFFFFFFFu;  // a lane exchange inserted by the planner
+
 struct PendingGate {
-    uint32_t g;
+    uint32_t g;      // circuit gate, or kNoGate
     GateClass gc;
     uint32_t ctrl;
+    uint32_t pq[2];  // physical positions of the gate's qubits when it runs
 };
+
+// The two-qubit swap (exactly): it only relabels positions.
+static bool is_swap(const Gate &g) {
+    if (g.a != 2) return false;
+    for (int r = 0; r < 4; r++)
+        for (int c = 0; c < 4; c++) {
+            const bool one = (r == c && (r == 0 || r == 3)) || (r == 1 && c == 2) || (r == 2 && c == 1);
+            if (g.m[r * 4 + c] != cd(one ? 1.0 : 0.0, 0.0)) return false;
+        }
+    return true;
+}
+
+static const cd kSwapMat[16] = {1, 0, 0, 0, 0, 0, 1, 0, 0, 1, 0, 0, 0, 0, 0, 1};
 
 // Estimated lane instructions per amplitude of each op (used to bound the
 // work of one pass to about what its HBM traffic takes).
@@ -151,8 +176,26 @@ extern "C" tqs_status tqs_plan_create(const tqs_circuit *c, const tqs_tree *tree
     const uint32_t nr_max = std::min(n - nl, p->reg_bits);
     const uint32_t lane_mask = (1u << nl) - 1u;
 
+    // the planner's permutation of qubit positions: lay[logical] = physical
+    std::vector<uint32_t> lay(n), inv(n);
+    for (uint32_t q = 0; q < n; q++) lay[q] = inv[q] = q;
+    auto swap_pos = [&](uint32_t pa, uint32_t pb) {
+        const uint32_t qa = inv[pa], qb = inv[pb];
+        lay[qa] = pb;
+        lay[qb] = pa;
+        inv[pa] = qb;
+        inv[pb] = qa;
+    };
+    std::vector<GateClass> cls(p->n_gates);
+    std::vector<uint32_t> ctl(p->n_gates, 0);
+    std::vector<char> swp(p->n_gates, 0);
+    for (uint32_t gi = 0; gi < p->n_gates; gi++) {
+        cls[gi] = classify(c->gates[gi], &ctl[gi]);
+        swp[gi] = is_swap(c->gates[gi]) ? 1 : 0;
+    }
+
     std::vector<PendingGate> pend;
-    uint32_t pend_changed = 0;  // changed qubits >= nl (need register slots)
+    uint32_t pend_regs = 0;     // physical register positions the pass needs
     double pend_cost = 4.0;     // load + store
     uint32_t pend_lds = 0;      // bytes of the pass's staged op data
     const uint32_t amp_bytes = prec == TQS_C64 ? 8 : 16;
@@ -161,8 +204,8 @@ extern "C" tqs_status tqs_plan_create(const tqs_circuit *c, const tqs_tree *tree
         PassDesc d;
         std::memset(&d, 0, sizeof d);
         d.nl = (uint8_t)nl;
-        // register qubits: the changed high qubits, then the lowest others
-        uint32_t regs = pend_changed;
+        // register qubits: the needed positions, then the lowest others
+        uint32_t regs = pend_regs;
         for (uint32_t b = nl; b < n && (uint32_t)__builtin_popcount(regs) < nr_max; b++) regs |= 1u << b;
         uint8_t role[32], pos[32];
         for (uint32_t b = 0; b < n; b++) {
@@ -186,11 +229,9 @@ extern "C" tqs_status tqs_plan_create(const tqs_circuit *c, const tqs_tree *tree
         d.op_begin = (uint32_t)p->ops.size();
         d.mat_begin = (uint32_t)p->mats.size();
         d.term_begin = (uint32_t)p->terms.size();
-        const uint32_t pass_idx = (uint32_t)p->passes.size();
 
         size_t i = 0;
         while (i < pend.size()) {
-            const Gate &g0 = c->gates[pend[i].g];
             OpDesc o;
             std::memset(&o, 0, sizeof o);
             o.slot0 = (uint16_t)i;
@@ -218,23 +259,24 @@ extern "C" tqs_status tqs_plan_create(const tqs_circuit *c, const tqs_tree *tree
                 };
                 for (size_t k = i; k < j; k++) {
                     const Gate &g = c->gates[pend[k].g];
+                    const uint32_t *pq = pend[k].pq;
                     const uint32_t nd = 1u << g.a;
                     DiagGate dg;
                     std::memset(&dg, 0, sizeof dg);
                     dg.nq = (uint8_t)g.a;
                     uint32_t nreg = 0, nlane = 0;
                     for (uint32_t q = 0; q < g.a; q++) {
-                        dg.role[q] = role[g.q[q]];
-                        dg.pos[q] = pos[g.q[q]];
-                        dg.phys[q] = (uint8_t)g.q[q];
-                        if (role[g.q[q]] == ROLE_REG) nreg++;
-                        if (role[g.q[q]] == ROLE_LANE) nlane++;
+                        dg.role[q] = role[pq[q]];
+                        dg.pos[q] = pos[pq[q]];
+                        dg.phys[q] = (uint8_t)pq[q];
+                        if (role[pq[q]] == ROLE_REG) nreg++;
+                        if (role[pq[q]] == ROLE_LANE) nlane++;
                     }
                     p->dgates.push_back(dg);
                     if (nreg == g.a) {
                         for (uint32_t t = 0; t < nt; t++) {
                             uint32_t r = 0;
-                            for (uint32_t q = 0; q < g.a; q++) r |= ((t >> pos[g.q[q]]) & 1u) << q;
+                            for (uint32_t q = 0; q < g.a; q++) r |= ((t >> pos[pq[q]]) & 1u) << q;
                             tab[t] *= g.m[r * nd + r];
                         }
                         has_t = true;
@@ -246,17 +288,17 @@ extern "C" tqs_status tqs_plan_create(const tqs_circuit *c, const tqs_tree *tree
                     // order: qubit 0 = a lane qubit if any, else a fixed one
                     uint32_t q0 = 0;
                     if (g.a == 2) {
-                        const uint32_t r0 = role[g.q[0]], r1 = role[g.q[1]];
+                        const uint32_t r0 = role[pq[0]], r1 = role[pq[1]];
                         if (r0 == ROLE_REG || (r0 == ROLE_FIXED && r1 == ROLE_LANE)) q0 = 1;
                     }
                     const uint32_t q1 = 1 - q0;
-                    tm.role[0] = role[g.q[q0]];
-                    tm.pos[0] = pos[g.q[q0]];
-                    tm.phys[0] = (uint8_t)g.q[q0];
+                    tm.role[0] = role[pq[q0]];
+                    tm.pos[0] = pos[pq[q0]];
+                    tm.phys[0] = (uint8_t)pq[q0];
                     if (g.a == 2) {
-                        tm.role[1] = role[g.q[q1]];
-                        tm.pos[1] = pos[g.q[q1]];
-                        tm.phys[1] = (uint8_t)g.q[q1];
+                        tm.role[1] = role[pq[q1]];
+                        tm.pos[1] = pos[pq[q1]];
+                        tm.phys[1] = (uint8_t)pq[q1];
                     }
                     for (uint32_t r = 0; r < nd; r++) {
                         // r in the normalised order -> index in the gate's order
@@ -298,22 +340,24 @@ extern "C" tqs_status tqs_plan_create(const tqs_circuit *c, const tqs_tree *tree
                 }
                 i = j;
             } else {
-                const Gate &g = g0;
+                const bool ins = pend[i].g == kNoGate;
+                const uint32_t a = ins ? 2u : c->gates[pend[i].g].a;
+                const cd *m = ins ? kSwapMat : c->gates[pend[i].g].m;
                 o.slot1 = (uint16_t)(i + 1);
-                o.nq = (uint8_t)g.a;
-                for (uint32_t q = 0; q < g.a; q++) {
-                    o.role[q] = role[g.q[q]];
-                    o.pos[q] = pos[g.q[q]];
-                    o.phys[q] = (uint8_t)g.q[q];
+                o.nq = (uint8_t)a;
+                for (uint32_t q = 0; q < a; q++) {
+                    o.role[q] = role[pend[i].pq[q]];
+                    o.pos[q] = pos[pend[i].pq[q]];
+                    o.phys[q] = (uint8_t)pend[i].pq[q];
                 }
                 o.kind = pend[i].gc == GC_DENSE2 ? OP_DENSE2 : OP_DENSE1;
                 o.tq = pend[i].gc == GC_CTRL ? (uint8_t)(1 - pend[i].ctrl) : 0;
                 o.mat = (uint32_t)p->mats.size();
-                const uint32_t nd = 1u << g.a;
+                const uint32_t nd = 1u << a;
                 o.real = 1;
                 for (uint32_t r = 0; r < nd * nd; r++) {
-                    p->mats.push_back(g.m[r]);
-                    if (g.m[r].imag() != 0.0) o.real = 0;
+                    p->mats.push_back(m[r]);
+                    if (m[r].imag() != 0.0) o.real = 0;
                 }
                 i++;
             }
@@ -325,73 +369,140 @@ extern "C" tqs_status tqs_plan_create(const tqs_circuit *c, const tqs_tree *tree
         d.has_d2 = 0;
         for (uint32_t k = d.op_begin; k < (uint32_t)p->ops.size(); k++)
             if (p->ops[k].kind == OP_DENSE2) d.has_d2 = 1;
-        (void)pass_idx;
         p->passes.push_back(d);
         pend.clear();
-        pend_changed = 0;
+        pend_regs = 0;
         pend_cost = 4.0;
         pend_lds = 0;
     };
 
+    const double diag_setup = 14.0 + 0.7 * (nr_max + 1);
+    const double lane_swap_cost = 12.0;
     for (uint32_t l = 0; l < L; l++) {
         tqs::Level lv;
         lv.pass_begin = (uint32_t)p->passes.size();
         lv.g0 = cut[l];
         lv.g1 = cut[l + 1];
-        bool in_diag_run = false;
-        uint32_t run_terms = 0;
-        for (uint32_t gi = cut[l]; gi < cut[l + 1]; gi++) {
-            const Gate &g = c->gates[gi];
-            uint32_t ctrl = 0;
-            const GateClass gc = classify(g, &ctrl);
-            const uint32_t ch = changed_mask(g, gc, ctrl) & ~lane_mask;
-            const uint32_t need = (uint32_t)__builtin_popcount(pend_changed | ch);
-            double cost;
-            if (gc == GC_DIAG) {
-                // a new run pays its per-amplitude evaluation; each term adds
-                // per-lane work spread over the lane's amplitudes
-                cost = (in_diag_run ? 0.0 : 14.0 + 0.7 * (nr_max + 1)) + 0.2;
-                run_terms++;
-            } else {
-                const uint32_t tq = gc == GC_CTRL ? 1 - ctrl : 0;
-                const bool lt = g.q[tq] < nl;
-                const bool lo = g.a == 2 && g.q[1 - tq] < nl;
-                cost = op_cost(gc, lt, lo);
-            }
-            // staged bytes: op record, matrix or diagonal, phase term, run table
-            uint32_t lds = 0;
-            if (gc == GC_DIAG)
-                lds = (uint32_t)(sizeof(DiagTerm) + 4 * amp_bytes) +
-                      (in_diag_run ? 0u : (uint32_t)sizeof(OpDesc) + (amp_bytes << nr_max));
-            else
-                lds = (uint32_t)sizeof(OpDesc) + (g.a == 2 ? 16u : 4u) * amp_bytes;
-            if (!pend.empty() && (need > nr_max || pend_cost + cost > tu.pass_cost ||
-                                  pend_lds + lds > kPassLdsBytes ||
-                                  pend.size() >= tu.max_ops_per_pass || pend.size() >= 60000)) {
-                emit();
-                run_terms = 0;
-                if (gc == GC_DIAG && in_diag_run) {
-                    // the run restarts in the new pass: it pays its set-up again
-                    cost = 14.0 + 0.7 * (nr_max + 1) + 0.2;
-                    lds += (uint32_t)sizeof(OpDesc) + (amp_bytes << nr_max);
+        std::vector<uint32_t> rem;
+        for (uint32_t gi = cut[l]; gi < cut[l + 1]; gi++) rem.push_back(gi);
+        // every level has at least one pass: its first pass copies the parent
+        bool first_pass = true;
+        while (first_pass || !rem.empty()) {
+            first_pass = false;
+            bool in_diag_run = false;
+            uint32_t blocked = 0;  // logical qubits of gates left for later passes
+            std::vector<uint32_t> left;
+            for (uint32_t gi : rem) {
+                const Gate &g = c->gates[gi];
+                const uint32_t qm = (1u << g.q[0]) | (g.a == 2 ? 1u << g.q[1] : 0u);
+                if (qm & blocked) {
+                    blocked |= qm;
+                    left.push_back(gi);
+                    continue;
                 }
-                in_diag_run = false;
+                p->gate_a[gi] = g.a;
+                if (swp[gi]) {
+                    // relabel: the two logical qubits exchange positions
+                    swap_pos(lay[g.q[0]], lay[g.q[1]]);
+                    p->gate_pass[gi] = (uint32_t)p->passes.size();
+                    p->gate_pos[gi] = (uint32_t)pend.size();
+                    p->gate_q0[gi] = lay[g.q[0]];
+                    p->gate_q1[gi] = lay[g.q[1]];
+                    continue;
+                }
+                const GateClass gc = cls[gi];
+                const uint32_t ctrl = ctl[gi];
+                uint32_t chl = changed_mask(g, gc, ctrl), ch = 0;
+                for (uint32_t q = 0; q < n; q++)
+                    if ((chl >> q) & 1u) ch |= 1u << lay[q];
+                ch &= ~lane_mask;
+                const uint32_t need = (uint32_t)__builtin_popcount(pend_regs | ch);
+                double cost;
+                if (gc == GC_DIAG) {
+                    // a new run pays its per-amplitude evaluation; each term adds
+                    // per-lane work spread over the lane's amplitudes
+                    cost = (in_diag_run ? 0.0 : diag_setup) + 0.2;
+                } else {
+                    const uint32_t tq = gc == GC_CTRL ? 1 - ctrl : 0;
+                    const bool lt = lay[g.q[tq]] < nl;
+                    const bool lo = g.a == 2 && lay[g.q[1 - tq]] < nl;
+                    cost = op_cost(gc, lt, lo);
+                }
+                // staged bytes: op record, matrix or diagonal, phase term, run table
+                uint32_t lds = 0;
+                if (gc == GC_DIAG)
+                    lds = (uint32_t)(sizeof(DiagTerm) + 4 * amp_bytes) +
+                          (in_diag_run ? 0u : (uint32_t)sizeof(OpDesc) + (amp_bytes << nr_max));
+                else
+                    lds = (uint32_t)sizeof(OpDesc) + (g.a == 2 ? 16u : 4u) * amp_bytes;
+                if (!pend.empty() && (need > nr_max || pend_cost + cost > tu.pass_cost ||
+                                      pend_lds + lds > kPassLdsBytes ||
+                                      pend.size() >= tu.max_ops_per_pass || pend.size() >= 60000)) {
+                    blocked |= qm;
+                    left.push_back(gi);
+                    continue;
+                }
+                in_diag_run = (gc == GC_DIAG);
+                pend_regs |= ch;
+                pend_cost += cost;
+                pend_lds += lds;
+                PendingGate pg{gi, gc, ctrl, {lay[g.q[0]], g.a == 2 ? lay[g.q[1]] : lay[g.q[0]]}};
+                pend.push_back(pg);
+                p->gate_pass[gi] = (uint32_t)p->passes.size();
+                p->gate_pos[gi] = (uint32_t)pend.size();  // slot after this gate
+                p->gate_q0[gi] = pg.pq[0];
+                p->gate_q1[gi] = pg.pq[1];
             }
-            in_diag_run = (gc == GC_DIAG);
-            pend_changed |= ch;
-            pend_cost += cost;
-            pend_lds += lds;
-            pend.push_back({gi, gc, ctrl});
-            p->gate_pass[gi] = (uint32_t)p->passes.size();
-            p->gate_pos[gi] = (uint32_t)pend.size();  // slot after this gate
-            p->gate_a[gi] = g.a;
-            p->gate_q0[gi] = g.q[0];
-            p->gate_q1[gi] = g.a == 2 ? g.q[1] : g.q[0];
+            rem.swap(left);
+            if (!rem.empty() && nl == kLaneBits && n > nl) {
+                // the logical qubits the next gates change, in order of need
+                std::vector<uint32_t> need;
+                uint32_t needm = 0;
+                for (uint32_t gi : rem) {
+                    const Gate &g = c->gates[gi];
+                    if (swp[gi]) continue;
+                    const uint32_t chl = changed_mask(g, cls[gi], ctl[gi]);
+                    for (uint32_t q = 0; q < g.a; q++)
+                        if (((chl >> g.q[q]) & 1u) && !((needm >> g.q[q]) & 1u)) {
+                            needm |= 1u << g.q[q];
+                            need.push_back(g.q[q]);
+                        }
+                    if (need.size() >= nl + nr_max) break;
+                }
+                if (need.size() > nl + nr_max) need.resize(nl + nr_max);
+                needm = 0;
+                for (uint32_t q : need) needm |= 1u << q;
+                // spare register slots hold needed qubits, which may move to lanes
+                for (uint32_t q : need)
+                    if ((uint32_t)__builtin_popcount(pend_regs) < nr_max && lay[q] >= nl) pend_regs |= 1u << lay[q];
+                std::vector<uint32_t> in, out;
+                for (uint32_t q : need)
+                    if (lay[q] >= nl && ((pend_regs >> lay[q]) & 1u)) in.push_back(q);
+                for (uint32_t pl = 0; pl < nl; pl++)
+                    if (!((needm >> inv[pl]) & 1u)) out.push_back(inv[pl]);
+                const size_t k = std::min(in.size(), out.size());
+                for (size_t i = 0; i < k && pend.size() < 60000; i++) {
+                    const uint32_t pr = lay[in[i]], pl = lay[out[i]];
+                    PendingGate pg{kNoGate, GC_DENSE2, 0, {pl, pr}};
+                    pend.push_back(pg);
+                    pend_cost += lane_swap_cost;
+                    swap_pos(pl, pr);
+                }
+            }
+            emit();
         }
-        (void)run_terms;
-        emit();
         lv.pass_count = (uint32_t)p->passes.size() - lv.pass_begin;
         p->levels.push_back(lv);
+    }
+    p->lay_final = lay;
+    {
+        // sampling partial sums: chunks of 2^c physically consecutive
+        // amplitudes, one partial per block the chunk touches
+        const uint32_t cbits = std::min(n, 12u);
+        uint32_t cmask = 0;
+        for (uint32_t q = p->sample_b; q < n; q++) cmask |= 1u << lay[q];
+        const uint32_t kc = (uint32_t)__builtin_popcount(cmask & ((1u << cbits) - 1u));
+        p->part_log = n - cbits + kc;
     }
     if (p->passes.size() >= (1u << 16)) {
         delete p;

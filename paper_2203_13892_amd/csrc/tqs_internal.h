@@ -157,6 +157,10 @@ struct tqs_plan {
     // gate slot inside that pass after which it acts
     std::vector<uint32_t> gate_pass, gate_pos;
     std::vector<uint32_t> gate_q0, gate_q1, gate_a;  // physical qubits per gate
+    // physical position of each logical qubit once the last level has run
+    // (swap gates and the planner's lane exchanges permute positions)
+    std::vector<uint32_t> lay_final;
+    uint32_t part_log = 0;  // log2 of the sampling partial sums per state
     std::vector<uint32_t> chunk;  // live states per level
     uint32_t sample_b = 12;
     std::vector<void *> events;  // hipEvent_t pool for run statistics

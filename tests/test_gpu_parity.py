@@ -164,6 +164,31 @@ def test_outcomes_all_leaves_c64_small(T):
     assert nb <= 3
 
 
+@pytest.mark.parametrize("n,blog", [(7, 8), (9, 8), (13, 12), (14, 8), (16, 12)])
+def test_sampling_under_permuted_positions(T, n, blog):
+    # swap gates only relabel positions, so the final state sits in memory
+    # with logical qubits at permuted bit positions (a reversal, then seeded
+    # random swaps); sampling and read-out still run in logical order
+    rng = np.random.default_rng(31 * n + blog)
+    wc = W.Circuit(n)
+    for q in range(n):
+        wc.add((q,), W.haar_unitary(2, rng))
+    for q in range(n - 1):
+        wc.add((q, q + 1), W.haar_unitary(4, rng))
+    for i in range(n // 2):
+        wc.add((i, n - 1 - i), W.swap())
+    for _ in range(2 * n):
+        a, b = [int(x) for x in rng.choice(n, 2, replace=False)]
+        wc.add((a, b), W.swap())
+    wc.add((0,), W.haar_unitary(2, rng))
+    wc = wc.with_depolarizing(1e-2, 5e-2)
+    tree = ([24], [0, len(wc)])
+    out, amps, oout, ost, onz = run_both(T, wc, tree, 3, "c64", np.arange(24),
+                                         tuning={"sample_block_log": blog})
+    assert np.max(np.abs(amps - ost)) < TOL["c64"]
+    check_outcomes(out, oout, ost, onz.leaf_u, DELTA["c64"])
+
+
 @pytest.mark.parametrize("family", ["qft", "bw"])
 def test_c2_20q_tree_sampled_leaves(T, family):
     # 20 qubits, 16384 leaves of the (16, 32, 32) tree, complex64; the

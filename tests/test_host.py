@@ -173,4 +173,18 @@ def test_plan_passes_respect_tile_capacity():
     p12 = T.Plan(c, tree, tuning={"tile_qubits": 12, "pass_cost": big}).info(0)
     assert p12["passes_level"] <= p10["passes_level"]
     p1 = T.Plan(c, tree, tuning={"max_ops_per_pass": 1}).info(0)
-    assert p1["passes_level"] == len(wc)
+    # swap gates relabel qubit positions and take no pass of their own
+    n_swap = sum(1 for q, m, _ in wc.gates if len(q) == 2 and np.array_equal(m, W.swap()))
+    assert n_swap == 10
+    assert p1["passes_level"] == len(wc) - n_swap
+
+
+def test_swap_gates_take_no_pass():
+    # a level made of swaps only still has its one (copy) pass
+    wc = W.Circuit(12)
+    for i in range(6):
+        wc.add((i, 11 - i), W.swap())
+    wc = wc.with_depolarizing(1e-3, 1e-2)
+    c = T.Circuit.from_workload(wc)
+    assert T.Plan(c, ([8], [0, len(wc)])).info(0)["passes_level"] == 1
+    assert T.Plan(c, ([2, 2], [0, 3, len(wc)])).info(1)["passes_level"] == 1
