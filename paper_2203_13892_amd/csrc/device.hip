@@ -33,10 +33,14 @@ __device__ __forceinline__ cplx<R> cmul(cplx<R> a, cplx<R> b) {
     return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
 }
 
+// acc + a b as four fused multiply-adds (each product term accumulates
+// directly; no separate product and add)
 template <typename R>
 __device__ __forceinline__ cplx<R> cmac(cplx<R> acc, cplx<R> a, cplx<R> b) {
-    acc.re += a.re * b.re - a.im * b.im;
-    acc.im += a.re * b.im + a.im * b.re;
+    acc.re = acc.re + a.re * b.re;
+    acc.re = acc.re - a.im * b.im;
+    acc.im = acc.im + a.re * b.im;
+    acc.im = acc.im + a.im * b.re;
     return acc;
 }
 

@@ -60,22 +60,13 @@ __device__ __forceinline__ cplx<R> rmac(cplx<R> acc, cplx<R> m, cplx<R> x) {
     return {acc.re + m.re * x.re, acc.im + m.re * x.im};
 }
 
-// Bounds how many cross-lane exchanges the scheduler keeps in flight (each
-// holds result registers until consumed): a fence after every 4th index.
+// Bounds how much independent work the scheduler hoists ahead of its use
+// (cross-lane exchanges, products): each hoisted result holds registers until
+// consumed, and the tile already fills most of them.  A fence after every
+// 4th register index.
 template <int J>
 __device__ __forceinline__ void shuffle_fence() {
     if constexpr ((J & 3) == 3) __builtin_amdgcn_sched_barrier(0);
-}
-
-// Value of lane `lane` (a compile-time constant) broadcast to the wave.
-__device__ __forceinline__ float bcast_lane(float x, int lane) {
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), lane));
-}
-__device__ __forceinline__ double bcast_lane(double x, int lane) {
-    const long long b = __double_as_longlong(x);
-    const int lo = __builtin_amdgcn_readlane((int)(b & 0xFFFFFFFFll), lane);
-    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
 // e^{2 pi i t} for fixed-point turns t: the nearest of 256 table points
@@ -192,6 +183,7 @@ __device__ __forceinline__ void d1_reg_ctrl(cplx<R> (&v)[1 << RB], const cplx<R>
             v[j] = mmac<REAL>(mmul<REAL>(m0, x0), m1, x1);
             v[j | (1 << I)] = mmac<REAL>(mmul<REAL>(m2, x0), m3, x1);
         }
+        shuffle_fence<j>();
     });
 }
 
@@ -297,6 +289,7 @@ __device__ __forceinline__ void dense2_rr(cplx<R> (&v)[1 << RB], const cplx<R> (
             v[i2] = cmac(cmac(cmac(cmul(M[8], x0), M[9], x1), M[10], x2), M[11], x3);
             v[i3] = cmac(cmac(cmac(cmul(M[12], x0), M[13], x1), M[14], x2), M[15], x3);
         }
+        shuffle_fence<j>();
     });
 }
 
@@ -536,41 +529,58 @@ __device__ __forceinline__ void op_diag_run(cplx<R> (&v)[1 << RB], const OpDesc 
             }
         }
     });
-    // subset products over the low and high register bits
-    cplx<R> wlo[1 << LO], whi[1 << HI];
-    wlo[0] = expi_turns(C, expt);
-    sfor<LO>([&](auto Ic) __attribute__((always_inline)) {
-        constexpr int i = decltype(Ic)::value;
-        const cplx<R> e = expi_turns(lam[i], expt);
-        sfor<(1 << i)>([&](auto Sc) __attribute__((always_inline)) {
-            constexpr int s = decltype(Sc)::value;
-            wlo[s | (1 << i)] = cmul(wlo[s], e);
-        });
-    });
-    whi[0] = cplx<R>{R(1), R(0)};
-    sfor<HI>([&](auto Ic) __attribute__((always_inline)) {
-        constexpr int i = decltype(Ic)::value;
-        const cplx<R> e = expi_turns(lam[LO + i], expt);
-        sfor<(1 << i)>([&](auto Sc) __attribute__((always_inline)) {
-            constexpr int s = decltype(Sc)::value;
-            whi[s | (1 << i)] = cmul(whi[s], e);
-        });
-    });
-    if (o.has_t) {
-        // lane l holds table entry l ^ f_reg; register index j reads it from lane j
-        const uint32_t tl = L & (NJ - 1);
-        const cplx<R> tv = T[(tl ^ fr) & ((1u << pd->nr) - 1u)];
+    const uint32_t lm = o.lam_mask;
+    if (__builtin_popcount(lm) <= 2) {
+        // few register-dependent factors: e^{2 pi i C}, then e^{2 pi i lam_i}
+        // on the registers with bit i set
+        const cplx<R> w0 = expi_turns(C, expt);
         sfor<NJ>([&](auto Jc) __attribute__((always_inline)) {
             constexpr int j = decltype(Jc)::value;
-            const cplx<R> t = {bcast_lane(tv.re, j), bcast_lane(tv.im, j)};
-            const cplx<R> w = cmul(cmul(wlo[j & ((1 << LO) - 1)], whi[j >> LO]), t);
-            v[j] = cmul(w, v[j]);
+            v[j] = cmul(w0, v[j]);
+        });
+        sfor<RB>([&](auto Ic) __attribute__((always_inline)) {
+            constexpr int i = decltype(Ic)::value;
+            if ((lm >> i) & 1u) {
+                const cplx<R> e = expi_turns(lam[i], expt);
+                sfor<NJ>([&](auto Jc) __attribute__((always_inline)) {
+                    constexpr int j = decltype(Jc)::value;
+                    if constexpr (((j >> i) & 1) != 0) v[j] = cmul(e, v[j]);
+                });
+            }
         });
     } else {
+        // subset products over the low and high register bits
+        cplx<R> wlo[1 << LO], whi[1 << HI];
+        wlo[0] = expi_turns(C, expt);
+        sfor<LO>([&](auto Ic) __attribute__((always_inline)) {
+            constexpr int i = decltype(Ic)::value;
+            const cplx<R> e = expi_turns(lam[i], expt);
+            sfor<(1 << i)>([&](auto Sc) __attribute__((always_inline)) {
+                constexpr int s = decltype(Sc)::value;
+                wlo[s | (1 << i)] = cmul(wlo[s], e);
+            });
+        });
+        whi[0] = cplx<R>{R(1), R(0)};
+        sfor<HI>([&](auto Ic) __attribute__((always_inline)) {
+            constexpr int i = decltype(Ic)::value;
+            const cplx<R> e = expi_turns(lam[LO + i], expt);
+            sfor<(1 << i)>([&](auto Sc) __attribute__((always_inline)) {
+                constexpr int s = decltype(Sc)::value;
+                whi[s | (1 << i)] = cmul(whi[s], e);
+            });
+        });
         sfor<NJ>([&](auto Jc) __attribute__((always_inline)) {
             constexpr int j = decltype(Jc)::value;
             const cplx<R> w = HI ? cmul(wlo[j & ((1 << LO) - 1)], whi[j >> LO]) : wlo[j & ((1 << LO) - 1)];
             v[j] = cmul(w, v[j]);
+        });
+    }
+    if (o.has_t) {
+        // register-only gates: one wave-uniform factor per register index
+        const uint32_t msk = (1u << pd->nr) - 1u;
+        sfor<NJ>([&](auto Jc) __attribute__((always_inline)) {
+            constexpr int j = decltype(Jc)::value;
+            v[j] = cmul(T[((uint32_t)j ^ fr) & msk], v[j]);
         });
     }
 }
@@ -578,8 +588,16 @@ __device__ __forceinline__ void op_diag_run(cplx<R> (&v)[1 << RB], const OpDesc 
 // ------------------------------------------------------------------ kernel --
 // D2: the pass contains 4x4 ops (a separate instantiation keeps the
 // register budget of the common passes small).
+// Waves per SIMD the register allocator is held to: three for the
+// complex64 tiles of up to 32 amplitudes per lane (at most 168 registers),
+// no bound for the larger tiles, whose registers hold the tile itself.
+template <typename R, int RB>
+struct PassWaves {
+    static constexpr int value = (sizeof(R) == 4 && RB <= 5) ? 3 : 1;
+};
+
 template <typename R, int RB, bool D2>
-__global__ __launch_bounds__(64) void pass_kernel(PassArgs<R> a) {
+__global__ __launch_bounds__(64, (PassWaves<R, RB>::value)) void pass_kernel(PassArgs<R> a) {
     constexpr int NJ = 1 << RB;
     const uint32_t nwg = gridDim.x, bid = blockIdx.x;
     const uint32_t w = (bid & 7u) * (nwg >> 3) + (bid >> 3);

@@ -139,7 +139,7 @@ extern "C" tqs_status tqs_plan_create(const tqs_circuit *c, const tqs_tree *tree
     if (!tu.max_ops_per_pass) tu.max_ops_per_pass = 1024;
     if (!tu.chunk_states) tu.chunk_states = 256;
     if (!tu.sample_block_log) tu.sample_block_log = 12;
-    if (!tu.pass_cost) tu.pass_cost = 240;
+    if (!tu.pass_cost) tu.pass_cost = 480;
     const uint32_t tmax = prec == TQS_C64 ? 12 : 11;
     if (tu.tile_qubits < 10 || tu.tile_qubits > tmax)
         return fail(TQS_E_ARG, "tile_qubits must be in 10..%u at this precision", tmax);
@@ -316,6 +316,9 @@ extern "C" tqs_status tqs_plan_create(const tqs_circuit *c, const tqs_tree *tree
                     }
                 }
                 o.has_t = has_t ? 1 : 0;
+                o.lam_mask = 0;
+                for (uint32_t b = 0; b < kMaxRegBits; b++)
+                    if (!g_fixreg[b].empty() || !g_lanereg[b].empty()) o.lam_mask |= (uint8_t)(1u << b);
                 o.n_fix = (uint16_t)g_fix.size();
                 o.n_lane = (uint16_t)g_lane.size();
                 for (const DiagTerm &tm : g_fix) p->terms.push_back(tm);

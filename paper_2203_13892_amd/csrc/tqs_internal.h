@@ -75,7 +75,7 @@ struct OpDesc {
     uint8_t tq;        // OP_DENSE1 with nq == 2: gate qubit that is the target
     uint8_t real;      // DENSE1/DENSE2: every matrix entry is real
     uint8_t has_t;     // DIAGRUN: the register-qubit table is not all ones
-    uint8_t pad;
+    uint8_t lam_mask;  // DIAGRUN: register bits that fixed+register or lane+register terms touch
     uint16_t slot0, slot1;  // gate slots [slot0, slot1) of the pass covered by the op
     uint32_t mat;      // DENSE1/DENSE2: matrix offset; DIAGRUN: table offset (2^nr entries)
     uint32_t terms;    // DIAGRUN: first term touching a non-register qubit
