@@ -143,6 +143,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--no-dcp", action="store_true",
+                    help="skip the copy-cost measurement and the DCP-shaped form")
     ap.add_argument("--forms", default="tree,pershot,tree4a,tree4b")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--tile", type=int, default=0, help="tile qubits (0 = library default)")
@@ -178,15 +180,16 @@ def main():
     # state copy in gate-equivalents on this GPU (the DCP copy-cost input):
     # one state's read + write at the streaming-copy rate, against the average
     # time per gate execution of a per-shot run
-    copy_gbps = T.probe_copy(1 << 30, 10)
-    copy_us = 2 * 8 * (1 << 20) / (copy_gbps * 1e3)
-    sps_ps, _, agg_ps, _ = time_form(T, torch, circuit, forms["pershot"], args.seed, 1, 1)
-    gate_us = agg_ps["ms_passes"] * 1e3 / (shots * G)
-    copy_cost = copy_us / gate_us
-    dcp_shape = T.dcp(circuit, shots, 1.96, 0.01, copy_cost, 8)
-    forms["dcp"] = dcp_shape
-    if "dcp" not in args.forms.split(","):
-        args.forms += ",dcp"
+    if not args.no_dcp:
+        copy_gbps = T.probe_copy(1 << 30, 10)
+        copy_us = 2 * 8 * (1 << 20) / (copy_gbps * 1e3)
+        sps_ps, _, agg_ps, _ = time_form(T, torch, circuit, forms["pershot"], args.seed, 1, 1)
+        gate_us = agg_ps["ms_passes"] * 1e3 / (shots * G)
+        copy_cost = copy_us / gate_us
+        dcp_shape = T.dcp(circuit, shots, 1.96, 0.01, copy_cost, 8)
+        forms["dcp"] = dcp_shape
+        if "dcp" not in args.forms.split(","):
+            args.forms += ",dcp"
     results = {}
     for name in args.forms.split(","):
         tree = forms[name]
@@ -234,10 +237,11 @@ def main():
     }
     if "pershot" in results and head != "pershot":
         line["tree_speedup_vs_pershot"] = h["shots_per_s"] / results["pershot"]["shots_per_s"]
-    line["copy_cost_gates"] = copy_cost
-    line["copy_GBps"] = copy_gbps
-    line["dcp"] = {"tree": dcp_shape[0], "cut": dcp_shape[1], "z": 1.96, "eps": 0.01,
-                   "copy_cost_gates": copy_cost}
+    if not args.no_dcp:
+        line["copy_cost_gates"] = copy_cost
+        line["copy_GBps"] = copy_gbps
+        line["dcp"] = {"tree": dcp_shape[0], "cut": dcp_shape[1], "z": 1.96, "eps": 0.01,
+                       "copy_cost_gates": copy_cost}
     if args.fidelity:
         line["fidelity_loss"] = fidelity_loss(T, W, torch, args.fid_seeds)
     if not args.no_cpu:

@@ -88,53 +88,74 @@ struct SampleMap {
     uint8_t lay[32];    // logical qubit -> physical position
 };
 
-// Partial masses: one workgroup per (state, chunk).  Inside a chunk the
-// amplitude at offset o belongs to the block spelled by o's block-bit
-// positions; o goes to LDS slot (pext(o, block bits) << sbits) | pext(o,
-// other bits), and each run of 2^sbits slots is summed pairwise.
+// Partial masses: one workgroup per (state, chunk).  Thread t reads the
+// chunk offsets o = t + 256 q (coalesced), so the offset's low 8 bits are the
+// thread's and its high bits are q.  Each thread first adds, in registers,
+// its values whose q differ only in non-block positions; the remaining
+// values go to LDS at (block part of o, then the thread's non-block bits),
+// and each run of threads that share a block part is summed pairwise.
 template <typename R>
 __global__ __launch_bounds__(kThreads) void block_partials_kernel(const cplx<R> *states, uint64_t slot_amps,
                                                                   const uint32_t *slots, SampleMap m,
                                                                   double *part) {
-    __shared__ double buf[1u << 12];
-    __shared__ uint32_t tab[2][64];
+    constexpr uint32_t kQ = 16;  // values per thread (chunk of at most 4096)
+    __shared__ double buf[kThreads * kQ];
     const uint32_t nch = 1u << (m.n - m.c);
     const uint32_t k = blockIdx.x / nch, ch = blockIdx.x % nch;
-    const uint32_t cl = (1u << m.c) - 1u;
-    const uint32_t cm = m.cmask & cl;
-    const uint32_t sbits = m.c - m.kc;
-    if (threadIdx.x < 128) {
-        const uint32_t h = threadIdx.x >> 6;
-        const uint32_t v = (threadIdx.x & 63u) << (6 * h);
-        uint32_t ci = 0, si = 0, nc = 0, ns = 0;
-        for (uint32_t bit = 0; bit < m.c; bit++) {
-            const uint32_t one = (v >> bit) & 1u;
-            if ((cm >> bit) & 1u) {
-                ci |= one << nc;
-                nc++;
-            } else {
-                si |= one << ns;
-                ns++;
+    const uint32_t t = threadIdx.x;
+    const uint32_t tb = m.c < 8 ? m.c : 8u, qb = m.c - tb;
+    const uint32_t cm = m.cmask & ((1u << m.c) - 1u);
+    const uint32_t cm_t = cm & ((1u << tb) - 1u), cm_q = cm >> tb;
+    const uint32_t ct_bits = (uint32_t)__builtin_popcount(cm_t);
+    const uint32_t st = tb - ct_bits;  // the thread's non-block bits
+    uint32_t ct = 0, stt = 0;
+    for (uint32_t bit = 0, nc = 0, ns = 0; bit < tb; bit++) {
+        const uint32_t one = (t >> bit) & 1u;
+        if ((cm_t >> bit) & 1u) ct |= one << nc++;
+        else stt |= one << ns++;
+    }
+    const bool active = t < (1u << tb);
+    const cplx<R> *s = states + (uint64_t)slots[k] * slot_amps + ((uint64_t)ch << m.c);
+    // (selects, not branches, keep the 16 values in fixed registers)
+    double acc[kQ];
+#pragma unroll
+    for (uint32_t q = 0; q < kQ; q++) {
+        const bool live = active && q < (1u << qb);
+        const cplx<R> v = s[live ? t + (q << tb) : 0u];
+        const double a2 = (double)v.re * (double)v.re + (double)v.im * (double)v.im;
+        acc[q] = live ? a2 : 0.0;
+    }
+#pragma unroll
+    for (uint32_t b = 0; b < 4; b++) {
+        const bool on = b < qb && !((cm_q >> b) & 1u);
+#pragma unroll
+        for (uint32_t q = 0; q < kQ; q++)
+            if (!(q & (1u << b))) acc[q] += on ? acc[q | (1u << b)] : 0.0;
+    }
+    // values left: q with every non-block bit clear
+    const uint32_t sq = ((1u << qb) - 1u) & ~cm_q;
+    if (active) {
+#pragma unroll
+        for (uint32_t q = 0; q < kQ; q++) {
+            if (q < (1u << qb) && (q & sq) == 0) {
+                uint32_t cq = 0;
+                for (uint32_t bit = 0, nc = 0; bit < qb; bit++)
+                    if ((cm_q >> bit) & 1u) cq |= ((q >> bit) & 1u) << nc++;
+                buf[((((cq << ct_bits) | ct)) << st) | stt] = acc[q];
             }
         }
-        tab[h][threadIdx.x & 63u] = (ci << sbits) | si;
     }
     __syncthreads();
-    const cplx<R> *s = states + (uint64_t)slots[k] * slot_amps + ((uint64_t)ch << m.c);
-    for (uint32_t i = threadIdx.x; i <= cl; i += kThreads) {
-        const cplx<R> v = s[i];
-        buf[tab[0][i & 63u] | tab[1][(i >> 6) & 63u]] = (double)v.re * (double)v.re + (double)v.im * (double)v.im;
-    }
-    __syncthreads();
-    for (uint32_t h = 1; h < (1u << sbits); h <<= 1) {
-        for (uint32_t i = threadIdx.x; i < ((1u << m.c) >> 1) / h; i += kThreads) {
+    const uint32_t nvals = 1u << (m.kc + st);
+    for (uint32_t h = 1; h < (1u << st); h <<= 1) {
+        for (uint32_t i = t; i < (nvals >> 1) / h; i += kThreads) {
             const uint32_t e = i * 2 * h;
             buf[e] += buf[e + h];
         }
         __syncthreads();
     }
     double *out = part + ((uint64_t)k << m.part_log) + ((uint64_t)ch << m.kc);
-    for (uint32_t j = threadIdx.x; j < (1u << m.kc); j += kThreads) out[j] = buf[j << sbits];
+    for (uint32_t j = t; j < (1u << m.kc); j += kThreads) out[j] = buf[j << st];
 }
 
 // Block masses in logical block order: block B's amplitudes lie in the

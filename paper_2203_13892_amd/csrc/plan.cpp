@@ -137,7 +137,11 @@ extern "C" tqs_status tqs_plan_create(const tqs_circuit *c, const tqs_tree *tree
     if (tuning) tu = *tuning;
     if (!tu.tile_qubits) tu.tile_qubits = prec == TQS_C64 ? 11 : 10;
     if (!tu.max_ops_per_pass) tu.max_ops_per_pass = 1024;
-    if (!tu.chunk_states) tu.chunk_states = 256;
+    if (!tu.chunk_states) {
+        // launches of about 4 GiB of states keep every compute unit busy
+        const uint64_t state_bytes = (uint64_t)(prec == TQS_C64 ? 8 : 16) << c->n;
+        tu.chunk_states = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(512, (4ull << 30) / state_bytes));
+    }
     if (!tu.sample_block_log) tu.sample_block_log = 12;
     if (!tu.pass_cost) tu.pass_cost = 480;
     const uint32_t tmax = prec == TQS_C64 ? 12 : 11;
