@@ -153,6 +153,8 @@ def main():
     ap.add_argument("--fidelity", action="store_true",
                     help="also report the tree's fidelity loss against per-shot sampling")
     ap.add_argument("--fid-seeds", type=int, default=10)
+    ap.add_argument("--no-bw", action="store_true",
+                    help="skip the 20-qubit brick-wall forms (reported beside the QFT ones)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -242,6 +244,21 @@ def main():
         line["copy_GBps"] = copy_gbps
         line["dcp"] = {"tree": dcp_shape[0], "cut": dcp_shape[1], "z": 1.96, "eps": 0.01,
                        "copy_cost_gates": copy_cost}
+    if not args.no_bw:
+        # the same noise model on a 20-qubit depth-20 brick-wall of Haar SU(4)
+        # gates (circuit seed 1): per-shot against tree reuse
+        bw = W.brickwall(20, 20, seed=1).with_depolarizing(1e-3, 1e-2)
+        Gb = len(bw)
+        cb = T.Circuit.from_workload(bw)
+        line["brickwall"] = {"workload": "brickwall20 d20 seed 1, depolarizing(1e-3,1e-2) 16384 shots",
+                             "gates": Gb, "forms": {}}
+        for name, tree in (("pershot", ([shots], [0, Gb])), ("tree", ([16, 32, 32], equal_cuts(Gb, 3))),
+                           ("tree4b", ([8, 8, 16, 16], equal_cuts(Gb, 4)))):
+            sps, ms, agg, _ = time_form(T, torch, cb, tree, args.seed, args.steps, args.warmup)
+            line["brickwall"]["forms"][name] = {
+                "shots_per_s": sps, "ms_per_step": ms, "shape": tree[0],
+                "pass_GBps": agg["bytes_passes"] / (agg["ms_passes"] * 1e-3) / 1e9}
+            print("# brickwall %s: %.1f shots/s, %.2f ms/step" % (name, sps, ms), file=sys.stderr, flush=True)
     if args.fidelity:
         line["fidelity_loss"] = fidelity_loss(T, W, torch, args.fid_seeds)
     if not args.no_cpu:

@@ -57,6 +57,20 @@ __device__ __forceinline__ cplx<R> cneg_if(cplx<R> a, uint32_t neg) {
     }
 }
 
+// Negates the real and/or imaginary part (integer sign flips).
+template <typename R>
+__device__ __forceinline__ cplx<R> cneg_parts(cplx<R> a, uint32_t neg_re, uint32_t neg_im) {
+    if constexpr (sizeof(R) == 4) {
+        return {__uint_as_float(__float_as_uint(a.re) ^ (neg_re << 31)),
+                __uint_as_float(__float_as_uint(a.im) ^ (neg_im << 31))};
+    } else {
+        return {__longlong_as_double((long long)((unsigned long long)__double_as_longlong(a.re) ^
+                                                 ((unsigned long long)neg_re << 63))),
+                __longlong_as_double((long long)((unsigned long long)__double_as_longlong(a.im) ^
+                                                 ((unsigned long long)neg_im << 63)))};
+    }
+}
+
 // Per-node noise metadata in device memory.
 struct NodeMeta {
     const uint32_t *frame0;  // [2 * node]: x, z at node start
@@ -375,7 +389,7 @@ struct Layout {
     uint32_t slots_total;
     std::vector<uint32_t> slot_base;  // per level
     uint32_t scratch_slot;
-    uint64_t off_meta, off_mats, off_ops, off_passes, off_terms, off_dgates, off_expt, off_frame0, off_evoff,
+    uint64_t off_meta, off_mats, off_ops, off_passes, off_terms, off_dgates, off_frame0, off_evoff,
         off_evpos, off_evdx, off_evdz, off_leafu, off_leaffx, off_sched, off_sums, off_part, off_out, total;
     uint64_t n_sched;
 };
@@ -403,8 +417,6 @@ static Layout make_layout(const tqs_plan *p, uint64_t n_events, uint64_t n_leave
     o = align256(o + p->terms.size() * sizeof(DiagTerm));
     L.off_dgates = o;
     o = align256(o + p->dgates.size() * sizeof(DiagGate));
-    L.off_expt = o;
-    o = align256(o + 256 * L.amp_bytes);
     L.off_frame0 = o;
     o = align256(o + p->n_nodes * 8);
     L.off_evoff = o;
@@ -577,7 +589,6 @@ static void launch_pass(const tqs_plan *p, const Layout &Ly, unsigned char *ws, 
     a.meta.ev_dz = reinterpret_cast<const uint32_t *>(ws + Ly.off_evdz);
     a.terms = reinterpret_cast<const DiagTerm *>(ws + Ly.off_terms);
     a.dgates = reinterpret_cast<const DiagGate *>(ws + Ly.off_dgates);
-    a.expt = reinterpret_cast<const cplx<R> *>(ws + Ly.off_expt);
     const uint32_t grid = (a.work + 7u) & ~7u;
     // one wave per workgroup; the register-qubit count is a compile-time tile width
     const bool d2 = pd.has_d2 != 0;
@@ -715,15 +726,6 @@ static tqs_status run_t(tqs_plan *p, const tqs_noise *nz, unsigned char *ws, uin
     put(Ly.off_passes, p->passes.data(), p->passes.size() * sizeof(PassDesc));
     put(Ly.off_terms, p->terms.data(), p->terms.size() * sizeof(DiagTerm));
     put(Ly.off_dgates, p->dgates.data(), p->dgates.size() * sizeof(DiagGate));
-    {
-        // e^{2 pi i k / 256} for the phase-run exponentials
-        std::vector<cplx<R>> et(256);
-        for (int k = 0; k < 256; k++) {
-            const double ang = 2.0 * 3.14159265358979323846 * k / 256.0;
-            et[k] = {(R)std::cos(ang), (R)std::sin(ang)};
-        }
-        put(Ly.off_expt, et.data(), et.size() * sizeof(cplx<R>));
-    }
     put(Ly.off_frame0, hm.frame0.data(), hm.frame0.size() * 4);
     put(Ly.off_evoff, hm.ev_off.data(), hm.ev_off.size() * 4);
     put(Ly.off_evpos, hm.ev_pos.data(), hm.ev_pos.size() * 4);

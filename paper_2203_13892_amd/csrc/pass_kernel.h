@@ -16,10 +16,77 @@
 // slots of the pass.
 #pragma once
 
+#include <cstddef>
 #include <type_traits>
 #include <utility>
 
 namespace tqs {
+
+// Read-only pass data (descriptors, matrices, phase terms, noise metadata)
+// is read through constant-address-space pointers: the compiler may then use
+// scalar loads for wave-uniform addresses, since nothing the kernel writes
+// can alias them.
+#if defined(__HIP_DEVICE_COMPILE__)
+template <typename T>
+using kptr = const __attribute__((address_space(4))) T *;
+#else
+template <typename T>
+using kptr = const T *;  // host pass: kernel bodies are only parsed there
+#endif
+template <typename T>
+__device__ __forceinline__ kptr<T> kconst(const T *p) {
+    return (kptr<T>)p;
+}
+
+// Copy of a read-only record, dword by dword (wave-uniform address: scalar
+// loads).
+template <typename T>
+__device__ __forceinline__ T kload(kptr<T> p) {
+    static_assert(sizeof(T) % 4 == 0, "record of whole dwords");
+    T out;
+    uint32_t *d = reinterpret_cast<uint32_t *>(&out);
+    const kptr<uint32_t> w = (kptr<uint32_t>)p;
+#pragma unroll
+    for (uint32_t i = 0; i < sizeof(T) / 4; i++) d[i] = w[i];
+    return out;
+}
+
+// A wave-uniform value, kept in a scalar register: a per-lane select between
+// two such values stays a register select (and is not turned into a per-lane
+// load from a selected address).
+__device__ __forceinline__ uint32_t uni(uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)x);
+}
+__device__ __forceinline__ uint64_t uni(uint64_t x) {
+    const uint32_t lo = uni((uint32_t)x), hi = uni((uint32_t)(x >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// A phase term read as whole dwords (scalar loads cannot read bytes): its
+// arity, the role of its second qubit, its physical qubits and its four
+// phases in the accumulator width A.
+template <typename A>
+struct TermU {
+    uint32_t nq, role1, phys0, phys1;
+    A th[4];
+};
+template <typename A>
+__device__ __forceinline__ TermU<A> load_term(kptr<DiagTerm> p) {
+    static_assert(sizeof(DiagTerm) == 40, "phase term layout");
+    const kptr<uint32_t> w = (kptr<uint32_t>)p;
+    const uint32_t w0 = uni(w[0]), w1 = uni(w[1]);
+    TermU<A> t;
+    t.nq = w0 & 0xFFu;
+    t.role1 = (w0 >> 16) & 0xFFu;
+    t.phys0 = (w1 >> 8) & 0xFFu;
+    t.phys1 = (w1 >> 16) & 0xFFu;
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+        if constexpr (sizeof(A) == 4) t.th[r] = uni(w[2 + 2 * r]);
+        else t.th[r] = uni((uint64_t)w[2 + 2 * r] | ((uint64_t)w[3 + 2 * r] << 32));
+    }
+    return t;
+}
 
 template <typename R>
 struct PassArgs {
@@ -36,7 +103,6 @@ struct PassArgs {
     const cplx<R> *mats;
     const DiagTerm *terms;
     const DiagGate *dgates;
-    const cplx<R> *expt;  // e^{2 pi i k / 256}, k = 0..255
     NodeMeta meta;
 };
 
@@ -69,28 +135,62 @@ __device__ __forceinline__ void shuffle_fence() {
     if constexpr ((J & 3) == 3) __builtin_amdgcn_sched_barrier(0);
 }
 
-// e^{2 pi i t} for fixed-point turns t: the nearest of 256 table points
-// times the Taylor series of the remaining angle |x| <= pi / 256 (truncation
-// error below 3e-12 in single, 1e-22 in double precision).
-__device__ __forceinline__ cplx<float> expi_turns(uint32_t t, const cplx<float> *tab) {
-    const uint32_t k = ((t + (1u << 23)) >> 24) & 255u;
-    const int32_t r = (int32_t)(t - (k << 24));
+// e^{2 pi i t} for fixed-point turns t, from arithmetic only (no table, so
+// no memory latency inside a phase run): t = q/4 + r with q the nearest
+// quarter turn and |r| <= 1/8 turn; the Taylor series of cos and sin at
+// x = 2 pi r (|x| <= pi/4) to x^10 / x^9 in single precision (truncation
+// below 2e-9) and to x^18 / x^17 in double (below 1e-19); then the quarter
+// turn i^q swaps and negates the two parts.
+__device__ __forceinline__ cplx<float> expi_turns(uint32_t t) {
+    const uint32_t q = ((t + (1u << 29)) >> 30) & 3u;
+    const int32_t r = (int32_t)(t - (q << 30));
     const float x = (float)r * 1.4629180792671596e-09f;  // 2 pi / 2^32
     const float x2 = x * x;
-    const float s = x * (1.0f - x2 * (1.0f / 6.0f));
-    const float c = 1.0f - x2 * (0.5f - x2 * (1.0f / 24.0f));
-    const cplx<float> e = tab[k];
-    return {e.re * c - e.im * s, e.re * s + e.im * c};
+    float ps = 1.0f / 362880.0f;
+    ps = ps * x2 - 1.0f / 5040.0f;
+    ps = ps * x2 + 1.0f / 120.0f;
+    ps = ps * x2 - 1.0f / 6.0f;
+    ps = ps * x2 + 1.0f;
+    float pc = -1.0f / 3628800.0f;
+    pc = pc * x2 + 1.0f / 40320.0f;
+    pc = pc * x2 - 1.0f / 720.0f;
+    pc = pc * x2 + 1.0f / 24.0f;
+    pc = pc * x2 - 0.5f;
+    pc = pc * x2 + 1.0f;
+    const float sn = x * ps;
+    const bool odd = (q & 1u) != 0;
+    cplx<float> e = {odd ? sn : pc, odd ? pc : sn};
+    return cneg_parts(e, ((q + 1u) >> 1) & 1u, q >> 1);
 }
-__device__ __forceinline__ cplx<double> expi_turns(uint64_t t, const cplx<double> *tab) {
-    const uint64_t k = ((t + (1ull << 55)) >> 56) & 255u;
-    const int64_t r = (int64_t)(t - (k << 56));
+__device__ __forceinline__ cplx<double> expi_turns(uint64_t t) {
+    const uint32_t q = (uint32_t)(((t + (1ull << 61)) >> 62) & 3u);
+    const int64_t r = (int64_t)(t - ((uint64_t)q << 62));
     const double x = (double)r * 3.4061215800865545e-19;  // 2 pi / 2^64
     const double x2 = x * x;
-    const double s = x * (1.0 - x2 / 6.0 * (1.0 - x2 / 20.0 * (1.0 - x2 / 42.0 * (1.0 - x2 / 72.0))));
-    const double c = 1.0 - x2 / 2.0 * (1.0 - x2 / 12.0 * (1.0 - x2 / 30.0 * (1.0 - x2 / 56.0)));
-    const cplx<double> e = tab[k];
-    return {e.re * c - e.im * s, e.re * s + e.im * c};
+    // 1/(2k+1)! and 1/(2k)! by Horner from the highest term
+    double ps = 1.0 / 355687428096000.0;            // 1/17!
+    ps = ps * x2 - 1.0 / 1307674368000.0;           // 1/15!
+    ps = ps * x2 + 1.0 / 6227020800.0;              // 1/13!
+    ps = ps * x2 - 1.0 / 39916800.0;                // 1/11!
+    ps = ps * x2 + 1.0 / 362880.0;                  // 1/9!
+    ps = ps * x2 - 1.0 / 5040.0;
+    ps = ps * x2 + 1.0 / 120.0;
+    ps = ps * x2 - 1.0 / 6.0;
+    ps = ps * x2 + 1.0;
+    double pc = 1.0 / 6402373705728000.0;           // 1/18!
+    pc = pc * x2 - 1.0 / 20922789888000.0;          // 1/16!
+    pc = pc * x2 + 1.0 / 87178291200.0;             // 1/14!
+    pc = pc * x2 - 1.0 / 479001600.0;               // 1/12!
+    pc = pc * x2 + 1.0 / 3628800.0;                 // 1/10!
+    pc = pc * x2 - 1.0 / 40320.0;
+    pc = pc * x2 + 1.0 / 720.0;
+    pc = pc * x2 - 1.0 / 24.0;
+    pc = pc * x2 + 0.5;
+    pc = 1.0 - pc * x2;
+    const double sn = x * ps;
+    const bool odd = (q & 1u) != 0;
+    cplx<double> e = {odd ? sn : pc, odd ? pc : sn};
+    return cneg_parts(e, ((q + 1u) >> 1) & 1u, q >> 1);
 }
 
 // Phase accumulator type: 32-bit turns at complex64, 64-bit at complex128.
@@ -135,7 +235,7 @@ __device__ __forceinline__ void with_reg(uint32_t i, F &&f) {
 
 // Frame-conjugated 2x2 / 4x4 entry: G[(r^x) * k + (c^x)] (-1)^{z.r + z.c}
 template <typename R>
-__device__ __forceinline__ cplx<R> conj_entry(const cplx<R> *G, uint32_t k, uint32_t r, uint32_t c,
+__device__ __forceinline__ cplx<R> conj_entry(kptr<cplx<R>> G, uint32_t k, uint32_t r, uint32_t c,
                                               uint32_t xl, uint32_t zl) {
     const cplx<R> v = G[(r ^ xl) * k + (c ^ xl)];
     return cneg_if(v, (__builtin_popcount(zl & r) + __builtin_popcount(zl & c)) & 1u);
@@ -246,7 +346,7 @@ __device__ __forceinline__ void dense1_apply(cplx<R> (&v)[1 << RB], const cplx<R
 }
 
 template <typename R, int RB>
-__device__ __forceinline__ void op_dense1(cplx<R> (&v)[1 << RB], const OpDesc &o, const cplx<R> *G,
+__device__ __forceinline__ void op_dense1(cplx<R> (&v)[1 << RB], const OpDesc &o, kptr<cplx<R>> G,
                                           uint32_t xl, uint32_t zl, uint32_t L, uint32_t base) {
     const uint32_t tq = o.nq == 2 ? o.tq : 0u, cq = 1u - tq;
     const uint32_t k = 1u << o.nq;
@@ -319,7 +419,7 @@ __device__ __forceinline__ void dense2_rr_dispatch(cplx<R> (&v)[1 << RB], const 
 }
 
 template <typename R, int RB>
-__device__ __forceinline__ void op_dense2(cplx<R> (&v)[1 << RB], const OpDesc &o, const cplx<R> *G,
+__device__ __forceinline__ void op_dense2(cplx<R> (&v)[1 << RB], const OpDesc &o, kptr<cplx<R>> G,
                                           uint32_t xl, uint32_t zl, uint32_t L) {
     constexpr int NJ = 1 << RB;
     // M[r][c] in the gate's qubit order, frame-conjugated
@@ -401,7 +501,7 @@ __device__ __forceinline__ void op_dense2(cplx<R> (&v)[1 << RB], const OpDesc &o
 // ------------------------------------------------------------ DIAG gates --
 // One diagonal gate, gate-by-gate path: d'(r) = d(r ^ x).
 template <typename R, int RB>
-__device__ __forceinline__ void op_diag_one(cplx<R> (&v)[1 << RB], const DiagGate &dg, const cplx<R> *D,
+__device__ __forceinline__ void op_diag_one(cplx<R> (&v)[1 << RB], const DiagGate &dg, kptr<cplx<R>> D,
                                             uint32_t fx, uint32_t L, uint32_t base) {
     constexpr int NJ = 1 << RB;
     uint32_t xl = (fx >> dg.phys[0]) & 1u;
@@ -443,9 +543,9 @@ __device__ __forceinline__ void op_diag_one(cplx<R> (&v)[1 << RB], const DiagGat
 // the other terms arrive grouped: fixed-only and fixed+register terms give
 // wave-uniform contributions, lane and lane+register terms per-lane ones.
 template <typename R, int RB>
-__device__ __forceinline__ void op_diag_run(cplx<R> (&v)[1 << RB], const OpDesc &o, const cplx<R> *T,
-                                            const DiagTerm *tm, const cplx<R> *expt, uint32_t fx,
-                                            uint32_t L, uint32_t base, const PassDesc *pd) {
+__device__ __forceinline__ void op_diag_run(cplx<R> (&v)[1 << RB], const OpDesc &o, kptr<cplx<R>> T,
+                                            kptr<DiagTerm> tm, uint32_t fx, uint32_t L, uint32_t base,
+                                            const uint32_t (&rq)[RB], uint32_t nr) {
     using A = typename Turns<R>::T;
     constexpr int NJ = 1 << RB;
     constexpr int LO = RB < 3 ? RB : 3;
@@ -457,12 +557,12 @@ __device__ __forceinline__ void op_diag_run(cplx<R> (&v)[1 << RB], const OpDesc 
     A lamu[RB];
 #pragma unroll
     for (int i = 0; i < RB; i++) lamu[i] = 0;
-    const DiagTerm *p = tm;
+    kptr<DiagTerm> p = tm;
     for (uint32_t k = 0; k < o.n_fix; k++) {
-        const DiagTerm &t = p[k];
-        const uint32_t y0 = (yfix >> t.phys[0]) & 1u;
-        const uint32_t y1 = t.nq == 2 ? (yfix >> t.phys[1]) & 1u : 0u;
-        const A t0 = (A)t.th[0], t1 = (A)t.th[1], t2 = (A)t.th[2], t3 = (A)t.th[3];
+        const TermU<A> t = load_term<A>(p + k);
+        const uint32_t y0 = (yfix >> t.phys0) & 1u;
+        const uint32_t y1 = t.nq == 2 ? (yfix >> t.phys1) & 1u : 0u;
+        const A t0 = t.th[0], t1 = t.th[1], t2 = t.th[2], t3 = t.th[3];
         const A lo = y0 ? t1 : t0, hi = y0 ? t3 : t2;
         Cu += y1 ? hi : lo;
     }
@@ -472,9 +572,9 @@ __device__ __forceinline__ void op_diag_run(cplx<R> (&v)[1 << RB], const OpDesc 
         const uint32_t cnt = o.n_fixreg[i];
         A cs = 0, ls = 0;
         for (uint32_t k = 0; k < cnt; k++) {
-            const DiagTerm &t = p[k];
-            const uint32_t y = (yfix >> t.phys[0]) & 1u;
-            const A t0 = (A)t.th[0], t1 = (A)t.th[1], t2 = (A)t.th[2], t3 = (A)t.th[3];
+            const TermU<A> t = load_term<A>(p + k);
+            const uint32_t y = (yfix >> t.phys0) & 1u;
+            const A t0 = t.th[0], t1 = t.th[1], t2 = t.th[2], t3 = t.th[3];
             const A a0 = y ? t1 : t0, a1 = y ? t3 : t2;
             cs += a0;
             ls += a1 - a0;
@@ -490,13 +590,13 @@ __device__ __forceinline__ void op_diag_run(cplx<R> (&v)[1 << RB], const OpDesc 
     for (int i = 0; i < RB; i++) lam[i] = lamu[i];
 #pragma unroll 2
     for (uint32_t k = 0; k < o.n_lane; k++) {
-        const DiagTerm &t = p[k];
-        const uint32_t y0 = (ylane >> t.phys[0]) & 1u;
-        const A t0 = (A)t.th[0], t1 = (A)t.th[1], t2 = (A)t.th[2], t3 = (A)t.th[3];
+        const TermU<A> t = load_term<A>(p + k);
+        const uint32_t y0 = (ylane >> t.phys0) & 1u;
+        const A t0 = t.th[0], t1 = t.th[1], t2 = t.th[2], t3 = t.th[3];
         if (t.nq == 1) {
             C += y0 ? t1 : t0;
         } else {
-            const uint32_t y1 = t.role[1] == ROLE_LANE ? (ylane >> t.phys[1]) & 1u : (yfix >> t.phys[1]) & 1u;
+            const uint32_t y1 = t.role1 == ROLE_LANE ? (ylane >> t.phys1) & 1u : (yfix >> t.phys1) & 1u;
             const A lo = y0 ? t1 : t0, hi = y0 ? t3 : t2;
             C += y1 ? hi : lo;
         }
@@ -507,10 +607,11 @@ __device__ __forceinline__ void op_diag_run(cplx<R> (&v)[1 << RB], const OpDesc 
         const uint32_t cnt = o.n_lanereg[i];
 #pragma unroll 2
         for (uint32_t k = 0; k < cnt; k++) {
-            const DiagTerm &t = p[k];
-            const uint32_t y = (ylane >> t.phys[0]) & 1u;
-            const A a0 = y ? (A)t.th[1] : (A)t.th[0];
-            const A a1 = y ? (A)t.th[3] : (A)t.th[2];
+            const TermU<A> t = load_term<A>(p + k);
+            const uint32_t y = (ylane >> t.phys0) & 1u;
+            const A t0 = t.th[0], t1 = t.th[1], t2 = t.th[2], t3 = t.th[3];
+            const A a0 = y ? t1 : t0;
+            const A a1 = y ? t3 : t2;
             C += a0;
             lam[i] += a1 - a0;
         }
@@ -520,8 +621,8 @@ __device__ __forceinline__ void op_diag_run(cplx<R> (&v)[1 << RB], const OpDesc 
     uint32_t fr = 0;
     sfor<RB>([&](auto Ic) __attribute__((always_inline)) {
         constexpr int i = decltype(Ic)::value;
-        if ((uint32_t)i < pd->nr) {
-            const uint32_t f = (fx >> pd->rq[i]) & 1u;
+        if ((uint32_t)i < nr) {
+            const uint32_t f = (fx >> rq[i]) & 1u;
             fr |= f << i;
             if (f) {
                 C += lam[i];
@@ -533,7 +634,7 @@ __device__ __forceinline__ void op_diag_run(cplx<R> (&v)[1 << RB], const OpDesc 
     if (__builtin_popcount(lm) <= 2) {
         // few register-dependent factors: e^{2 pi i C}, then e^{2 pi i lam_i}
         // on the registers with bit i set
-        const cplx<R> w0 = expi_turns(C, expt);
+        const cplx<R> w0 = expi_turns(C);
         sfor<NJ>([&](auto Jc) __attribute__((always_inline)) {
             constexpr int j = decltype(Jc)::value;
             v[j] = cmul(w0, v[j]);
@@ -541,7 +642,7 @@ __device__ __forceinline__ void op_diag_run(cplx<R> (&v)[1 << RB], const OpDesc 
         sfor<RB>([&](auto Ic) __attribute__((always_inline)) {
             constexpr int i = decltype(Ic)::value;
             if ((lm >> i) & 1u) {
-                const cplx<R> e = expi_turns(lam[i], expt);
+                const cplx<R> e = expi_turns(lam[i]);
                 sfor<NJ>([&](auto Jc) __attribute__((always_inline)) {
                     constexpr int j = decltype(Jc)::value;
                     if constexpr (((j >> i) & 1) != 0) v[j] = cmul(e, v[j]);
@@ -551,10 +652,10 @@ __device__ __forceinline__ void op_diag_run(cplx<R> (&v)[1 << RB], const OpDesc 
     } else {
         // subset products over the low and high register bits
         cplx<R> wlo[1 << LO], whi[1 << HI];
-        wlo[0] = expi_turns(C, expt);
+        wlo[0] = expi_turns(C);
         sfor<LO>([&](auto Ic) __attribute__((always_inline)) {
             constexpr int i = decltype(Ic)::value;
-            const cplx<R> e = expi_turns(lam[i], expt);
+            const cplx<R> e = expi_turns(lam[i]);
             sfor<(1 << i)>([&](auto Sc) __attribute__((always_inline)) {
                 constexpr int s = decltype(Sc)::value;
                 wlo[s | (1 << i)] = cmul(wlo[s], e);
@@ -563,7 +664,7 @@ __device__ __forceinline__ void op_diag_run(cplx<R> (&v)[1 << RB], const OpDesc 
         whi[0] = cplx<R>{R(1), R(0)};
         sfor<HI>([&](auto Ic) __attribute__((always_inline)) {
             constexpr int i = decltype(Ic)::value;
-            const cplx<R> e = expi_turns(lam[LO + i], expt);
+            const cplx<R> e = expi_turns(lam[LO + i]);
             sfor<(1 << i)>([&](auto Sc) __attribute__((always_inline)) {
                 constexpr int s = decltype(Sc)::value;
                 whi[s | (1 << i)] = cmul(whi[s], e);
@@ -577,7 +678,7 @@ __device__ __forceinline__ void op_diag_run(cplx<R> (&v)[1 << RB], const OpDesc 
     }
     if (o.has_t) {
         // register-only gates: one wave-uniform factor per register index
-        const uint32_t msk = (1u << pd->nr) - 1u;
+        const uint32_t msk = (1u << nr) - 1u;
         sfor<NJ>([&](auto Jc) __attribute__((always_inline)) {
             constexpr int j = decltype(Jc)::value;
             v[j] = cmul(T[((uint32_t)j ^ fr) & msk], v[j]);
@@ -604,17 +705,26 @@ __global__ __launch_bounds__(64, (PassWaves<R, RB>::value)) void pass_kernel(Pas
     if (w >= a.work) return;
     const uint32_t traj = w % a.count, tile = w / a.count;
     const uint32_t L = threadIdx.x;
-    const PassDesc *pd = a.pass;
-    const uint32_t nl = pd->nl, nr = pd->nr, nfree = pd->nfree;
+    const kptr<PassDesc> pd = kconst(a.pass);
+    const kptr<OpDesc> ops = kconst(a.ops);
+    const kptr<cplx<R>> mats = kconst(a.mats);
+    const kptr<uint32_t> ev_pos = kconst(a.meta.ev_pos), ev_dx = kconst(a.meta.ev_dx),
+                         ev_dz = kconst(a.meta.ev_dz);
+    static_assert(offsetof(PassDesc, nl) == 8 && offsetof(PassDesc, rq) == 12 && offsetof(PassDesc, fbits) == 20,
+                  "pass descriptor layout");
+    const kptr<uint32_t> pw = (kptr<uint32_t>)pd;
+    const uint32_t op_begin = uni(pw[0]), op_count = uni(pw[1]), pw2 = uni(pw[2]);
+    const uint32_t rq03 = uni(pw[3]), rq47 = uni(pw[4]);
+    const uint32_t nl = pw2 & 0xFFu, nr = (pw2 >> 8) & 0xFFu, nfree = (pw2 >> 16) & 0xFFu;
 
     // tile loads go out first; the noise metadata is fetched behind them
-    const uint32_t src_s = a.src_slot[traj];
-    const uint32_t dst_s = a.dst_slot[traj];
+    const uint32_t src_s = kconst(a.src_slot)[traj];
+    const uint32_t dst_s = kconst(a.dst_slot)[traj];
     uint32_t base = 0;
-    for (uint32_t i = 0; i < nfree; i++) base |= ((tile >> i) & 1u) << pd->fbits[i];
+    for (uint32_t i = 0; i < nfree; i++) base |= ((tile >> i) & 1u) << ((uni(pw[5 + (i >> 2)]) >> (8 * (i & 3u))) & 0xFFu);
     uint32_t rq[RB];
 #pragma unroll
-    for (int i = 0; i < RB; i++) rq[i] = (uint32_t)i < nr ? pd->rq[i] : 0u;
+    for (int i = 0; i < RB; i++) rq[i] = (uint32_t)i < nr ? (((i < 4 ? rq03 : rq47) >> (8 * (i & 3))) & 0xFFu) : 0u;
     const bool lane_ok = L < (1u << nl);
     const uint32_t jmax = 1u << nr;
     const bool init = src_s == kInit;
@@ -654,37 +764,37 @@ __global__ __launch_bounds__(64, (PassWaves<R, RB>::value)) void pass_kernel(Pas
     }
 
     // frame at the start of this pass
-    const uint32_t node = a.node_ids[traj];
-    uint32_t fx = a.meta.frame0[2 * node], fz = a.meta.frame0[2 * node + 1];
-    uint32_t e = a.meta.ev_off[node];
-    const uint32_t e1 = a.meta.ev_off[node + 1];
-    while (e < e1 && a.meta.ev_pos[e] < a.pass_key) {
-        fx ^= a.meta.ev_dx[e];
-        fz ^= a.meta.ev_dz[e];
+    const uint32_t node = kconst(a.node_ids)[traj];
+    uint32_t fx = kconst(a.meta.frame0)[2 * node], fz = kconst(a.meta.frame0)[2 * node + 1];
+    uint32_t e = kconst(a.meta.ev_off)[node];
+    const uint32_t e1 = kconst(a.meta.ev_off)[node + 1];
+    while (e < e1 && ev_pos[e] < a.pass_key) {
+        fx ^= ev_dx[e];
+        fz ^= ev_dz[e];
         e++;
     }
 
-    for (uint32_t oi = 0; oi < pd->op_count; oi++) {
-        const OpDesc &o = a.ops[pd->op_begin + oi];
-        while (e < e1 && a.meta.ev_pos[e] <= (a.pass_key | o.slot0)) {
-            fx ^= a.meta.ev_dx[e];
-            fz ^= a.meta.ev_dz[e];
+    for (uint32_t oi = 0; oi < op_count; oi++) {
+        const OpDesc o = kload(ops + op_begin + oi);
+        while (e < e1 && ev_pos[e] <= (a.pass_key | o.slot0)) {
+            fx ^= ev_dx[e];
+            fz ^= ev_dz[e];
             e++;
         }
         if (o.kind == OP_DIAGRUN) {
-            const bool inside = e < e1 && a.meta.ev_pos[e] < (a.pass_key | o.slot1);
+            const bool inside = e < e1 && ev_pos[e] < (a.pass_key | o.slot1);
             if (!inside) {
-                op_diag_run<R, RB>(v, o, a.mats + o.mat, a.terms + o.terms, a.expt, fx, L, base, pd);
+                op_diag_run<R, RB>(v, o, mats + o.mat, kconst(a.terms) + o.terms, fx, L, base, rq, nr);
             } else {
                 // an event inside the run: gate by gate with frame updates
                 for (uint32_t k = 0; k < o.ngates; k++) {
-                    while (e < e1 && a.meta.ev_pos[e] <= (a.pass_key | (o.slot0 + k))) {
-                        fx ^= a.meta.ev_dx[e];
-                        fz ^= a.meta.ev_dz[e];
+                    while (e < e1 && ev_pos[e] <= (a.pass_key | (o.slot0 + k))) {
+                        fx ^= ev_dx[e];
+                        fz ^= ev_dz[e];
                         e++;
                     }
-                    const DiagGate &dg = a.dgates[o.gates + k];
-                    op_diag_one<R, RB>(v, dg, a.mats + dg.d, fx, L, base);
+                    const DiagGate dg = kload(kconst(a.dgates) + o.gates + k);
+                    op_diag_one<R, RB>(v, dg, mats + dg.d, fx, L, base);
                 }
             }
             continue;
@@ -694,7 +804,7 @@ __global__ __launch_bounds__(64, (PassWaves<R, RB>::value)) void pass_kernel(Pas
             xl |= ((fx >> o.phys[1]) & 1u) << 1;
             zl |= ((fz >> o.phys[1]) & 1u) << 1;
         }
-        const cplx<R> *G = a.mats + o.mat;
+        const kptr<cplx<R>> G = mats + o.mat;
         if constexpr (D2) {
             if (o.kind == OP_DENSE2) {
                 op_dense2<R, RB>(v, o, G, xl, zl, L);
