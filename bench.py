@@ -111,6 +111,50 @@ def fidelity_loss(T, W, torch, seeds, n=20, shots=16384):
             "seeds": seeds}
 
 
+def precision_sweep(T, W, torch, seed):
+    """26-qubit depth-24 brick-wall, depolarizing p2 in {1e-3, 1e-2} plus the
+    Pauli-twirled amplitude damping with gamma = p2 on each gate's qubits,
+    8192 shots in the tree (8, 4, 4, 4, 4, 4): complex64 evolution (FP64 CDF)
+    over all leaves against complex128 over level-0 subtree 0 (1024 leaves).
+    Reports rates and how many of the common leaves draw the same outcome.
+    (The amplitude error of either precision against the FP64 oracle is a
+    GPU parity test on the same circuit family.)"""
+    import numpy as np
+    n, depth, shape = 26, 24, [8, 4, 4, 4, 4, 4]
+    out = []
+    for p2 in (1e-3, 1e-2):
+        wc = W.brickwall(n, depth, seed=1).with_noise(0.0, p2, gamma=p2)
+        G = len(wc)
+        c = T.Circuit.from_workload(wc)
+        tree = (shape, equal_cuts(G, len(shape)))
+        nz = T.Noise.sample(c, tree, seed)
+        per = int(np.prod(shape[1:]))
+        rec = {"p2": p2, "gamma": p2, "qubits": n, "depth": depth, "gates": G, "tree": shape}
+        outs = {}
+        for prec, (first, last) in (("c64", (0, shape[0])), ("c128", (0, 1))):
+            plan = T.Plan(c, tree, prec)
+            ws = T.Workspace(plan.workspace_bytes(nz))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            o, st = T.run(plan, nz, ws, stats=True, subtrees=(first, last))
+            dt = time.perf_counter() - t0
+            outs[prec] = o
+            rec[prec] = {"leaves": int(o.size), "shots_per_s": o.size / dt, "s": dt,
+                         "pass_GBps": st["bytes_passes"] / (st["ms_passes"] * 1e-3) / 1e9}
+            del ws
+        same = outs["c64"][:per] == outs["c128"]
+        rec["outcomes_equal_c64_c128"] = "%d of %d" % (int(same.sum()), per)
+        # a rounding-level difference moves the inverse-CDF pick across a
+        # neighbouring boundary: the differing outcomes are index neighbours
+        gap = np.abs(outs["c64"][:per].astype(np.int64) - outs["c128"].astype(np.int64))
+        rec["largest_outcome_index_gap"] = int(gap.max())
+        out.append(rec)
+        print("# precision p2=%g: c64 %.1f shots/s, c128 %.1f shots/s, equal outcomes %s, largest index gap %d" %
+              (p2, rec["c64"]["shots_per_s"], rec["c128"]["shots_per_s"], rec["outcomes_equal_c64_c128"],
+               rec["largest_outcome_index_gap"]), file=sys.stderr, flush=True)
+    return out
+
+
 def cpu_baseline(wc, seed, budget_s=15.0):
     """The oracle (per-shot, complex128, threads over shots) on a bounded
     sample of the same workload's shots."""
@@ -153,6 +197,8 @@ def main():
     ap.add_argument("--fidelity", action="store_true",
                     help="also report the tree's fidelity loss against per-shot sampling")
     ap.add_argument("--fid-seeds", type=int, default=10)
+    ap.add_argument("--precision", action="store_true",
+                    help="also run the 26-qubit complex64 / complex128 precision sweep")
     ap.add_argument("--no-bw", action="store_true",
                     help="skip the 20-qubit brick-wall forms (reported beside the QFT ones)")
     args = ap.parse_args()
@@ -261,6 +307,8 @@ def main():
             print("# brickwall %s: %.1f shots/s, %.2f ms/step" % (name, sps, ms), file=sys.stderr, flush=True)
     if args.fidelity:
         line["fidelity_loss"] = fidelity_loss(T, W, torch, args.fid_seeds)
+    if args.precision:
+        line["precision_sweep"] = precision_sweep(T, W, torch, args.seed)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(wc, args.seed, args.cpu_budget)
     print(json.dumps(line), flush=True)

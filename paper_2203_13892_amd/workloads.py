@@ -97,6 +97,56 @@ def pauli_probs_1q(px: float, py: float, pz: float) -> np.ndarray:
     return np.array([1.0 - px - py - pz, px, py, pz], np.float64)
 
 
+def amplitude_damping_twirl(gamma: float) -> np.ndarray:
+    """Pauli twirl of amplitude damping with decay probability gamma (the
+    channel keeps only its Pauli-diagonal part): p_X = p_Y = gamma / 4,
+    p_Z = (1 - sqrt(1 - gamma))^2 / 4, p_I = (1 + sqrt(1 - gamma))^2 / 4."""
+    a = np.sqrt(1.0 - gamma)
+    return np.array([(1.0 + a) ** 2 / 4.0, gamma / 4.0, gamma / 4.0, (1.0 - a) ** 2 / 4.0], np.float64)
+
+
+def phase_damping_probs(lam: float) -> np.ndarray:
+    """Phase damping with parameter lambda is exactly the Z channel with
+    p_Z = (1 - sqrt(1 - lambda)) / 2 (it damps coherences by sqrt(1 - lambda))."""
+    pz = (1.0 - np.sqrt(1.0 - lam)) / 2.0
+    return np.array([1.0 - pz, 0.0, 0.0, pz], np.float64)
+
+
+# one-qubit Pauli codes (0 I, 1 X, 2 Y, 3 Z) multiply, up to phase, as their
+# (x, z) bit pairs xor: I (0,0), X (1,0), Y (1,1), Z (0,1)
+_CODE_XZ = [(0, 0), (1, 0), (1, 1), (0, 1)]
+_XZ_CODE = {xz: c for c, xz in enumerate(_CODE_XZ)}
+
+
+def _pauli_product_code(a: int, b: int, arity: int) -> int:
+    out = 0
+    for j in range(arity):
+        ca, cb = (a >> (2 * j)) & 3, (b >> (2 * j)) & 3
+        xa, za = _CODE_XZ[ca]
+        xb, zb = _CODE_XZ[cb]
+        out |= _XZ_CODE[(xa ^ xb, za ^ zb)] << (2 * j)
+    return out
+
+
+def compose_pauli_channels(p: np.ndarray, q: np.ndarray, arity: int) -> np.ndarray:
+    """Probabilities of the product of independent Paulis drawn from p and
+    from q (phases cancel in P rho P^dagger): the two channels in sequence."""
+    k = 1 << (2 * arity)
+    out = np.zeros(k, np.float64)
+    for a in range(k):
+        for b in range(k):
+            out[_pauli_product_code(a, b, arity)] += p[a] * q[b]
+    return out
+
+
+def per_qubit_channel(ch: np.ndarray, arity: int) -> np.ndarray:
+    """The same one-qubit Pauli channel on each of a gate's qubits
+    (code c0 + 4 c1 for qubits[0], qubits[1])."""
+    if arity == 1:
+        return np.asarray(ch, np.float64).copy()
+    return np.array([ch[c & 3] * ch[c >> 2] for c in range(16)], np.float64)
+
+
 # --------------------------------------------------------------- circuits --
 
 @dataclass
@@ -120,6 +170,19 @@ class Circuit:
         for q, m, _ in self.gates:
             p = p1 if len(q) == 1 else p2
             out.add(q, m, depolarizing_probs(p, len(q)) if p > 0 else None)
+        return out
+
+    def with_noise(self, p1: float, p2: float, gamma: float = 0.0, lam: float = 0.0) -> "Circuit":
+        """Copy with, after every gate, the depolarizing channel (p1 / p2) and
+        then on each of its qubits the Pauli-twirled amplitude damping (gamma)
+        and phase damping (lambda), combined into one Pauli channel."""
+        ch = compose_pauli_channels(amplitude_damping_twirl(gamma), phase_damping_probs(lam), 1)
+        out = Circuit(self.n, [], self.name)
+        for q, m, _ in self.gates:
+            a = len(q)
+            dep = depolarizing_probs(p1 if a == 1 else p2, a)
+            pr = compose_pauli_channels(dep, per_qubit_channel(ch, a), a)
+            out.add(q, m, pr if pr[0] < 1.0 else None)
         return out
 
     def noiseless(self) -> "Circuit":

@@ -341,3 +341,38 @@ def test_tree_fidelity_loss_is_small(T):
     se = d.std(ddof=1) / math.sqrt(d.size)
     assert 0.2 < F["pershot"].mean() < 0.99
     assert abs(d.mean()) <= 0.016 + 3 * se, (d.mean(), se)
+
+
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+def test_damping_channels(T, prec):
+    # depolarizing plus twirled amplitude damping and phase damping on each
+    # gate's qubits (one Pauli channel per gate), a 13-qubit brick-wall in a
+    # 3-level tree, at rates high enough that most nodes draw events
+    wc = W.brickwall(13, 10, seed=4).with_noise(0.01, 0.05, gamma=0.05, lam=0.03)
+    G = len(wc)
+    tree = ([4, 3, 3], [0, G // 3, 2 * G // 3, G])
+    out, amps, oout, ost, onz = run_both(T, wc, tree, 9, prec, np.arange(36))
+    assert np.max(np.abs(amps - ost)) < TOL[prec]
+    check_outcomes(out, oout, ost, onz.leaf_u, DELTA[prec])
+
+
+def test_c4_precision_brickwall_22q(T):
+    # the precision-sweep circuit family at 22 qubits: depth-24 brick-wall,
+    # p2 = 1e-2 with twirled amplitude damping gamma = 1e-2; two leaves of a
+    # (8, 32, 32) tree at complex64 (FP64 CDF) and complex128 against the
+    # FP64 oracle
+    n = 22
+    wc = W.brickwall(n, 24, seed=1).with_noise(0.0, 1e-2, gamma=1e-2)
+    G = len(wc)
+    tree = ([8, 32, 32], [0, G // 3, 2 * G // 3, G])
+    leaves = np.array([0, 8191], np.uint64)
+    c = T.Circuit.from_workload(wc)
+    nz = T.Noise.sample(c, tree, 3)
+    onz = oracle.sample_noise(wc.gates, tree, 3)
+    oout, ost = oracle.run_leaves(n, wc.gates, tree, onz, leaves, states=True)
+    for prec in ("c64", "c128"):
+        out, amps = T.run_capture(T.Plan(c, tree, prec), nz, leaves)
+        err = np.max(np.abs(amps - ost))
+        print(prec, "max-abs error vs oracle", err)
+        assert err < TOL[prec]
+        check_outcomes(out[leaves.astype(np.int64)], oout, ost, onz.leaf_u[leaves.astype(np.int64)], DELTA[prec])

@@ -344,3 +344,67 @@ def test_fidelity_metrics():
     assert abs(tree.fidelity_norm(p, np.full(4, 0.25))) < 1e-15
     assert math.isnan(tree.fidelity_norm(np.full(4, 0.25), p))
     assert tree.tv_distance(p, np.array([0, 0, 0.5, 0.5])) == 1.0
+
+
+# ------------------------------------------------------------ channels --
+def _random_rho(d, rng):
+    a = rng.normal(size=(d, d)) + 1j * rng.normal(size=(d, d))
+    r = a @ a.conj().T
+    return r / np.trace(r)
+
+
+@pytest.mark.parametrize("gamma", [0.0, 1e-3, 0.02, 0.3, 1.0])
+def test_amplitude_damping_twirl_from_kraus(gamma):
+    from oracle import channels as ch
+    tw = ch.pauli_twirl(ch.kraus_amplitude_damping(gamma))
+    assert np.allclose(tw, W.amplitude_damping_twirl(gamma), atol=1e-15)
+    assert abs(tw.sum() - 1.0) < 1e-14
+    # the twirled channel by its definition acts as this Pauli channel
+    rng = np.random.default_rng(int(gamma * 1000) + 1)
+    rho = _random_rho(2, rng)
+    assert np.allclose(ch.twirl_channel(rho, ch.kraus_amplitude_damping(gamma)),
+                       ch.apply_pauli_channel(rho, tw), atol=1e-14)
+
+
+@pytest.mark.parametrize("lam", [0.0, 1e-3, 0.05, 0.5, 1.0])
+def test_phase_damping_is_a_z_channel(lam):
+    from oracle import channels as ch
+    rng = np.random.default_rng(int(lam * 1000) + 7)
+    rho = _random_rho(2, rng)
+    # phase damping needs no twirl: it already is this Z channel, exactly
+    assert np.allclose(ch.apply_kraus(rho, ch.kraus_phase_damping(lam)),
+                       ch.apply_pauli_channel(rho, W.phase_damping_probs(lam)), atol=1e-14)
+    assert np.allclose(ch.pauli_twirl(ch.kraus_phase_damping(lam)), W.phase_damping_probs(lam), atol=1e-15)
+
+
+def test_composed_pauli_channels_act_in_sequence():
+    from oracle import channels as ch
+    rng = np.random.default_rng(5)
+    for arity in (1, 2):
+        k = 4 ** arity
+        p = rng.random(k); p /= p.sum()
+        q = rng.random(k); q /= q.sum()
+        rho = _random_rho(2 ** arity, rng)
+        seq = ch.apply_pauli_channel(ch.apply_pauli_channel(rho, p), q)
+        assert np.allclose(ch.apply_pauli_channel(rho, W.compose_pauli_channels(p, q, arity)), seq, atol=1e-14)
+    # the per-qubit product is the channel on each qubit in turn
+    c1 = W.amplitude_damping_twirl(0.1)
+    rho = _random_rho(4, rng)
+    two = ch.apply_pauli_channel(rho, W.per_qubit_channel(c1, 2))
+    one_each = ch.apply_pauli_channel(rho, np.array([c1[c & 3] * (c >> 2 == 0) for c in range(16)]))
+    one_each = ch.apply_pauli_channel(one_each, np.array([c1[c >> 2] * (c & 3 == 0) for c in range(16)]))
+    assert np.allclose(two, one_each, atol=1e-14)
+
+
+def test_damped_circuit_trajectories_match_density_matrix():
+    # noise = depolarizing, then twirled amplitude damping and phase damping
+    # per qubit: trajectory average of |psi|^2 = density-matrix diagonal
+    from oracle import density
+    wc = W.brickwall(4, 4, seed=2).with_noise(0.02, 0.05, gamma=0.2, lam=0.1)
+    rho = density.dm_run(wc.n, wc.gates)
+    tree = ([3000], [0, len(wc)])
+    nz = oracle.sample_noise(wc.gates, tree, 11)
+    _, st = oracle.run_leaves(wc.n, wc.gates, tree, nz, states=True)
+    mean = np.mean(np.abs(st) ** 2, axis=0)
+    sd = np.std(np.abs(st) ** 2, axis=0) / np.sqrt(st.shape[0])
+    assert np.all(np.abs(mean - np.real(np.diag(rho))) <= 4 * sd + 1e-12)
