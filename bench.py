@@ -197,6 +197,9 @@ def main():
     ap.add_argument("--fidelity", action="store_true",
                     help="also report the tree's fidelity loss against per-shot sampling")
     ap.add_argument("--fid-seeds", type=int, default=10)
+    ap.add_argument("--learned", action="store_true",
+                    help="also evaluate the learned tree shape against DCP and per-shot on "
+                         "held-out 24-qubit circuits")
     ap.add_argument("--precision", action="store_true",
                     help="also run the 26-qubit complex64 / complex128 precision sweep")
     ap.add_argument("--no-bw", action="store_true",
@@ -309,6 +312,13 @@ def main():
         line["fidelity_loss"] = fidelity_loss(T, W, torch, args.fid_seeds)
     if args.precision:
         line["precision_sweep"] = precision_sweep(T, W, torch, args.seed)
+    if args.learned:
+        from paper_2203_13892_amd import learned as Lm
+        model = Lm.ShapeModel.load(T)
+        cc = line.get("copy_cost_gates", 26.0)
+        line["learned_shape"] = Lm.evaluate(T, torch, model, Lm.held_out_circuits(), copy_cost=cc,
+                                            seed=args.seed,
+                                            log=lambda m: print("# learned " + m, file=sys.stderr, flush=True))
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(wc, args.seed, args.cpu_budget)
     print(json.dumps(line), flush=True)

@@ -187,6 +187,22 @@ tqs_status tqs_plan_info(const tqs_plan *p, uint32_t level, uint32_t *passes_lev
  * list (nz may be NULL for a bound valid for any list of this tree). */
 tqs_status tqs_workspace_bytes(const tqs_plan *p, const tqs_noise *nz, uint64_t *bytes);
 
+/* Text description of the plan, for tests and analysis (no device work).
+ * Writes at most cap bytes, NUL-terminated, into buf (may be NULL) and the
+ * full size including the NUL into *len.  Lines:
+ *   plan <n> <passes> <gates> <levels>
+ *   layout <physical position of logical qubit 0> ... (after the last level)
+ *   gate <g> <pass> <slot after it> <arity> <phys q0> <phys q1>   (positions
+ *        when the gate runs; a noise event of gate g acts there)
+ *   level <l> <first pass> <pass count>
+ *   pass <p> <op count> regs <register positions...>
+ *   dense <arity> <phys q0> <phys q1> <slot0> <slot1> | <row-major matrix, re im ...>
+ *   diag <slot0> <slot1> | <arity> <phys q0> <phys q1> <diagonal, re im ...> | ...
+ * Ops run in the listed order; gate slot s of a pass lies between ops whose
+ * slot ranges end at s and begin at s.  A dense op with no circuit gate in
+ * its slot is a lane exchange (a swap of two positions). */
+tqs_status tqs_plan_describe(const tqs_plan *p, char *buf, uint64_t cap, uint64_t *len);
+
 void tqs_plan_destroy(tqs_plan *p);
 
 /* --------------------------------------------------------------------- run */
@@ -213,6 +229,33 @@ tqs_status tqs_run_range(tqs_plan *p, const tqs_noise *nz, void *d_workspace,
 tqs_status tqs_run_capture(tqs_plan *p, const tqs_noise *nz, void *d_workspace,
                            uint64_t ws_bytes, void *stream, uint64_t *outcomes,
                            const uint64_t *leaves, uint64_t n, double *host_amps);
+
+/* ------------------------------------------------- learned tree shape ---
+ * A two-hidden-layer perceptron (ReLU, FP32) that predicts, from circuit,
+ * noise, shot-count and candidate-shape features, a tree shape's run time
+ * and fidelity spread; it stands in for the partition heuristic (Sec. 3.2)
+ * when its prediction is trusted.  All pointers are device pointers (caller
+ * owned, 4-byte aligned); calls are stream-ordered and do not synchronise.
+ * Parameters, one array of tqs_mlp_param_count floats, row-major with the
+ * input index first: W1[d_in x h], b1[h], W2[h x h], b2[h], W3[h x d_out],
+ * b3[d_out]; forward y = relu(relu(x W1 + b1) W2 + b2) W3 + b3.
+ * Limits: d_in, h <= 4096, d_out <= 64, batch <= 2^20; violations return
+ * TQS_E_ARG. */
+uint64_t tqs_mlp_param_count(uint32_t d_in, uint32_t h, uint32_t d_out);
+/* Floats of device scratch that forward / loss_grad need for `batch` rows. */
+uint64_t tqs_mlp_scratch_floats(uint32_t d_in, uint32_t h, uint32_t d_out, uint32_t batch);
+/* y[batch x d_out] from x[batch x d_in] (row-major). */
+tqs_status tqs_mlp_forward(const float *params, uint32_t d_in, uint32_t h, uint32_t d_out,
+                           const float *x, uint32_t batch, float *y, float *scratch, void *stream);
+/* Weighted squared error L = (1/B) sum_b sum_o w_o (y_bo - t_bo)^2 into
+ * *loss (device float) and dL/dparams into grad (param_count floats),
+ * by back-propagation; ReLU'(0) is taken as 0. */
+tqs_status tqs_mlp_loss_grad(const float *params, uint32_t d_in, uint32_t h, uint32_t d_out,
+                             const float *x, const float *target, const float *out_weight,
+                             uint32_t batch, float *grad, float *loss, float *scratch, void *stream);
+/* One Adam step (step counts from 1) on params with moments m, v. */
+tqs_status tqs_mlp_adam(float *params, const float *grad, float *m, float *v, uint64_t count,
+                        float lr, float beta1, float beta2, float eps, uint32_t step, void *stream);
 
 /* ------------------------------------------------------- results, errors */
 

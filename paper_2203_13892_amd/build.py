@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SO = os.path.join(HERE, "libtqsim.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("host.cpp", "plan.cpp", "device.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("host.cpp", "plan.cpp", "device.hip", "mlp.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # Packed FP32 instructions are kept out of generated code (ordinary scalar

@@ -20,7 +20,9 @@
 // own order on the gate's qubits, so every trajectory is unchanged.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <string>
 #include <new>
 
 #include "tqs_internal.h"
@@ -533,3 +535,57 @@ extern "C" tqs_status tqs_plan_info(const tqs_plan *p, uint32_t level, uint32_t 
 }
 
 extern "C" void tqs_plan_destroy(tqs_plan *p) { delete p; }
+
+// Text description of a plan (see the header for the format).
+extern "C" tqs_status tqs_plan_describe(const tqs_plan *p, char *buf, uint64_t cap, uint64_t *len) {
+    TQS_GUARD_BEGIN
+    if (!p || !len) return fail(TQS_E_ARG, "plan or len is NULL");
+    std::string s;
+    char tmp[128];
+    auto put = [&](const char *fmt, auto... a) {
+        std::snprintf(tmp, sizeof tmp, fmt, a...);
+        s += tmp;
+    };
+    put("plan %u %zu %u %zu\n", p->n, p->passes.size(), p->n_gates, p->levels.size());
+    s += "layout";
+    for (uint32_t q = 0; q < p->n; q++) put(" %u", p->lay_final[q]);
+    s += "\n";
+    for (uint32_t g = 0; g < p->n_gates; g++)
+        put("gate %u %u %u %u %u %u\n", g, p->gate_pass[g], p->gate_pos[g], p->gate_a[g], p->gate_q0[g],
+            p->gate_q1[g]);
+    for (size_t l = 0; l < p->levels.size(); l++)
+        put("level %zu %u %u\n", l, p->levels[l].pass_begin, p->levels[l].pass_count);
+    for (size_t pi = 0; pi < p->passes.size(); pi++) {
+        const PassDesc &d = p->passes[pi];
+        put("pass %zu %u regs", pi, d.op_count);
+        for (uint32_t i = 0; i < d.nr; i++) put(" %u", d.rq[i]);
+        s += "\n";
+        for (uint32_t oi = d.op_begin; oi < d.op_begin + d.op_count; oi++) {
+            const OpDesc &o = p->ops[oi];
+            if (o.kind == OP_DIAGRUN) {
+                put("diag %u %u", o.slot0, o.slot1);
+                for (uint32_t k = 0; k < o.ngates; k++) {
+                    const DiagGate &dg = p->dgates[o.gates + k];
+                    put(" | %u %u %u", dg.nq, dg.phys[0], dg.nq == 2 ? dg.phys[1] : dg.phys[0]);
+                    for (uint32_t r = 0; r < (1u << dg.nq); r++)
+                        put(" %.17g %.17g", p->mats[dg.d + r].real(), p->mats[dg.d + r].imag());
+                }
+            } else {
+                put("dense %u %u %u %u %u |", o.nq, o.phys[0], o.nq == 2 ? o.phys[1] : o.phys[0], o.slot0,
+                    o.slot1);
+                const uint32_t nd = 1u << o.nq;
+                for (uint32_t r = 0; r < nd * nd; r++)
+                    put(" %.17g %.17g", p->mats[o.mat + r].real(), p->mats[o.mat + r].imag());
+            }
+            s += "\n";
+        }
+    }
+    *len = s.size() + 1;
+    if (buf && cap) {
+        const uint64_t k = std::min<uint64_t>(cap - 1, s.size());
+        std::memcpy(buf, s.data(), k);
+        buf[k] = 0;
+    }
+    return TQS_OK;
+    TQS_GUARD_END
+}

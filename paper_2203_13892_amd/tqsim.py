@@ -62,6 +62,12 @@ SIGNATURES = {
     "tqs_run_capture": (i32, [vp, vp, vp, u64, vp, P(u64), P(u64), u64, P(dbl)]),
     "tqs_histogram": (i32, [P(u64), u64, P(u64), P(u64), P(u64)]),
     "tqs_probe_copy": (i32, [vp, u64, u32, vp, P(dbl)]),
+    "tqs_plan_describe": (i32, [vp, C.c_char_p, u64, P(u64)]),
+    "tqs_mlp_param_count": (u64, [u32, u32, u32]),
+    "tqs_mlp_scratch_floats": (u64, [u32, u32, u32, u32]),
+    "tqs_mlp_forward": (i32, [vp, u32, u32, u32, vp, u32, vp, vp, vp]),
+    "tqs_mlp_loss_grad": (i32, [vp, u32, u32, u32, vp, vp, vp, u32, vp, vp, vp, vp]),
+    "tqs_mlp_adam": (i32, [vp, vp, vp, vp, u64, C.c_float, C.c_float, C.c_float, C.c_float, u32, vp]),
     "tqs_last_error": (C.c_char_p, []),
     "tqs_version": (C.c_char_p, []),
 }
@@ -240,6 +246,14 @@ class Plan:
         _check(lib.tqs_plan_info(self.h, level, C.byref(a), C.byref(b), C.byref(c)))
         return {"passes_level": a.value, "passes_total": b.value, "chunk_states": c.value}
 
+    def describe(self) -> str:
+        """The plan as text (format in tqsim.h, tqs_plan_describe)."""
+        n = u64()
+        _check(lib.tqs_plan_describe(self.h, None, 0, C.byref(n)))
+        buf = C.create_string_buffer(n.value)
+        _check(lib.tqs_plan_describe(self.h, buf, n.value, C.byref(n)))
+        return buf.value.decode()
+
     def workspace_bytes(self, noise: Noise = None) -> int:
         b = u64()
         _check(lib.tqs_workspace_bytes(self.h, noise.h if noise is not None else None, C.byref(b)))
@@ -326,3 +340,74 @@ def probe_copy(nbytes: int, reps: int = 10, stream=None) -> float:
     g = dbl()
     _check(lib.tqs_probe_copy(vp(ws.ptr), nbytes, reps, _stream(stream), C.byref(g)))
     return g.value
+
+
+class Perceptron:
+    """The library's two-hidden-layer perceptron on device tensors (torch
+    float32 on the GPU): forward, loss gradient and Adam run in the
+    library's kernels; torch only holds the memory."""
+
+    def __init__(self, d_in: int, hidden: int, d_out: int, params=None, seed: int = 0):
+        import torch
+        self.d_in, self.h, self.d_out = int(d_in), int(hidden), int(d_out)
+        self.count = int(lib.tqs_mlp_param_count(self.d_in, self.h, self.d_out))
+        if params is None:
+            # He-uniform weights, zero biases (host draw, then one copy)
+            rng = np.random.default_rng(seed)
+            p = np.zeros(self.count, np.float32)
+            o = 0
+            for fan_in, fan_out in ((self.d_in, self.h), (self.h, self.h), (self.h, self.d_out)):
+                lim = np.sqrt(6.0 / fan_in)
+                p[o:o + fan_in * fan_out] = rng.uniform(-lim, lim, fan_in * fan_out)
+                o += fan_in * fan_out + fan_out
+            params = p
+        params = np.ascontiguousarray(np.asarray(params, np.float32))
+        if params.size != self.count:
+            raise ValueError("expected %d parameters, got %d" % (self.count, params.size))
+        self.params = torch.from_numpy(params).cuda()
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.grad = torch.zeros_like(self.params)
+        self.step = 0
+        self._scratch = None
+
+    def _scr(self, batch):
+        import torch
+        need = int(lib.tqs_mlp_scratch_floats(self.d_in, self.h, self.d_out, batch))
+        if self._scratch is None or self._scratch.numel() < need:
+            self._scratch = torch.empty(need, dtype=torch.float32, device="cuda")
+        return self._scratch
+
+    @staticmethod
+    def _dev(a):
+        import torch
+        t = a if isinstance(a, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(np.asarray(a, np.float32)))
+        return t.to(device="cuda", dtype=torch.float32).contiguous()
+
+    def forward(self, x):
+        import torch
+        x = self._dev(x)
+        b = x.shape[0]
+        y = torch.empty((b, self.d_out), dtype=torch.float32, device="cuda")
+        s = _stream(None)
+        _check(lib.tqs_mlp_forward(vp(self.params.data_ptr()), self.d_in, self.h, self.d_out,
+                                   vp(x.data_ptr()), b, vp(y.data_ptr()), vp(self._scr(b).data_ptr()), s))
+        return y
+
+    def loss_grad(self, x, target, weight):
+        """Loss (device scalar) and the gradient (into self.grad)."""
+        import torch
+        x, t, w = self._dev(x), self._dev(target), self._dev(weight)
+        b = x.shape[0]
+        loss = torch.empty(1, dtype=torch.float32, device="cuda")
+        _check(lib.tqs_mlp_loss_grad(vp(self.params.data_ptr()), self.d_in, self.h, self.d_out,
+                                     vp(x.data_ptr()), vp(t.data_ptr()), vp(w.data_ptr()), b,
+                                     vp(self.grad.data_ptr()), vp(loss.data_ptr()),
+                                     vp(self._scr(b).data_ptr()), _stream(None)))
+        return loss
+
+    def adam(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        self.step += 1
+        _check(lib.tqs_mlp_adam(vp(self.params.data_ptr()), vp(self.grad.data_ptr()), vp(self.m.data_ptr()),
+                                vp(self.v.data_ptr()), self.count, lr, beta1, beta2, eps, self.step,
+                                _stream(None)))

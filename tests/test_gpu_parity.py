@@ -376,3 +376,53 @@ def test_c4_precision_brickwall_22q(T):
         print(prec, "max-abs error vs oracle", err)
         assert err < TOL[prec]
         check_outcomes(out[leaves.astype(np.int64)], oout, ost, onz.leaf_u[leaves.astype(np.int64)], DELTA[prec])
+
+
+def test_perceptron_kernels_against_oracle(T):
+    # forward, loss gradient and Adam of the shape perceptron (float32 HIP
+    # kernels) against the float64 oracle, batch not a multiple of the tile
+    import torch
+    from oracle import mlp as omlp
+    d_in, h, d_out, B = 11, 128, 2, 37
+    rng = np.random.default_rng(8)
+    net = T.Perceptron(d_in, h, d_out, seed=4)
+    p0 = net.params.cpu().numpy().astype(np.float64)
+    x = rng.normal(size=(B, d_in)).astype(np.float32)
+    t = rng.normal(size=(B, d_out)).astype(np.float32)
+    w = np.array([1.0, 0.5], np.float32)
+    y = net.forward(x).cpu().numpy()
+    yo = omlp.forward(p0, x, d_in, h, d_out)
+    assert np.max(np.abs(y - yo)) < 1e-4 * max(1.0, np.max(np.abs(yo)))
+    loss = net.loss_grad(x, t, w)
+    torch.cuda.synchronize()
+    Lo, go = omlp.loss_grad(p0, x, t, w, d_in, h, d_out)
+    assert abs(float(loss.cpu()) - Lo) < 1e-4 * max(1.0, Lo)
+    g = net.grad.cpu().numpy()
+    assert np.max(np.abs(g - go)) < 1e-4 * max(1.0, np.max(np.abs(go)))
+    net.adam(lr=1e-2)
+    po, _, _ = omlp.adam(p0, go, np.zeros_like(p0), np.zeros_like(p0), 1, 1e-2)
+    assert np.max(np.abs(net.params.cpu().numpy() - po)) < 1e-5
+
+
+def test_learned_shape_against_partition_heuristic(T):
+    # the committed shape model (trained on the simulator's own runs of 12-22
+    # qubit circuits) against the DCP shape on a circuit it has not seen:
+    # measured time per leaf and the design effect of the fidelity estimate
+    import torch
+    from paper_2203_13892_amd import learned as Lm
+    model = Lm.ShapeModel.load(T)
+    wc = W.brickwall(18, 18, seed=11).with_noise(1e-3, 1e-2)
+    shots = 8192
+    (shape, _), src = Lm.choose_shape(T, model, wc, shots)
+    assert src == "learned"
+    c = T.Circuit.from_workload(wc)
+    dshape = T.dcp(c, shots, 1.96, 0.01, 26.0, 8)[0]
+    p_ideal = Lm.ideal_probs(T, wc)
+    t_d, deff_d, ws = Lm.measure(T, torch, wc, c, dshape, shots, p_ideal, 1)
+    t_l, deff_l, ws = Lm.measure(T, torch, wc, c, shape, shots, p_ideal, 1, ws)
+    print("learned", shape, t_l, deff_l, "dcp", list(dshape), t_d, deff_d)
+    assert t_l < 0.8 * t_d
+    assert deff_l < 12.0
+    # far outside the training range: the heuristic decides
+    big = W.brickwall(30, 4, seed=1).with_noise(1e-3, 1e-2)
+    assert Lm.choose_shape(T, model, big, shots)[1] == "dcp"

@@ -188,3 +188,123 @@ def test_swap_gates_take_no_pass():
     c = T.Circuit.from_workload(wc)
     assert T.Plan(c, ([8], [0, len(wc)])).info(0)["passes_level"] == 1
     assert T.Plan(c, ([2, 2], [0, 3, len(wc)])).info(1)["passes_level"] == 1
+
+
+def test_perceptron_sizes_and_argument_errors():
+    # parameter count of the layout W1 b1 W2 b2 W3 b3; bad sizes fail before
+    # any device work
+    lib = T.lib
+    assert lib.tqs_mlp_param_count(11, 128, 2) == 11 * 128 + 128 + 128 * 128 + 128 + 128 * 2 + 2
+    assert lib.tqs_mlp_scratch_floats(11, 128, 2, 10) == 10 * (4 * 128 + 2 * 2 + 1)
+    st = lib.tqs_mlp_forward(None, 0, 128, 2, None, 1, None, None, None)
+    assert st == -1 and b"positive" in lib.tqs_last_error()
+    st = lib.tqs_mlp_adam(None, None, None, None, 0, 1e-3, 0.9, 0.999, 1e-8, 1, None)
+    assert st == -1
+
+
+# ------------------------------------------------------ planner emulation --
+def _parse_plan(text):
+    lines = text.strip().split("\n")
+    n = int(lines[0].split()[1])
+    lay = [int(v) for v in lines[1].split()[1:]]
+    gates, passes = {}, []
+    for ln in lines[2:]:
+        head, _, rest = ln.partition("|")
+        f = head.split()
+        if f[0] == "gate":
+            g, p, pos, a, q0, q1 = map(int, f[1:])
+            gates[g] = (p, pos, a, q0, q1)
+        elif f[0] == "pass":
+            passes.append([])
+        elif f[0] == "dense":
+            nq, p0, p1, s0, s1 = map(int, f[1:])
+            v = np.array(rest.split(), float)
+            m = (v[0::2] + 1j * v[1::2]).reshape(1 << nq, 1 << nq)
+            passes[-1].append(("dense", s0, [(((p0, p1)[:nq]), m)]))
+        elif f[0] == "diag":
+            s0, s1 = int(f[1]), int(f[2])
+            gl = []
+            for seg in ln.split("|")[1:]:
+                v = seg.split()
+                nq, p0, p1 = int(v[0]), int(v[1]), int(v[2])
+                d = np.array(v[3:], float)
+                gl.append(((p0, p1)[:nq], np.diag(d[0::2] + 1j * d[1::2])))
+            passes[-1].append(("diag", s0, gl))
+    return n, lay, gates, passes
+
+
+def _emulate(text, events):
+    """Run the described plan gate by gate on a physical-order state, with
+    each noise event (gate, code) applied at its planned position."""
+    n, lay, gates, passes = _parse_plan(text)
+    psi = np.zeros(1 << n, np.complex128)
+    psi[0] = 1.0
+    evs = sorted(((gates[g][0] << 16) | gates[g][1], i, g, c) for i, (g, c) in enumerate(events))
+    k = 0
+
+    def flush(key):
+        nonlocal k
+        while k < len(evs) and evs[k][0] <= key:
+            _, _, g, c = evs[k]
+            p, pos, a, q0, q1 = gates[g]
+            oracle.apply_pauli(psi, [q0, q1][:a], c)
+            k += 1
+
+    for pi, ops in enumerate(passes):
+        flush((pi << 16) - 1)
+        for kind, s0, gl in ops:
+            for j, (qs, m) in enumerate(gl):
+                flush((pi << 16) | (s0 + j))
+                oracle.apply_gate(psi, list(qs), m)
+    flush(1 << 62)
+    idx = [sum(((y >> q) & 1) << lay[q] for q in range(n)) for y in range(1 << n)]
+    return psi[idx]
+
+
+def _random_gates(n, count, rng):
+    c = W.Circuit(n)
+    for i in range(count):
+        kind = i % 7
+        if kind == 0:
+            c.add((int(rng.integers(n)),), W.haar_unitary(2, rng))
+        elif kind == 1:
+            c.add((int(rng.integers(n)),), W.phase(float(rng.uniform(0, 6))))
+        else:
+            a, b = [int(x) for x in rng.choice(n, 2, replace=False)]
+            m = {2: W.cphase(float(rng.uniform(0, 6))), 3: W.cx(), 4: W.haar_unitary(4, rng),
+                 5: W.swap(), 6: W.rzz(float(rng.uniform(0, 6)))}[kind]
+            c.add((a, b), m)
+    return c
+
+
+@pytest.mark.parametrize("n,tree,tuning", [
+    (7, ([5], None), None),
+    (8, ([3, 2], None), {"max_ops_per_pass": 3}),
+    (9, ([2, 2, 2], None), None),
+    (10, ([4, 2], None), {"tile_qubits": 10}),
+    (10, ([3], None), {"pass_cost": 60}),
+    (11, ([2, 3], None), None),
+])
+def test_planner_schedule_reproduces_trajectories(n, tree, tuning):
+    # the plan's ops in its order (gates reordered, swaps relabelled, lane
+    # exchanges inserted), noise events at their planned positions, and the
+    # final layout reproduce every leaf's oracle trajectory
+    rng = np.random.default_rng(40 + n)
+    wc = _random_gates(n, 70, rng).with_depolarizing(0.1, 0.2)
+    G = len(wc)
+    A = tree[0]
+    cut = [round(i * G / len(A)) for i in range(len(A) + 1)]
+    tr = (A, cut)
+    c = T.Circuit.from_workload(wc)
+    text = T.Plan(c, tr, "c64", tuning).describe()
+    nz = oracle.sample_noise(wc.gates, tr, 5)
+    leaves = int(np.prod(A))
+    _, st = oracle.run_leaves(n, wc.gates, tr, nz, np.arange(leaves, dtype=np.uint64), states=True)
+    off = np.cumsum([0] + [int(np.prod(A[:l + 1])) for l in range(len(A))])
+    for lam in range(leaves):
+        events = []
+        for l in range(len(A)):
+            node = int(off[l]) + lam // int(np.prod(A[l + 1:], dtype=np.int64))
+            for e in range(int(nz.node_off[node]), int(nz.node_off[node + 1])):
+                events.append((int(nz.ev_gate[e]), int(nz.ev_code[e])))
+        assert np.max(np.abs(_emulate(text, events) - st[lam])) < 1e-12

@@ -408,3 +408,49 @@ def test_damped_circuit_trajectories_match_density_matrix():
     mean = np.mean(np.abs(st) ** 2, axis=0)
     sd = np.std(np.abs(st) ** 2, axis=0) / np.sqrt(st.shape[0])
     assert np.all(np.abs(mean - np.real(np.diag(rho))) <= 4 * sd + 1e-12)
+
+
+# ---------------------------------------------------- shape perceptron --
+def test_perceptron_gradient_matches_finite_differences():
+    from oracle import mlp
+    rng = np.random.default_rng(3)
+    d_in, h, d_out, B = 5, 7, 2, 9
+    n = sum(int(np.prod(s)) for s in mlp.sizes(d_in, h, d_out))
+    p = rng.normal(size=n) * 0.5
+    x = rng.normal(size=(B, d_in))
+    t = rng.normal(size=(B, d_out))
+    w = np.array([1.0, 0.3])
+    L, g = mlp.loss_grad(p, x, t, w, d_in, h, d_out)
+    assert abs(L - mlp.loss(p, x, t, w, d_in, h, d_out)) < 1e-14
+    eps = 1e-6
+    fd = np.array([(mlp.loss(p + eps * e, x, t, w, d_in, h, d_out) - mlp.loss(p - eps * e, x, t, w, d_in, h, d_out))
+                   / (2 * eps) for e in np.eye(n)])
+    assert np.max(np.abs(fd - g)) < 1e-7 * max(1.0, np.max(np.abs(g)))
+
+
+def test_perceptron_linear_regime_closed_form():
+    # with every pre-activation positive the network is affine in x, and a
+    # one-output squared error has the textbook gradient 2/B sum (y - t) dy/dp
+    from oracle import mlp
+    d_in, h, d_out = 2, 3, 1
+    W1 = np.array([[1.0, 0.5, 0.2], [0.3, 1.0, 0.1]]); b1 = np.ones(3)
+    W2 = np.eye(3) * 2.0; b2 = np.ones(3)
+    W3 = np.array([[1.0], [-1.0], [0.5]]); b3 = np.array([0.25])
+    p = mlp.pack([W1, b1, W2, b2, W3, b3])
+    x = np.array([[1.0, 2.0], [0.5, 0.0]])
+    y = mlp.forward(p, x, d_in, h, d_out)
+    want = ((x @ W1 + b1) @ W2 + b2) @ W3 + b3
+    assert np.allclose(y, want, atol=1e-14)
+    t = np.zeros((2, 1))
+    L, g = mlp.loss_grad(p, x, t, np.ones(1), d_in, h, d_out)
+    assert abs(L - np.mean(want[:, 0] ** 2)) < 1e-12
+    # gradient wrt b3 is 2 mean(y - t)
+    assert abs(g[-1] - 2 * np.mean(want[:, 0])) < 1e-12
+
+
+def test_adam_first_step_moves_by_lr():
+    # after bias correction the first step is lr * g / (|g| + eps)
+    from oracle import mlp
+    g = np.array([0.5, -2.0, 1e-3])
+    p1, m, v = mlp.adam(np.zeros(3), g, np.zeros(3), np.zeros(3), 1, 0.01)
+    assert np.allclose(p1, -0.01 * g / (np.abs(g) + 1e-8), atol=1e-12)
