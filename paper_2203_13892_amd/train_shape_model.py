@@ -28,13 +28,13 @@ DATA = os.path.join(Lm.HERE, "data", "shape_runs.npz")
 def circuit_pool(rng):
     fams = []
     for n in (12, 14, 16, 18, 20, 22):
-        for s in range(8):
+        for s in range(6):
             fams.append(("bw", n, s))
+            fams.append(("bw2", n, s))
             fams.append(("qaoa", n, s))
             fams.append(("rand", n, s))
-        for s in range(2):
-            fams.append(("ghz", n, s))
             fams.append(("qftrt", n, s))
+        fams.append(("ghz", n, 0))
     rng.shuffle(fams)
     return fams
 
@@ -42,6 +42,8 @@ def circuit_pool(rng):
 def make(fam, n, s, rng):
     if fam == "bw":
         wc = W.brickwall(n, n, seed=100 + s)
+    elif fam == "bw2":
+        wc = W.brickwall(n, 2 * n, seed=150 + s)
     elif fam == "qaoa":
         wc = W.qaoa(n, 2, seed=200 + s)
     elif fam == "rand":
