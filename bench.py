@@ -155,6 +155,78 @@ def precision_sweep(T, W, torch, seed):
     return out
 
 
+def batch_workload(W, count=512):
+    """512 circuits of 12-22 qubits: QFT, GHZ chains, QAOA p = 2 on seeded
+    random 3-regular graphs (angles uniform in [0, pi]), random brick-walls
+    (depth = qubits), depolarizing 1e-3 / 1e-2."""
+    out = []
+    fams = ("qft", "ghz", "qaoa", "bw")
+    ns = (12, 14, 16, 18, 20, 22)
+    i = 0
+    while len(out) < count:
+        f, n = fams[i % 4], ns[(i // 4) % 6]
+        s = i // 24
+        wc = {"qft": lambda: W.qft(n), "ghz": lambda: W.ghz(n), "qaoa": lambda: W.qaoa(n, 2, seed=s),
+              "bw": lambda: W.brickwall(n, n, seed=s)}[f]()
+        out.append(("%s%d_%d" % (f, n, s), wc.with_depolarizing(1e-3, 1e-2)))
+        i += 1
+    return out
+
+
+def batch_bench(T, W, torch, seed, shots=2048, budget_gib=32):
+    """The mixed workload per-shot at 2048 shots each: one run after another
+    against batches (runs grouped in qubit order up to a workspace budget,
+    each batch advancing its runs together)."""
+    import numpy as np
+    circs = batch_workload(W)
+    items = []
+    for i, (name, wc) in enumerate(circs):
+        G = len(wc)
+        c = T.Circuit.from_workload(wc)
+        tree = ([shots], [0, G])
+        # live states per run: about 256 MiB of states, at most 512
+        chunk = int(max(1, min(512, (256 << 20) // (8 << wc.n))))
+        plan = T.Plan(c, tree, "c64", {"chunk_states": chunk})
+        items.append((wc.n, plan, T.Noise.sample(c, tree, seed + i)))
+    # one after another
+    ws = T.Workspace(max(p.workspace_bytes(nz) for _, p, nz in items))
+    for _, p, nz in items[:4]:
+        T.run(p, nz, ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    seq = [T.run(p, nz, ws) for _, p, nz in items]
+    t_seq = time.perf_counter() - t0
+    del ws
+    # batches in qubit order
+    order = sorted(range(len(items)), key=lambda k: items[k][0])
+    groups, cur, cur_b = [], [], 0
+    for k in order:
+        b = items[k][1].workspace_bytes(items[k][2])
+        if cur and cur_b + b > (budget_gib << 30):
+            groups.append(cur)
+            cur, cur_b = [], 0
+        cur.append(k)
+        cur_b += b
+    groups.append(cur)
+    batches = [T.Batch([items[k][1] for k in g], [items[k][2] for k in g]) for g in groups]
+    wsb = T.Workspace(max(b.info()["workspace_bytes"] for b in batches))
+    batches[0].run(wsb)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = [b.run(wsb) for b in batches]
+    t_bat = time.perf_counter() - t0
+    same = all(np.array_equal(res[gi][j], seq[k]) for gi, g in enumerate(groups) for j, k in enumerate(g))
+    total = shots * len(items)
+    print("# batch: %d runs, sequential %.2f s (%.0f shots/s), batched %.2f s in %d batches (%.0f shots/s), "
+          "outcomes identical %s" % (len(items), t_seq, total / t_seq, t_bat, len(batches), total / t_bat, same),
+          file=sys.stderr, flush=True)
+    return {"workload": "512 circuits of 12-22 qubits (qft, ghz, qaoa p=2, brick-wall), 2048 shots each, "
+                        "per-shot, depolarizing(1e-3,1e-2)",
+            "runs": len(items), "shots_total": total, "sequential_s": t_seq, "batched_s": t_bat,
+            "batches": len(batches), "sequential_shots_per_s": total / t_seq,
+            "batched_shots_per_s": total / t_bat, "outcomes_identical": bool(same)}
+
+
 def cpu_baseline(wc, seed, budget_s=15.0):
     """The oracle (per-shot, complex128, threads over shots) on a bounded
     sample of the same workload's shots."""
@@ -197,6 +269,8 @@ def main():
     ap.add_argument("--fidelity", action="store_true",
                     help="also report the tree's fidelity loss against per-shot sampling")
     ap.add_argument("--fid-seeds", type=int, default=10)
+    ap.add_argument("--batch", action="store_true",
+                    help="also run the 512-circuit mixed workload one run at a time and batched")
     ap.add_argument("--learned", action="store_true",
                     help="also evaluate the learned tree shape against DCP and per-shot on "
                          "held-out 24-qubit circuits")
@@ -312,6 +386,8 @@ def main():
         line["fidelity_loss"] = fidelity_loss(T, W, torch, args.fid_seeds)
     if args.precision:
         line["precision_sweep"] = precision_sweep(T, W, torch, args.seed)
+    if args.batch:
+        line["batched_mixed"] = batch_bench(T, W, torch, args.seed)
     if args.learned:
         from paper_2203_13892_amd import learned as Lm
         model = Lm.ShapeModel.load(T)

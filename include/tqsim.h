@@ -230,6 +230,26 @@ tqs_status tqs_run_capture(tqs_plan *p, const tqs_noise *nz, void *d_workspace,
                            uint64_t ws_bytes, void *stream, uint64_t *outcomes,
                            const uint64_t *leaves, uint64_t n, double *host_amps);
 
+/* --------------------------------------------------------------- batches
+ * Several runs (each a plan with its insertion list; different circuits,
+ * qubit counts and trees) advanced together: the k-th launch of every run
+ * (a pass over a chunk of states, or the sampling of a leaf chunk) joins one
+ * combined launch, so small circuits fill the device together (the runs'
+ * trees follow Sec. 3.1 each, unchanged).  Every plan needs the same
+ * precision and tile width.  The batch keeps pointers to the plans and
+ * insertion lists, which must outlive it.  Outcomes of run i start at the
+ * sum of the leaf counts of runs 0..i-1. */
+typedef struct tqs_batch tqs_batch;
+tqs_status tqs_batch_create(tqs_plan *const *plans, const tqs_noise *const *noises, uint32_t count,
+                            tqs_batch **out);
+/* Device workspace bytes, total leaves, combined launch steps (any pointer may be NULL). */
+tqs_status tqs_batch_info(const tqs_batch *b, uint64_t *workspace_bytes, uint64_t *leaves, uint32_t *steps);
+/* Runs the batch (stream-ordered; returns with the outcomes on the host).
+ * stats (nullable) gets ms_device, ms_wall and launches. */
+tqs_status tqs_batch_run(tqs_batch *b, void *d_workspace, uint64_t ws_bytes, void *stream,
+                         uint64_t *outcomes, tqs_run_stats *stats);
+void tqs_batch_destroy(tqs_batch *b);
+
 /* ------------------------------------------------- learned tree shape ---
  * A two-hidden-layer perceptron (ReLU, FP32) that predicts, from circuit,
  * noise, shot-count and candidate-shape features, a tree shape's run time

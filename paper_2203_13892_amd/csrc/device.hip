@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -102,6 +103,51 @@ struct SampleMap {
     uint8_t lay[32];    // logical qubit -> physical position
 };
 
+// Sampling of one chunk of leaves of one plan (a segment of a launch).
+template <typename R>
+struct SampleArgs {
+    const cplx<R> *states;
+    uint64_t slot_amps;
+    const uint32_t *slots;     // state slot per leaf of the chunk
+    const uint32_t *node_ids;  // global node id per leaf of the chunk
+    double *part, *sums;
+    const double *leaf_u;
+    const uint32_t *leaf_fx;
+    uint64_t *outcomes;
+    uint64_t leaf_first;       // first leaf of the run's outcome array
+    uint32_t leaf_off, count;  // node id of leaf 0, leaves in the chunk
+    uint32_t wg_begin[3];      // first workgroup in the partials / gather / sample launches
+    uint32_t pad;
+    SampleMap m;
+};
+
+// One segment by value, or a table of segments sorted by wg_begin.
+template <typename R>
+struct SampleLaunch {
+    SampleArgs<R> one;
+    const SampleArgs<R> *segs;
+    uint32_t nseg;  // 0: `one` is the launch
+};
+
+template <typename R>
+__device__ __forceinline__ SampleArgs<R> sample_seg(const SampleLaunch<R> &sl, int stage, uint32_t wg,
+                                                    uint32_t *local) {
+    if (sl.nseg == 0) {
+        *local = wg;
+        return sl.one;
+    }
+    const SampleArgs<R> *segs = sl.segs;
+    uint32_t lo = 0, hi = sl.nseg;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (segs[mid].wg_begin[stage] <= wg) lo = mid;
+        else hi = mid;
+    }
+    const SampleArgs<R> a = segs[lo];
+    *local = wg - a.wg_begin[stage];
+    return a;
+}
+
 // Partial masses: one workgroup per (state, chunk).  Thread t reads the
 // chunk offsets o = t + 256 q (coalesced), so the offset's low 8 bits are the
 // thread's and its high bits are q.  Each thread first adds, in registers,
@@ -109,13 +155,19 @@ struct SampleMap {
 // values go to LDS at (block part of o, then the thread's non-block bits),
 // and each run of threads that share a block part is summed pairwise.
 template <typename R>
-__global__ __launch_bounds__(kThreads) void block_partials_kernel(const cplx<R> *states, uint64_t slot_amps,
-                                                                  const uint32_t *slots, SampleMap m,
-                                                                  double *part) {
+__global__ __launch_bounds__(kThreads) void block_partials_kernel(SampleLaunch<R> sl) {
     constexpr uint32_t kQ = 16;  // values per thread (chunk of at most 4096)
     __shared__ double buf[kThreads * kQ];
+    uint32_t local;
+    const SampleArgs<R> sa = sample_seg(sl, 0, blockIdx.x, &local);
+    const SampleMap &m = sa.m;
     const uint32_t nch = 1u << (m.n - m.c);
-    const uint32_t k = blockIdx.x / nch, ch = blockIdx.x % nch;
+    if (local >= sa.count * nch) return;
+    const uint32_t k = local / nch, ch = local % nch;
+    const cplx<R> *states = sa.states;
+    const uint64_t slot_amps = sa.slot_amps;
+    const uint32_t *slots = sa.slots;
+    double *part = sa.part;
     const uint32_t t = threadIdx.x;
     const uint32_t tb = m.c < 8 ? m.c : 8u, qb = m.c - tb;
     const uint32_t cm = m.cmask & ((1u << m.c) - 1u);
@@ -175,12 +227,17 @@ __global__ __launch_bounds__(kThreads) void block_partials_kernel(const cplx<R> 
 // Block masses in logical block order: block B's amplitudes lie in the
 // chunks spelled by P(B 2^b) plus any value of the in-block positions above
 // the chunk, at the same partial index in each.
-__global__ __launch_bounds__(kThreads) void block_gather_kernel(SampleMap m, const double *part,
-                                                                uint32_t count, double *sums) {
+template <typename R>
+__global__ __launch_bounds__(kThreads) void block_gather_kernel(SampleLaunch<R> sl) {
+    uint32_t local;
+    const SampleArgs<R> sa = sample_seg(sl, 1, blockIdx.x, &local);
+    const SampleMap &m = sa.m;
     const uint32_t nblocks = 1u << (m.n - m.b);
-    const uint64_t gid = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (gid >= (uint64_t)count * nblocks) return;
+    const uint64_t gid = (uint64_t)local * kThreads + threadIdx.x;
+    if (gid >= (uint64_t)sa.count * nblocks) return;
     const uint32_t k = (uint32_t)(gid / nblocks), B = (uint32_t)(gid % nblocks);
+    const double *part = sa.part;
+    double *sums = sa.sums;
     uint32_t pb = 0;
     for (uint32_t q = m.b; q < m.n; q++) pb |= ((B >> (q - m.b)) & 1u) << m.lay[q];
     uint32_t j = 0, nc = 0;
@@ -207,19 +264,26 @@ __global__ __launch_bounds__(kThreads) void block_gather_kernel(SampleMap m, con
 // index y is s's (y ^ xl) low bits, read at physical position P(.).  The
 // outcome is min { y : sum_{y' <= y} |psi_y'|^2 > u T } with FP64 sums.
 template <typename R>
-__global__ __launch_bounds__(kThreads) void sample_kernel(const cplx<R> *states, uint64_t slot_amps,
-                                                          const uint32_t *slots, const uint32_t *node_ids,
-                                                          uint32_t leaf_off, uint32_t b, uint32_t nblocks,
-                                                          const double *sums,
-                                                          const double *leaf_u, const uint32_t *leaf_fx,
-                                                          uint64_t *outcomes, uint64_t leaf_first, SampleMap m) {
+__global__ __launch_bounds__(kThreads) void sample_kernel(SampleLaunch<R> sl) {
     __shared__ double part[kThreads];
     __shared__ uint32_t ptab[3][64];  // P of the in-block index, by 6-bit digit
     __shared__ double pre[kThreads];
     __shared__ uint32_t hit;
     __shared__ double tsh, cum_sh;
-    const uint32_t k = blockIdx.x, tid = threadIdx.x;
-    const uint32_t lam = node_ids[k] - leaf_off;
+    uint32_t k;
+    const SampleArgs<R> sa = sample_seg(sl, 2, blockIdx.x, &k);
+    if (k >= sa.count) return;
+    const SampleMap &m = sa.m;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t b = m.b, nblocks = 1u << (m.n - m.b);
+    const cplx<R> *states = sa.states;
+    const uint64_t slot_amps = sa.slot_amps;
+    const uint32_t *slots = sa.slots;
+    const double *sums = sa.sums, *leaf_u = sa.leaf_u;
+    const uint32_t *leaf_fx = sa.leaf_fx;
+    uint64_t *outcomes = sa.outcomes;
+    const uint64_t leaf_first = sa.leaf_first;
+    const uint32_t lam = sa.node_ids[k] - sa.leaf_off;
     const double u = leaf_u[lam];
     const uint32_t x = leaf_fx[lam];
     const uint32_t xb = x >> b, xlow = x & ((1u << b) - 1u);
@@ -264,6 +328,7 @@ __global__ __launch_bounds__(kThreads) void sample_kernel(const cplx<R> *states,
     }
     __syncthreads();
     uint32_t BL = hit;
+    __syncthreads();  // every thread has read `hit` before thread 0 rewrites it
     if (BL == 0xFFFFFFFFu) {
         // rounding left no crossing: last block with nonzero mass
         if (tid == 0) {
@@ -274,6 +339,7 @@ __global__ __launch_bounds__(kThreads) void sample_kernel(const cplx<R> *states,
         }
         __syncthreads();
         BL = hit;
+        __syncthreads();
     }
     // cumulative mass before block BL (same order as above)
     if (tid == 0) {
@@ -389,13 +455,19 @@ struct Layout {
     uint32_t slots_total;
     std::vector<uint32_t> slot_base;  // per level
     uint32_t scratch_slot;
+    uint64_t off_states;  // first state slot
     uint64_t off_meta, off_mats, off_ops, off_passes, off_terms, off_dgates, off_frame0, off_evoff,
         off_evpos, off_evdx, off_evdz, off_leafu, off_leaffx, off_sched, off_sums, off_part, off_out, total;
     uint64_t n_sched;
 };
 
-static Layout make_layout(const tqs_plan *p, uint64_t n_events, uint64_t n_leaves_out, uint64_t n_sched) {
+// Offsets are absolute in the workspace: states from `states_at`, the
+// metadata and sampling regions from `meta_at` (by default right after the
+// states).  `total` is the end of the metadata regions.
+static Layout make_layout(const tqs_plan *p, uint64_t n_events, uint64_t n_leaves_out, uint64_t n_sched,
+                          uint64_t states_at = 0, uint64_t meta_at = ~0ull) {
     Layout L;
+    L.off_states = states_at;
     L.amp_bytes = p->prec == TQS_C64 ? 8 : 16;
     L.state_bytes = L.amp_bytes << p->n;
     uint32_t s = 0;
@@ -405,7 +477,7 @@ static Layout make_layout(const tqs_plan *p, uint64_t n_events, uint64_t n_leave
     }
     L.scratch_slot = s;
     L.slots_total = s + 1;
-    uint64_t o = align256((uint64_t)L.slots_total * L.state_bytes);
+    uint64_t o = meta_at != ~0ull ? meta_at : align256(states_at + (uint64_t)L.slots_total * L.state_bytes);
     L.off_meta = o;
     L.off_mats = o;
     o = align256(o + p->mats.size() * L.amp_bytes);
@@ -565,20 +637,20 @@ static void build_meta(const tqs_plan *p, const tqs_noise *nz, HostMeta *hm) {
 }
 
 template <typename R>
-static void launch_pass(const tqs_plan *p, const Layout &Ly, unsigned char *ws, hipStream_t s,
-                        const Task &t, uint32_t pass_idx, bool first) {
+static PassArgs<R> pass_args(const tqs_plan *p, const Layout &Ly, unsigned char *ws, const Task &t,
+                             uint32_t pass_idx, bool first) {
     const PassDesc &pd = p->passes[pass_idx];
     PassArgs<R> a;
-    a.states = reinterpret_cast<cplx<R> *>(ws);
+    a.states = reinterpret_cast<cplx<R> *>(ws + Ly.off_states);
     a.slot_amps = 1ull << p->n;
     const uint32_t *sched = reinterpret_cast<const uint32_t *>(ws + Ly.off_sched) + t.sched;
     a.node_ids = sched;
     a.src_slot = first ? sched + t.count : sched + 2 * t.count;
     a.dst_slot = sched + 2 * t.count;
     a.count = t.count;
-    const uint32_t tiles = 1u << pd.nfree;
-    a.work = t.count * tiles;
+    a.work = t.count * (1u << pd.nfree);
     a.pass_key = pass_idx << 16;
+    a.wg_begin = 0;
     a.pass = reinterpret_cast<const PassDesc *>(ws + Ly.off_passes) + pass_idx;
     a.ops = reinterpret_cast<const OpDesc *>(ws + Ly.off_ops);
     a.mats = reinterpret_cast<const cplx<R> *>(ws + Ly.off_mats);
@@ -589,23 +661,27 @@ static void launch_pass(const tqs_plan *p, const Layout &Ly, unsigned char *ws, 
     a.meta.ev_dz = reinterpret_cast<const uint32_t *>(ws + Ly.off_evdz);
     a.terms = reinterpret_cast<const DiagTerm *>(ws + Ly.off_terms);
     a.dgates = reinterpret_cast<const DiagGate *>(ws + Ly.off_dgates);
-    const uint32_t grid = (a.work + 7u) & ~7u;
-    // one wave per workgroup; the register-qubit count is a compile-time tile width
-    const bool d2 = pd.has_d2 != 0;
-    const size_t lds = 0;
-#define TQS_LAUNCH(RB)                                                                        \
-    do {                                                                                       \
-        if (d2) hipLaunchKernelGGL((pass_kernel<R, RB, true>), dim3(grid), dim3(64), lds, s, a); \
-        else hipLaunchKernelGGL((pass_kernel<R, RB, false>), dim3(grid), dim3(64), lds, s, a);   \
+    return a;
+}
+
+// One wave per workgroup; the register-qubit count is a compile-time tile
+// width, D2 the variant with 4x4 ops.
+template <typename R>
+static void launch_pass_kernel(uint32_t reg_bits, bool d2, const PassLaunch<R> &pl, hipStream_t s) {
+    const uint32_t grid = (pl.total + 7u) & ~7u;
+#define TQS_LAUNCH(RB)                                                                          \
+    do {                                                                                         \
+        if (d2) hipLaunchKernelGGL((pass_kernel<R, RB, true>), dim3(grid), dim3(64), 0, s, pl);  \
+        else hipLaunchKernelGGL((pass_kernel<R, RB, false>), dim3(grid), dim3(64), 0, s, pl);    \
     } while (0)
     if constexpr (sizeof(R) == 4) {
-        switch (p->reg_bits) {
+        switch (reg_bits) {
             case 4: TQS_LAUNCH(4); break;
             case 5: TQS_LAUNCH(5); break;
             default: TQS_LAUNCH(6); break;
         }
     } else {
-        switch (p->reg_bits) {
+        switch (reg_bits) {
             case 4: TQS_LAUNCH(4); break;
             default: TQS_LAUNCH(5); break;
         }
@@ -613,6 +689,16 @@ static void launch_pass(const tqs_plan *p, const Layout &Ly, unsigned char *ws, 
 #undef TQS_LAUNCH
 }
 
+template <typename R>
+static void launch_pass(const tqs_plan *p, const Layout &Ly, unsigned char *ws, hipStream_t s,
+                        const Task &t, uint32_t pass_idx, bool first) {
+    PassLaunch<R> pl;
+    std::memset(&pl, 0, sizeof pl);
+    pl.one = pass_args<R>(p, Ly, ws, t, pass_idx, first);
+    pl.nseg = 0;
+    pl.total = pl.one.work;
+    launch_pass_kernel<R>(p->reg_bits, p->passes[pass_idx].has_d2 != 0, pl, s);
+}
 
 static SampleMap sample_map(const tqs_plan *p) {
     SampleMap m;
@@ -638,26 +724,51 @@ static uint32_t to_logical(const tqs_plan *p, uint32_t x) {
 }
 
 template <typename R>
+static SampleArgs<R> sample_args(const tqs_plan *p, const Layout &Ly, unsigned char *ws, const Task &t,
+                                 uint64_t leaf_first) {
+    SampleArgs<R> a;
+    std::memset(&a, 0, sizeof a);
+    const uint32_t *sched = reinterpret_cast<const uint32_t *>(ws + Ly.off_sched) + t.sched;
+    a.states = reinterpret_cast<const cplx<R> *>(ws + Ly.off_states);
+    a.slot_amps = 1ull << p->n;
+    a.slots = sched + 2 * t.count;
+    a.node_ids = sched;
+    a.part = reinterpret_cast<double *>(ws + Ly.off_part);
+    a.sums = reinterpret_cast<double *>(ws + Ly.off_sums);
+    a.leaf_u = reinterpret_cast<const double *>(ws + Ly.off_leafu);
+    a.leaf_fx = reinterpret_cast<const uint32_t *>(ws + Ly.off_leaffx);
+    a.outcomes = reinterpret_cast<uint64_t *>(ws + Ly.off_out);
+    a.leaf_first = leaf_first;
+    a.leaf_off = (uint32_t)p->level_offset.back();
+    a.count = t.count;
+    a.m = sample_map(p);
+    return a;
+}
+
+// Workgroups of the partials / gather / sample launches for one segment.
+template <typename R>
+static void sample_grid(const SampleArgs<R> &a, uint32_t g[3]) {
+    g[0] = a.count << (a.m.n - a.m.c);
+    g[1] = (uint32_t)((((uint64_t)a.count << (a.m.n - a.m.b)) + kThreads - 1) / kThreads);
+    g[2] = a.count;
+}
+
+template <typename R>
+static void launch_sample_kernels(const SampleLaunch<R> &sl, const uint32_t grid[3], hipStream_t s) {
+    hipLaunchKernelGGL(block_partials_kernel<R>, dim3(grid[0]), dim3(kThreads), 0, s, sl);
+    hipLaunchKernelGGL(block_gather_kernel<R>, dim3(grid[1]), dim3(kThreads), 0, s, sl);
+    hipLaunchKernelGGL(sample_kernel<R>, dim3(grid[2]), dim3(kThreads), 0, s, sl);
+}
+
+template <typename R>
 static void launch_sample(const tqs_plan *p, const Layout &Ly, unsigned char *ws, hipStream_t s,
                           const Task &t, uint64_t leaf_first) {
-    const SampleMap m = sample_map(p);
-    const uint32_t b = p->sample_b;
-    const uint32_t nblocks = 1u << (p->n - b);
-    const uint32_t *sched = reinterpret_cast<const uint32_t *>(ws + Ly.off_sched) + t.sched;
-    const cplx<R> *st = reinterpret_cast<const cplx<R> *>(ws);
-    double *sums = reinterpret_cast<double *>(ws + Ly.off_sums);
-    double *part = reinterpret_cast<double *>(ws + Ly.off_part);
-    const uint32_t leaf_off = (uint32_t)p->level_offset.back();
-    hipLaunchKernelGGL(block_partials_kernel<R>, dim3(t.count << (p->n - m.c)), dim3(kThreads), 0, s, st,
-                       1ull << p->n, sched + 2 * t.count, m, part);
-    const uint64_t nsum = (uint64_t)t.count * nblocks;
-    hipLaunchKernelGGL(block_gather_kernel, dim3((uint32_t)((nsum + kThreads - 1) / kThreads)), dim3(kThreads),
-                       0, s, m, part, t.count, sums);
-    hipLaunchKernelGGL(sample_kernel<R>, dim3(t.count), dim3(kThreads), 0, s, st, 1ull << p->n,
-                       sched + 2 * t.count, sched, leaf_off, b, nblocks, sums,
-                       reinterpret_cast<const double *>(ws + Ly.off_leafu),
-                       reinterpret_cast<const uint32_t *>(ws + Ly.off_leaffx),
-                       reinterpret_cast<uint64_t *>(ws + Ly.off_out), leaf_first, m);
+    SampleLaunch<R> sl;
+    std::memset(&sl, 0, sizeof sl);
+    sl.one = sample_args<R>(p, Ly, ws, t, leaf_first);
+    uint32_t g[3];
+    sample_grid(sl.one, g);
+    launch_sample_kernels(sl, g, s);
 }
 
 static tqs_status check_noise(const tqs_plan *p, const tqs_noise *nz) {
@@ -681,6 +792,33 @@ struct Capture {
     uint64_t n = 0;
     double *amps = nullptr;
 };
+
+// The plan data, noise metadata and schedule of one run, written into a
+// host image of the workspace whose first byte is workspace offset `base`.
+template <typename R>
+static void pack_meta(const tqs_plan *p, const tqs_noise *nz, const HostMeta &hm,
+                      const std::vector<uint32_t> &sched, const Layout &Ly, unsigned char *hb, uint64_t base) {
+    auto put = [&](uint64_t off, const void *src, size_t bytes) {
+        if (bytes) std::memcpy(hb + (off - base), src, bytes);
+    };
+    {
+        std::vector<cplx<R>> mats(p->mats.size());
+        for (size_t i = 0; i < mats.size(); i++) mats[i] = {(R)p->mats[i].real(), (R)p->mats[i].imag()};
+        put(Ly.off_mats, mats.data(), mats.size() * sizeof(cplx<R>));
+    }
+    put(Ly.off_ops, p->ops.data(), p->ops.size() * sizeof(OpDesc));
+    put(Ly.off_passes, p->passes.data(), p->passes.size() * sizeof(PassDesc));
+    put(Ly.off_terms, p->terms.data(), p->terms.size() * sizeof(DiagTerm));
+    put(Ly.off_dgates, p->dgates.data(), p->dgates.size() * sizeof(DiagGate));
+    put(Ly.off_frame0, hm.frame0.data(), hm.frame0.size() * 4);
+    put(Ly.off_evoff, hm.ev_off.data(), hm.ev_off.size() * 4);
+    put(Ly.off_evpos, hm.ev_pos.data(), hm.ev_pos.size() * 4);
+    put(Ly.off_evdx, hm.ev_dx.data(), hm.ev_dx.size() * 4);
+    put(Ly.off_evdz, hm.ev_dz.data(), hm.ev_dz.size() * 4);
+    put(Ly.off_leafu, nz->leaf_u.data(), nz->leaf_u.size() * 8);
+    put(Ly.off_leaffx, hm.leaf_fx.data(), hm.leaf_fx.size() * 4);
+    put(Ly.off_sched, sched.data(), sched.size() * 4);
+}
 
 template <typename R>
 static tqs_status run_t(tqs_plan *p, const tqs_noise *nz, unsigned char *ws, uint64_t ws_bytes,
@@ -714,26 +852,7 @@ static tqs_status run_t(tqs_plan *p, const tqs_noise *nz, unsigned char *ws, uin
 
     // pack the metadata exactly as laid out in the workspace
     std::vector<unsigned char> hb(Ly.off_sums - Ly.off_meta, 0);
-    auto put = [&](uint64_t off, const void *src, size_t bytes) {
-        if (bytes) std::memcpy(hb.data() + (off - Ly.off_meta), src, bytes);
-    };
-    {
-        std::vector<cplx<R>> mats(p->mats.size());
-        for (size_t i = 0; i < mats.size(); i++) mats[i] = {(R)p->mats[i].real(), (R)p->mats[i].imag()};
-        put(Ly.off_mats, mats.data(), mats.size() * sizeof(cplx<R>));
-    }
-    put(Ly.off_ops, p->ops.data(), p->ops.size() * sizeof(OpDesc));
-    put(Ly.off_passes, p->passes.data(), p->passes.size() * sizeof(PassDesc));
-    put(Ly.off_terms, p->terms.data(), p->terms.size() * sizeof(DiagTerm));
-    put(Ly.off_dgates, p->dgates.data(), p->dgates.size() * sizeof(DiagGate));
-    put(Ly.off_frame0, hm.frame0.data(), hm.frame0.size() * 4);
-    put(Ly.off_evoff, hm.ev_off.data(), hm.ev_off.size() * 4);
-    put(Ly.off_evpos, hm.ev_pos.data(), hm.ev_pos.size() * 4);
-    put(Ly.off_evdx, hm.ev_dx.data(), hm.ev_dx.size() * 4);
-    put(Ly.off_evdz, hm.ev_dz.data(), hm.ev_dz.size() * 4);
-    put(Ly.off_leafu, nz->leaf_u.data(), nz->leaf_u.size() * 8);
-    put(Ly.off_leaffx, hm.leaf_fx.data(), hm.leaf_fx.size() * 4);
-    put(Ly.off_sched, sched.data(), sched.size() * 4);
+    pack_meta<R>(p, nz, hm, sched, Ly, hb.data(), Ly.off_meta);
 
     size_t ev_i = 0;
     hipEvent_t e_begin = nullptr, e_end = nullptr;
@@ -797,8 +916,8 @@ static tqs_status run_t(tqs_plan *p, const tqs_noise *nz, unsigned char *ws, uin
                         const Frame &f = hm.leaf_frame[lam];
                         const uint32_t slot = Ly.slot_base[L - 1] + i;
                         const uint64_t amps = 1ull << p->n;
-                        const cplx<R> *in = reinterpret_cast<const cplx<R> *>(ws) + (uint64_t)slot * amps;
-                        cplx<R> *out = reinterpret_cast<cplx<R> *>(ws) + (uint64_t)Ly.scratch_slot * amps;
+                        const cplx<R> *in = reinterpret_cast<const cplx<R> *>(ws + Ly.off_states) + (uint64_t)slot * amps;
+                        cplx<R> *out = reinterpret_cast<cplx<R> *>(ws + Ly.off_states) + (uint64_t)Ly.scratch_slot * amps;
                         hipLaunchKernelGGL(frame_apply_kernel<R>, dim3((uint32_t)((amps + kThreads - 1) / kThreads)),
                                            dim3(kThreads), 0, s, in, out, amps, f.x, f.z, f.k, sample_map(p));
                         HIP_TRY(hipGetLastError(), "frame_apply launch");
@@ -858,6 +977,152 @@ static tqs_status run_any(tqs_plan *p, const tqs_noise *nz, void *ws, uint64_t w
     if (p->prec == TQS_C64)
         return run_t<float>(p, nz, (unsigned char *)ws, ws_bytes, s, first, last, outcomes, stats, cap);
     return run_t<double>(p, nz, (unsigned char *)ws, ws_bytes, s, first, last, outcomes, stats, cap);
+}
+
+// ------------------------------------------------------------- batches --
+// Several independent runs (different circuits, trees, noise) advanced
+// together: run i's k-th launch (a pass over a chunk of states, or the
+// sampling of a leaf chunk) goes into step k, and each step is one pass
+// launch and one sampling launch whose segments are the runs' launches, so
+// small circuits share the device instead of queueing one small grid after
+// another.  Within a run the launches keep their order; runs never share
+// state slots.
+struct BatchOp {
+    uint32_t kind;  // 0 pass, 1 sampling
+    uint32_t task, pass, first;
+};
+
+struct BatchItem {
+    tqs_plan *p = nullptr;
+    const tqs_noise *nz = nullptr;
+    Layout Ly;
+    HostMeta hm;
+    std::vector<Task> tasks;
+    std::vector<uint32_t> sched;
+    std::vector<BatchOp> ops;
+    uint64_t leaf_base = 0;
+};
+
+}  // namespace tqs
+
+struct tqs_batch {
+    tqs_precision prec = TQS_C64;
+    uint32_t reg_bits = 0;
+    std::vector<tqs::BatchItem> items;
+    uint32_t steps = 0;
+    std::vector<uint32_t> npass, nsamp;  // segments per step
+    uint64_t table_at = 0, table_bytes = 0, total = 0, leaves = 0;
+    std::vector<void *> events;
+};
+
+namespace tqs {
+
+template <typename R>
+static tqs_status batch_run_t(tqs_batch *B, unsigned char *ws, uint64_t ws_bytes, hipStream_t s,
+                              uint64_t *outcomes, tqs_run_stats *stats) {
+    const auto t0 = std::chrono::steady_clock::now();
+    if (!ws) return fail(TQS_E_WORKSPACE, "workspace is NULL");
+    if (((uintptr_t)ws) & 255) return fail(TQS_E_WORKSPACE, "workspace must be 256-byte aligned");
+    if (ws_bytes < B->total)
+        return fail(TQS_E_WORKSPACE, "workspace has %llu bytes, the batch needs %llu",
+                    (unsigned long long)ws_bytes, (unsigned long long)B->total);
+    if (!outcomes) return fail(TQS_E_ARG, "outcomes is NULL");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (stats) {
+        while (B->events.size() < 2) {
+            hipEvent_t e = nullptr;
+            if (hipEventCreate(&e) != hipSuccess) return fail(TQS_E_HIP, "hipEventCreate failed");
+            B->events.push_back((void *)e);
+        }
+        e0 = (hipEvent_t)B->events[0];
+        e1 = (hipEvent_t)B->events[1];
+        HIP_TRY(hipEventRecord(e0, s), "hipEventRecord");
+    }
+    // per-run metadata
+    std::vector<std::vector<unsigned char>> hbs(B->items.size());
+    for (size_t i = 0; i < B->items.size(); i++) {
+        BatchItem &it = B->items[i];
+        hbs[i].assign(it.Ly.off_sums - it.Ly.off_meta, 0);
+        pack_meta<R>(it.p, it.nz, it.hm, it.sched, it.Ly, hbs[i].data(), it.Ly.off_meta);
+        HIP_TRY(hipMemcpyAsync(ws + it.Ly.off_meta, hbs[i].data(), hbs[i].size(), hipMemcpyHostToDevice, s),
+                "metadata upload");
+    }
+    // segment tables of every step
+    std::vector<unsigned char> tb(B->table_bytes, 0);
+    std::vector<uint64_t> pass_at(B->steps), samp_at(B->steps);
+    std::vector<uint32_t> pass_total(B->steps, 0), pass_d2(B->steps, 0);
+    std::vector<std::array<uint32_t, 3>> samp_total(B->steps, {0, 0, 0});
+    {
+        uint64_t o = 0;
+        for (uint32_t k = 0; k < B->steps; k++) {
+            pass_at[k] = o;
+            PassArgs<R> *pa = reinterpret_cast<PassArgs<R> *>(tb.data() + o);
+            o += align256((uint64_t)B->npass[k] * sizeof(PassArgs<R>));
+            samp_at[k] = o;
+            SampleArgs<R> *sa = reinterpret_cast<SampleArgs<R> *>(tb.data() + o);
+            o += align256((uint64_t)B->nsamp[k] * sizeof(SampleArgs<R>));
+            uint32_t np = 0, ns = 0;
+            for (BatchItem &it : B->items) {
+                if (k >= it.ops.size()) continue;
+                const BatchOp &op = it.ops[k];
+                const Task &t = it.tasks[op.task];
+                if (op.kind == 0) {
+                    PassArgs<R> a = pass_args<R>(it.p, it.Ly, ws, t, op.pass, op.first != 0);
+                    a.wg_begin = pass_total[k];
+                    pass_total[k] += a.work;
+                    if (it.p->passes[op.pass].has_d2) pass_d2[k] = 1;
+                    pa[np++] = a;
+                } else {
+                    SampleArgs<R> a = sample_args<R>(it.p, it.Ly, ws, t, 0);
+                    uint32_t g[3];
+                    sample_grid(a, g);
+                    for (int q = 0; q < 3; q++) {
+                        a.wg_begin[q] = samp_total[k][q];
+                        samp_total[k][q] += g[q];
+                    }
+                    sa[ns++] = a;
+                }
+            }
+        }
+    }
+    HIP_TRY(hipMemcpyAsync(ws + B->table_at, tb.data(), tb.size(), hipMemcpyHostToDevice, s), "table upload");
+    for (uint32_t k = 0; k < B->steps; k++) {
+        if (B->npass[k]) {
+            PassLaunch<R> pl;
+            std::memset(&pl, 0, sizeof pl);
+            pl.segs = reinterpret_cast<const PassArgs<R> *>(ws + B->table_at + pass_at[k]);
+            pl.nseg = B->npass[k];
+            pl.total = pass_total[k];
+            launch_pass_kernel<R>(B->reg_bits, pass_d2[k] != 0, pl, s);
+        }
+        if (B->nsamp[k]) {
+            SampleLaunch<R> sl;
+            std::memset(&sl, 0, sizeof sl);
+            sl.segs = reinterpret_cast<const SampleArgs<R> *>(ws + B->table_at + samp_at[k]);
+            sl.nseg = B->nsamp[k];
+            const uint32_t g[3] = {samp_total[k][0], samp_total[k][1], samp_total[k][2]};
+            launch_sample_kernels(sl, g, s);
+        }
+        HIP_TRY(hipGetLastError(), "kernel launch");
+    }
+    for (BatchItem &it : B->items)
+        HIP_TRY(hipMemcpyAsync(outcomes + it.leaf_base, ws + it.Ly.off_out, it.p->n_leaves * 8,
+                               hipMemcpyDeviceToHost, s),
+                "outcome download");
+    if (stats) HIP_TRY(hipEventRecord(e1, s), "hipEventRecord");
+    HIP_TRY(hipStreamSynchronize(s), "stream synchronize");
+    if (stats) {
+        std::memset(stats, 0, sizeof *stats);
+        float ms = 0;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+        stats->ms_device = ms;
+        uint64_t launches = 0;
+        for (uint32_t k = 0; k < B->steps; k++) launches += (B->npass[k] ? 1 : 0) + (B->nsamp[k] ? 3 : 0);
+        stats->launches = launches;
+        stats->ms_wall =
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return TQS_OK;
 }
 
 }  // namespace tqs
@@ -958,3 +1223,95 @@ tqs_status tqs_probe_copy(void *d_workspace, uint64_t bytes, uint32_t reps, void
 }
 
 }  // extern "C"
+
+extern "C" tqs_status tqs_batch_create(tqs_plan *const *plans, const tqs_noise *const *noises, uint32_t count,
+                                       tqs_batch **out) {
+    TQS_GUARD_BEGIN
+    if (!out) return fail(TQS_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (!plans || !noises || !count) return fail(TQS_E_ARG, "empty batch");
+    tqs_batch *B = new tqs_batch;
+    B->prec = plans[0] ? plans[0]->prec : TQS_C64;
+    B->reg_bits = plans[0] ? plans[0]->reg_bits : 0;
+    uint64_t states = 0;
+    B->items.resize(count);
+    for (uint32_t i = 0; i < count; i++) {
+        tqs_plan *p = plans[i];
+        if (!p) {
+            delete B;
+            return fail(TQS_E_ARG, "plan %u is NULL", i);
+        }
+        tqs_status st = check_noise(p, noises[i]);
+        if (st) {
+            delete B;
+            return st;
+        }
+        if (p->prec != B->prec || p->reg_bits != B->reg_bits) {
+            delete B;
+            return fail(TQS_E_ARG, "plan %u: a batch needs one precision and one tile width", i);
+        }
+        BatchItem &it = B->items[i];
+        it.p = p;
+        it.nz = noises[i];
+        build_meta(p, it.nz, &it.hm);
+        Layout Ly0 = make_layout(p, it.nz->ev_gate.size(), p->n_leaves, 0);
+        build_schedule(p, 0, p->arity[0], &it.tasks, &it.sched, Ly0.slot_base);
+        it.Ly = make_layout(p, it.nz->ev_gate.size(), p->n_leaves, it.sched.size(), states, 0);
+        states = align256(states + (uint64_t)it.Ly.slots_total * it.Ly.state_bytes);
+        it.leaf_base = B->leaves;
+        B->leaves += p->n_leaves;
+        const uint32_t L = (uint32_t)p->arity.size();
+        for (uint32_t ti = 0; ti < it.tasks.size(); ti++) {
+            const Task &t = it.tasks[ti];
+            const tqs::Level &lv = p->levels[t.level];
+            for (uint32_t k = 0; k < lv.pass_count; k++) it.ops.push_back({0, ti, lv.pass_begin + k, k == 0 ? 1u : 0u});
+            if (t.level == L - 1) it.ops.push_back({1, ti, 0, 0});
+        }
+        B->steps = std::max<uint32_t>(B->steps, (uint32_t)it.ops.size());
+    }
+    // metadata regions after all states, then the segment tables
+    uint64_t o = states;
+    for (BatchItem &it : B->items) {
+        it.Ly = make_layout(it.p, it.nz->ev_gate.size(), it.p->n_leaves, it.sched.size(), it.Ly.off_states, o);
+        o = it.Ly.total;
+    }
+    B->npass.assign(B->steps, 0);
+    B->nsamp.assign(B->steps, 0);
+    for (BatchItem &it : B->items)
+        for (uint32_t k = 0; k < it.ops.size(); k++) (it.ops[k].kind == 0 ? B->npass : B->nsamp)[k]++;
+    const uint64_t pa = B->prec == TQS_C64 ? sizeof(PassArgs<float>) : sizeof(PassArgs<double>);
+    const uint64_t sa = B->prec == TQS_C64 ? sizeof(SampleArgs<float>) : sizeof(SampleArgs<double>);
+    B->table_at = align256(o);
+    B->table_bytes = 0;
+    for (uint32_t k = 0; k < B->steps; k++)
+        B->table_bytes += align256(B->npass[k] * pa) + align256(B->nsamp[k] * sa);
+    B->total = B->table_at + B->table_bytes;
+    *out = B;
+    return TQS_OK;
+    TQS_GUARD_END
+}
+
+extern "C" tqs_status tqs_batch_info(const tqs_batch *b, uint64_t *workspace_bytes, uint64_t *leaves,
+                                     uint32_t *steps) {
+    if (!b) return fail(TQS_E_ARG, "batch is NULL");
+    if (workspace_bytes) *workspace_bytes = b->total;
+    if (leaves) *leaves = b->leaves;
+    if (steps) *steps = b->steps;
+    return TQS_OK;
+}
+
+extern "C" tqs_status tqs_batch_run(tqs_batch *b, void *d_workspace, uint64_t ws_bytes, void *stream,
+                                    uint64_t *outcomes, tqs_run_stats *stats) {
+    TQS_GUARD_BEGIN
+    if (!b) return fail(TQS_E_ARG, "batch is NULL");
+    if (b->prec == TQS_C64)
+        return batch_run_t<float>(b, (unsigned char *)d_workspace, ws_bytes, (hipStream_t)stream, outcomes, stats);
+    return batch_run_t<double>(b, (unsigned char *)d_workspace, ws_bytes, (hipStream_t)stream, outcomes, stats);
+    TQS_GUARD_END
+}
+
+extern "C" void tqs_batch_destroy(tqs_batch *b) {
+    if (!b) return;
+    for (void *e : b->events) (void)hipEventDestroy((hipEvent_t)e);
+    delete b;
+}

@@ -88,6 +88,7 @@ __device__ __forceinline__ TermU<A> load_term(kptr<DiagTerm> p) {
     return t;
 }
 
+// One pass over `count` states of one plan (a segment of a launch).
 template <typename R>
 struct PassArgs {
     cplx<R> *states;
@@ -96,14 +97,25 @@ struct PassArgs {
     const uint32_t *src_slot;
     const uint32_t *dst_slot;
     uint32_t count;
-    uint32_t work;  // count * tiles (unpadded)
+    uint32_t work;      // count * tiles (unpadded)
     uint32_t pass_key;
+    uint32_t wg_begin;  // first workgroup of this segment in the launch
     const PassDesc *pass;
     const OpDesc *ops;
     const cplx<R> *mats;
     const DiagTerm *terms;
     const DiagGate *dgates;
     NodeMeta meta;
+};
+
+// A launch: one segment passed by value, or a table of segments (passes
+// of different plans, for batches) in device memory, sorted by wg_begin.
+template <typename R>
+struct PassLaunch {
+    PassArgs<R> one;
+    const PassArgs<R> *segs;
+    uint32_t nseg;   // 0: `one` is the launch
+    uint32_t total;  // workgroups with work
 };
 
 template <typename R>
@@ -698,10 +710,27 @@ struct PassWaves {
 };
 
 template <typename R, int RB, bool D2>
-__global__ __launch_bounds__(64, (PassWaves<R, RB>::value)) void pass_kernel(PassArgs<R> a) {
+__global__ __launch_bounds__(64, (PassWaves<R, RB>::value)) void pass_kernel(PassLaunch<R> pl) {
     constexpr int NJ = 1 << RB;
     const uint32_t nwg = gridDim.x, bid = blockIdx.x;
-    const uint32_t w = (bid & 7u) * (nwg >> 3) + (bid >> 3);
+    const uint32_t wall = (bid & 7u) * (nwg >> 3) + (bid >> 3);
+    if (wall >= pl.total) return;
+    PassArgs<R> a;
+    uint32_t w = wall;
+    if (pl.nseg == 0) {
+        a = pl.one;
+    } else {
+        // the last segment starting at or before this workgroup
+        const kptr<PassArgs<R>> segs = kconst(pl.segs);
+        uint32_t lo = 0, hi = pl.nseg;
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (segs[mid].wg_begin <= wall) lo = mid;
+            else hi = mid;
+        }
+        a = kload(segs + lo);
+        w = wall - a.wg_begin;
+    }
     if (w >= a.work) return;
     const uint32_t traj = w % a.count, tile = w / a.count;
     const uint32_t L = threadIdx.x;

@@ -63,6 +63,10 @@ SIGNATURES = {
     "tqs_histogram": (i32, [P(u64), u64, P(u64), P(u64), P(u64)]),
     "tqs_probe_copy": (i32, [vp, u64, u32, vp, P(dbl)]),
     "tqs_plan_describe": (i32, [vp, C.c_char_p, u64, P(u64)]),
+    "tqs_batch_create": (i32, [P(vp), P(vp), u32, P(vp)]),
+    "tqs_batch_info": (i32, [vp, P(u64), P(u64), P(u32)]),
+    "tqs_batch_run": (i32, [vp, vp, u64, vp, P(u64), P(TqsRunStats)]),
+    "tqs_batch_destroy": (None, [vp]),
     "tqs_mlp_param_count": (u64, [u32, u32, u32]),
     "tqs_mlp_scratch_floats": (u64, [u32, u32, u32, u32]),
     "tqs_mlp_forward": (i32, [vp, u32, u32, u32, vp, u32, vp, vp, vp]),
@@ -340,6 +344,46 @@ def probe_copy(nbytes: int, reps: int = 10, stream=None) -> float:
     g = dbl()
     _check(lib.tqs_probe_copy(vp(ws.ptr), nbytes, reps, _stream(stream), C.byref(g)))
     return g.value
+
+
+class Batch:
+    """Owned tqs_batch: several (plan, insertion list) runs advanced together."""
+
+    def __init__(self, plans, noises):
+        if len(plans) != len(noises) or not plans:
+            raise ValueError("need one insertion list per plan")
+        self._keep = (list(plans), list(noises))
+        ph = (vp * len(plans))(*[p.h.value for p in plans])
+        nh = (vp * len(noises))(*[n.h.value for n in noises])
+        h = vp()
+        _check(lib.tqs_batch_create(ph, nh, len(plans), C.byref(h)))
+        self.h = h
+        self.leaf_counts = [p.n_leaves for p in plans]
+
+    def info(self):
+        ws, lv, st = u64(), u64(), u32()
+        _check(lib.tqs_batch_info(self.h, C.byref(ws), C.byref(lv), C.byref(st)))
+        return {"workspace_bytes": ws.value, "leaves": lv.value, "steps": st.value}
+
+    def run(self, workspace=None, stream=None, stats=False):
+        """Per-run outcome arrays (and the stats dict with ``stats``)."""
+        info = self.info()
+        if workspace is None:
+            workspace = Workspace(info["workspace_bytes"])
+        out = np.zeros(info["leaves"], np.uint64)
+        st = TqsRunStats() if stats else None
+        _check(lib.tqs_batch_run(self.h, vp(workspace.ptr), workspace.nbytes, _stream(stream), _ptr(out, u64),
+                                 C.byref(st) if st is not None else None))
+        parts, o = [], 0
+        for k in self.leaf_counts:
+            parts.append(out[o:o + k])
+            o += k
+        return (parts, st.as_dict()) if stats else parts
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            lib.tqs_batch_destroy(h)
 
 
 class Perceptron:

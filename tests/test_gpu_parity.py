@@ -426,3 +426,35 @@ def test_learned_shape_against_partition_heuristic(T):
     # far outside the training range: the heuristic decides
     big = W.brickwall(30, 4, seed=1).with_noise(1e-3, 1e-2)
     assert Lm.choose_shape(T, model, big, shots)[1] == "dcp"
+
+
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+def test_batch_equals_separate_runs(T, prec):
+    # runs of different circuits, qubit counts, trees and noise advanced
+    # together give exactly the outcomes of the same runs made one by one;
+    # the small ones also match the oracle
+    rng = np.random.default_rng(12)
+    specs = [(W.qft(10).with_depolarizing(1e-2, 5e-2), ([40], None)),
+             (W.ghz(12).with_depolarizing(1e-2, 5e-2), ([4, 4, 3], None)),
+             (W.brickwall(14, 8, seed=3).with_noise(0.0, 3e-2, gamma=2e-2), ([8, 8], None)),
+             (W.qaoa(12, 2, seed=5).with_depolarizing(1e-2, 3e-2), ([6, 5], None)),
+             (W.random_circuit(11, 60, seed=9).with_depolarizing(2e-2, 5e-2), ([3, 3, 3, 3], None))]
+    plans, noises, wcs, trees = [], [], [], []
+    for i, (wc, (A, _)) in enumerate(specs):
+        G = len(wc)
+        tree = (A, [round(j * G / len(A)) for j in range(len(A) + 1)])
+        c = T.Circuit.from_workload(wc)
+        plans.append(T.Plan(c, tree, prec, {"chunk_states": 7}))
+        noises.append(T.Noise.sample(c, tree, 20 + i))
+        wcs.append(wc)
+        trees.append(tree)
+    b = T.Batch(plans, noises)
+    assert b.info()["steps"] > 1
+    outs = b.run()
+    for i in range(len(specs)):
+        want = T.run(plans[i], noises[i])
+        assert np.array_equal(outs[i], want), i
+    # the first run against the oracle (boundary leaves counted, not failed)
+    onz = oracle.sample_noise(wcs[0].gates, trees[0], 20)
+    oout, ost = oracle.run_leaves(wcs[0].n, wcs[0].gates, trees[0], onz, states=True)
+    check_outcomes(outs[0], oout, ost, onz.leaf_u, DELTA[prec])
