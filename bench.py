@@ -175,56 +175,101 @@ def batch_workload(W, count=512):
 
 def batch_bench(T, W, torch, seed, shots=2048, budget_gib=32):
     """The mixed workload per-shot at 2048 shots each: one run after another
-    against batches (runs grouped in qubit order up to a workspace budget,
-    each batch advancing its runs together)."""
+    (default tuning) against batches (runs grouped in qubit order up to a
+    workspace budget, each batch advancing its runs together), with the
+    default tuning and with the tile width and pass bound autotuned per
+    family and size; also the 12-16 qubit runs alone, where launches, not
+    bytes, dominate."""
     import numpy as np
+    from paper_2203_13892_amd import autotune as AT
     circs = batch_workload(W)
-    items = []
-    for i, (name, wc) in enumerate(circs):
-        G = len(wc)
-        c = T.Circuit.from_workload(wc)
-        tree = ([shots], [0, G])
-        # live states per run: about 256 MiB of states, at most 512
-        chunk = int(max(1, min(512, (256 << 20) // (8 << wc.n))))
-        plan = T.Plan(c, tree, "c64", {"chunk_states": chunk})
-        items.append((wc.n, plan, T.Noise.sample(c, tree, seed + i)))
-    # one after another
-    ws = T.Workspace(max(p.workspace_bytes(nz) for _, p, nz in items))
-    for _, p, nz in items[:4]:
-        T.run(p, nz, ws)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    seq = [T.run(p, nz, ws) for _, p, nz in items]
-    t_seq = time.perf_counter() - t0
-    del ws
-    # batches in qubit order
-    order = sorted(range(len(items)), key=lambda k: items[k][0])
-    groups, cur, cur_b = [], [], 0
-    for k in order:
-        b = items[k][1].workspace_bytes(items[k][2])
-        if cur and cur_b + b > (budget_gib << 30):
-            groups.append(cur)
-            cur, cur_b = [], 0
-        cur.append(k)
-        cur_b += b
-    groups.append(cur)
-    batches = [T.Batch([items[k][1] for k in g], [items[k][2] for k in g]) for g in groups]
-    wsb = T.Workspace(max(b.info()["workspace_bytes"] for b in batches))
-    batches[0].run(wsb)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    res = [b.run(wsb) for b in batches]
-    t_bat = time.perf_counter() - t0
-    same = all(np.array_equal(res[gi][j], seq[k]) for gi, g in enumerate(groups) for j, k in enumerate(g))
-    total = shots * len(items)
-    print("# batch: %d runs, sequential %.2f s (%.0f shots/s), batched %.2f s in %d batches (%.0f shots/s), "
-          "outcomes identical %s" % (len(items), t_seq, total / t_seq, t_bat, len(batches), total / t_bat, same),
-          file=sys.stderr, flush=True)
-    return {"workload": "512 circuits of 12-22 qubits (qft, ghz, qaoa p=2, brick-wall), 2048 shots each, "
-                        "per-shot, depolarizing(1e-3,1e-2)",
-            "runs": len(items), "shots_total": total, "sequential_s": t_seq, "batched_s": t_bat,
-            "batches": len(batches), "sequential_shots_per_s": total / t_seq,
-            "batched_shots_per_s": total / t_bat, "outcomes_identical": bool(same)}
+
+    def build(tunings):
+        items = []
+        for i, (name, wc) in enumerate(circs):
+            G = len(wc)
+            c = T.Circuit.from_workload(wc)
+            tree = ([shots], [0, G])
+            tun = dict(tunings.get(name.split("_")[0], {}))
+            # live states per run: about 256 MiB of states, at most 512
+            tun["chunk_states"] = int(max(1, min(512, (256 << 20) // (8 << wc.n))))
+            plan = T.Plan(c, tree, "c64", tun)
+            items.append((wc.n, plan, T.Noise.sample(c, tree, seed + i), tun.get("tile_qubits", 11)))
+        return items
+
+    def sequential(items):
+        ws = T.Workspace(max(p.workspace_bytes(nz) for _, p, nz, _ in items))
+        for _, p, nz, _ in items[:4]:
+            T.run(p, nz, ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = [T.run(p, nz, ws) for _, p, nz, _ in items]
+        return time.perf_counter() - t0, out
+
+    def batched(items):
+        order = sorted(range(len(items)), key=lambda k: (items[k][3], items[k][0]))
+        groups, cur, cur_b, cur_t = [], [], 0, None
+        for k in order:
+            b = items[k][1].workspace_bytes(items[k][2])
+            if cur and (cur_b + b > (budget_gib << 30) or items[k][3] != cur_t):
+                groups.append(cur)
+                cur, cur_b = [], 0
+            cur.append(k)
+            cur_b += b
+            cur_t = items[k][3]
+        groups.append(cur)
+        batches = [T.Batch([items[k][1] for k in g], [items[k][2] for k in g]) for g in groups]
+        ws = T.Workspace(max(bt.info()["workspace_bytes"] for bt in batches))
+        batches[0].run(ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = [bt.run(ws) for bt in batches]
+        dt = time.perf_counter() - t0
+        out = [None] * len(items)
+        for gi, g in enumerate(groups):
+            for j, k in enumerate(g):
+                out[k] = res[gi][j]
+        return dt, out, len(batches)
+
+    rec = {"workload": "512 circuits of 12-22 qubits (qft, ghz, qaoa p=2, brick-wall), 2048 shots each, "
+                       "per-shot, depolarizing(1e-3,1e-2)", "runs": len(circs), "shots_total": shots * len(circs)}
+    def note(msg):
+        print("# batch: " + msg, file=sys.stderr, flush=True)
+
+    items = build({})
+    note("%d runs planned" % len(items))
+    t_seq, seq = sequential(items)
+    note("one after another %.2f s" % t_seq)
+    t_bat, bat, nb = batched(items)
+    note("batched %.2f s in %d batches" % (t_bat, nb))
+    rec["sequential_s"], rec["batched_s"], rec["batches"] = t_seq, t_bat, nb
+    rec["outcomes_identical"] = bool(all(np.array_equal(a, b) for a, b in zip(seq, bat)))
+    # autotuned tile width and pass bound per family and size
+    tunings, t_tune = {}, time.perf_counter()
+    for name, wc in circs:
+        key = name.split("_")[0]
+        if key not in tunings:
+            tunings[key], _ = AT.autotune(T, torch, wc)
+            note("autotuned %s: %s" % (key, tunings[key]))
+    t_tune = time.perf_counter() - t_tune
+    items_t = build(tunings)
+    t_auto, _, nb_a = batched(items_t)
+    note("autotuned batched %.2f s" % t_auto)
+    rec["autotuned_batched_s"], rec["autotune_s"], rec["autotuned_batches"] = t_auto, t_tune, nb_a
+    rec["tunings"] = tunings
+    # the small runs alone
+    small = [it for it in items if it[0] <= 16]
+    t_ss, _ = sequential(small)
+    t_sb, _, _ = batched(small)
+    rec["small_runs"] = len(small)
+    rec["small_sequential_s"], rec["small_batched_s"] = t_ss, t_sb
+    for k in ("sequential", "batched", "autotuned_batched"):
+        rec[k + "_shots_per_s"] = rec["shots_total"] / rec[k + "_s"]
+    rec["small_batch_speedup"] = t_ss / t_sb
+    print("# batch: sequential %.2f s, batched %.2f s (%d batches, identical %s), autotuned batched %.2f s; "
+          "12-16q runs: sequential %.3f s, batched %.3f s" % (t_seq, t_bat, nb, rec["outcomes_identical"], t_auto,
+                                                              t_ss, t_sb), file=sys.stderr, flush=True)
+    return rec
 
 
 def cpu_baseline(wc, seed, budget_s=15.0):
