@@ -59,7 +59,7 @@ def time_form(T, torch, circuit, tree, seed, steps, warmup, tuning=None):
         T.run(plan, nz, ws, stream)
     torch.cuda.synchronize()
     agg = {"ms_passes": 0.0, "ms_sample": 0.0, "bytes_passes": 0, "bytes_sample": 0,
-           "pass_launches": 0, "ms_device": 0.0, "launches": 0}
+           "pass_launches": 0, "ms_device": 0.0, "launches": 0, "nodes_merged": 0}
     t0 = time.perf_counter()
     for _ in range(steps):
         out, st = T.run(plan, nz, ws, stream, stats=True)
@@ -70,6 +70,7 @@ def time_form(T, torch, circuit, tree, seed, steps, warmup, tuning=None):
         agg["ms_device"] += st["ms_device"]
         agg["launches"] += st["launches"]
         agg["pass_launches"] += st["pass_launches"]
+        agg["nodes_merged"] = st["nodes_merged"]
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     passes_total = sum(plan.info(l)["passes_level"] * int(__import__("numpy").prod(tree[0][:l + 1]))
@@ -306,7 +307,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-dcp", action="store_true",
                     help="skip the copy-cost measurement and the DCP-shaped form")
-    ap.add_argument("--forms", default="tree,pershot,tree4a,tree4b")
+    ap.add_argument("--forms", default="tree,pershot,tree_nomerge,pershot_nomerge,tree4a,tree4b")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--tile", type=int, default=0, help="tile qubits (0 = library default)")
     ap.add_argument("--pass-cost", type=int, default=0, help="per-pass work bound (0 = default)")
@@ -347,13 +348,18 @@ def main():
         "tree4a": ([32, 8, 8, 8], equal_cuts(G, 4)),
         "tree4b": ([8, 8, 16, 16], equal_cuts(G, 4)),
     }
+    # the same shapes with every node's state computed (tree reuse alone,
+    # without sharing the states of nodes with equal noise histories)
+    forms["tree_nomerge"] = forms["tree"]
+    forms["pershot_nomerge"] = forms["pershot"]
     # state copy in gate-equivalents on this GPU (the DCP copy-cost input):
     # one state's read + write at the streaming-copy rate, against the average
     # time per gate execution of a per-shot run
     if not args.no_dcp:
         copy_gbps = T.probe_copy(1 << 30, 10)
         copy_us = 2 * 8 * (1 << 20) / (copy_gbps * 1e3)
-        sps_ps, _, agg_ps, _ = time_form(T, torch, circuit, forms["pershot"], args.seed, 1, 1)
+        sps_ps, _, agg_ps, _ = time_form(T, torch, circuit, forms["pershot"], args.seed, 1, 1,
+                                         {"no_merge": 1})
         gate_us = agg_ps["ms_passes"] * 1e3 / (shots * G)
         copy_cost = copy_us / gate_us
         dcp_shape = T.dcp(circuit, shots, 1.96, 0.01, copy_cost, 8)
@@ -365,6 +371,8 @@ def main():
         tree = forms[name]
         tuning = {k: v for k, v in (("tile_qubits", args.tile), ("pass_cost", args.pass_cost),
                                      ("chunk_states", args.chunk)) if v}
+        if name.endswith("_nomerge"):
+            tuning["no_merge"] = 1
         sps, ms, agg, _ = time_form(T, torch, circuit, tree, args.seed, args.steps, args.warmup,
                                     tuning or None)
         results[name] = {"shots_per_s": sps, "ms_per_step": ms, "shape": tree[0], "cut": tree[1],
@@ -374,6 +382,7 @@ def main():
                          "launches": agg["launches"] // args.steps,
                          "pass_launches_per_step": agg["pass_launches_per_step"],
                          "pass_launches": agg["pass_launches"],
+                         "nodes_merged": agg["nodes_merged"],
                          "bytes_per_launch": agg["bytes_passes"] / max(agg["pass_launches"], 1),
                          "us_per_launch": agg["ms_passes"] * 1e3 / max(agg["pass_launches"], 1)}
         print("# %s: %.1f shots/s, %.2f ms/step, pass %.0f GB/s" %
@@ -402,11 +411,17 @@ def main():
                      "kernel": "pass_kernel<float>",
                      "algorithmic_bytes_per_launch": h["bytes_per_launch"],
                      "us_per_launch": h["us_per_launch"], "launches": h["pass_launches"]},
-        "forms": {k: {kk: v[kk] for kk in ("shots_per_s", "ms_per_step", "pass_GBps", "shape")}
+        "forms": {k: {kk: v[kk] for kk in ("shots_per_s", "ms_per_step", "pass_GBps", "shape", "nodes_merged")}
                   for k, v in results.items()},
     }
-    if "pershot" in results and head != "pershot":
-        line["tree_speedup_vs_pershot"] = h["shots_per_s"] / results["pershot"]["shots_per_s"]
+    # per-shot without merged states is the baseline the tree is measured
+    # against; the ratios separate tree reuse from state sharing
+    base = results.get("pershot_nomerge", results.get("pershot"))
+    if base is not None and head != "pershot":
+        line["tree_speedup_vs_pershot"] = h["shots_per_s"] / base["shots_per_s"]
+    if "tree_nomerge" in results and "pershot_nomerge" in results:
+        line["tree_nomerge_speedup_vs_pershot"] = (results["tree_nomerge"]["shots_per_s"] /
+                                                   results["pershot_nomerge"]["shots_per_s"])
     if not args.no_dcp:
         line["copy_cost_gates"] = copy_cost
         line["copy_GBps"] = copy_gbps

@@ -91,6 +91,11 @@ typedef struct {
     uint32_t sample_block_log; /* log2 amplitudes per sampling block (default 12) */
     uint32_t pass_cost;        /* estimated lane instructions per amplitude allowed in one
                                   pass before a new pass starts (default 480) */
+    uint32_t no_merge;         /* 1: compute every node's state.  Default 0: nodes of one
+                                  chunk whose parents share a state and whose frames and
+                                  noise events are equal share one state (Sec. 6,
+                                  inter-shot redundancy; most often siblings without an
+                                  event), each leaf still sampled with its own draw */
 } tqs_tuning;
 
 /* Timing and traffic of one run. */
@@ -105,6 +110,7 @@ typedef struct {
     uint64_t bytes_passes;     /* algorithmic HBM bytes of the passes (read + write) */
     uint64_t bytes_sample;     /* algorithmic HBM bytes of sampling */
     uint64_t events;           /* noise events in the insertion list */
+    uint64_t nodes_merged;     /* nodes whose state is an identical earlier node's */
 } tqs_run_stats;
 
 /* ---------------------------------------------------------------- circuit */
@@ -184,7 +190,9 @@ tqs_status tqs_plan_info(const tqs_plan *p, uint32_t level, uint32_t *passes_lev
                          uint32_t *passes_total, uint32_t *chunk_states);
 
 /* Device workspace bytes that tqs_run needs for this plan and insertion
- * list (nz may be NULL for a bound valid for any list of this tree). */
+ * list, exactly (host work over the list's nodes and events); nz may be
+ * NULL for a bound valid for any list of this tree with at most one event
+ * per gate of each node. */
 tqs_status tqs_workspace_bytes(const tqs_plan *p, const tqs_noise *nz, uint64_t *bytes);
 
 /* Text description of the plan, for tests and analysis (no device work).

@@ -16,6 +16,7 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <unordered_map>
 #include <vector>
 
 #include "tqs_internal.h"
@@ -110,14 +111,16 @@ struct SampleArgs {
     uint64_t slot_amps;
     const uint32_t *slots;     // state slot per leaf of the chunk
     const uint32_t *node_ids;  // global node id per leaf of the chunk
-    double *part, *sums;
+    const uint32_t *rep;       // per leaf: index of its distinct state
+    const uint32_t *rep_slots; // state slot per distinct state
+    double *part, *sums;       // partial and block sums per distinct state
     const double *leaf_u;
     const uint32_t *leaf_fx;
     uint64_t *outcomes;
     uint64_t leaf_first;       // first leaf of the run's outcome array
     uint32_t leaf_off, count;  // node id of leaf 0, leaves in the chunk
     uint32_t wg_begin[3];      // first workgroup in the partials / gather / sample launches
-    uint32_t pad;
+    uint32_t reps;             // distinct states of the chunk
     SampleMap m;
 };
 
@@ -162,11 +165,11 @@ __global__ __launch_bounds__(kThreads) void block_partials_kernel(SampleLaunch<R
     const SampleArgs<R> sa = sample_seg(sl, 0, blockIdx.x, &local);
     const SampleMap &m = sa.m;
     const uint32_t nch = 1u << (m.n - m.c);
-    if (local >= sa.count * nch) return;
+    if (local >= sa.reps * nch) return;
     const uint32_t k = local / nch, ch = local % nch;
     const cplx<R> *states = sa.states;
     const uint64_t slot_amps = sa.slot_amps;
-    const uint32_t *slots = sa.slots;
+    const uint32_t *slots = sa.rep_slots;
     double *part = sa.part;
     const uint32_t t = threadIdx.x;
     const uint32_t tb = m.c < 8 ? m.c : 8u, qb = m.c - tb;
@@ -234,7 +237,7 @@ __global__ __launch_bounds__(kThreads) void block_gather_kernel(SampleLaunch<R> 
     const SampleMap &m = sa.m;
     const uint32_t nblocks = 1u << (m.n - m.b);
     const uint64_t gid = (uint64_t)local * kThreads + threadIdx.x;
-    if (gid >= (uint64_t)sa.count * nblocks) return;
+    if (gid >= (uint64_t)sa.reps * nblocks) return;
     const uint32_t k = (uint32_t)(gid / nblocks), B = (uint32_t)(gid % nblocks);
     const double *part = sa.part;
     double *sums = sa.sums;
@@ -287,7 +290,7 @@ __global__ __launch_bounds__(kThreads) void sample_kernel(SampleLaunch<R> sl) {
     const double u = leaf_u[lam];
     const uint32_t x = leaf_fx[lam];
     const uint32_t xb = x >> b, xlow = x & ((1u << b) - 1u);
-    const double *S = sums + (uint64_t)k * nblocks;
+    const double *S = sums + (uint64_t)sa.rep[k] * nblocks;
     const cplx<R> *psi = states + (uint64_t)slots[k] * slot_amps;
     if (tid < 192) {
         const uint32_t h = tid >> 6;
@@ -518,25 +521,45 @@ static Layout make_layout(const tqs_plan *p, uint64_t n_events, uint64_t n_leave
 }
 
 // Chunk task of the depth-first walk: `count` consecutive nodes of `level`
-// starting at local index `first`, with their slot tables at `sched`.
+// starting at local index `first`.  Of those, `ccount` distinct states are
+// computed; a node whose parent state, starting frame and event list equal an
+// earlier node's of the chunk shares that node's state (Sec. 6, inter-shot
+// redundancy).  Tables at `sched` (u32): per node its id, state slot and the
+// index of the computed state it uses; then per computed state its node id,
+// source slot and destination slot.
 struct Task {
     uint32_t level;
     uint64_t first;
-    uint32_t count;
-    uint64_t sched;  // offset (in u32) of node_ids; src at +count, dst at +2 count
+    uint32_t count, ccount;
+    uint64_t sched;
+    uint64_t node_ids() const { return sched; }
+    uint64_t slot_of() const { return sched + count; }
+    uint64_t rep_of() const { return sched + 2ull * count; }
+    uint64_t cnode() const { return sched + 3ull * count; }
+    uint64_t csrc() const { return cnode() + ccount; }
+    uint64_t cdst() const { return cnode() + 2ull * ccount; }
 };
 
+struct HostMeta;
+static bool same_history(const HostMeta &hm, uint32_t a, uint32_t b);
+static uint64_t history_hash(const HostMeta &hm, uint32_t a);
+
+// Depth-first chunk walk of the subtrees [first0, last0).  hm == NULL
+// computes every node.
 static void build_schedule(const tqs_plan *p, uint64_t first0, uint64_t last0, std::vector<Task> *tasks,
-                           std::vector<uint32_t> *sched, const std::vector<uint32_t> &slot_base) {
+                           std::vector<uint32_t> *sched, const std::vector<uint32_t> &slot_base,
+                           const HostMeta *hm) {
     const uint32_t L = (uint32_t)p->arity.size();
-    // recursive walk with an explicit stack of (level, parent range)
     struct Frame_ {
         uint32_t level;
-        uint64_t p0, p1;   // parent range at level-1 (for level 0: subtree range)
-        uint64_t next;     // next child to process (local index at `level`)
+        uint64_t p0, p1;                 // parent range at level-1 (for level 0: subtree range)
+        uint64_t next;                   // next child to process (local index at `level`)
+        std::vector<uint32_t> pslot;     // state slot of each parent in [p0, p1)
     };
     std::vector<Frame_> st;
-    st.push_back({0, first0, last0, first0});
+    st.push_back({0, first0, last0, first0, {}});
+    std::vector<uint32_t> slot, rep, cnode, csrc;
+    std::unordered_multimap<uint64_t, uint32_t> seen;  // history key -> computed index
     while (!st.empty()) {
         Frame_ &f = st.back();
         const uint32_t l = f.level;
@@ -546,20 +569,55 @@ static void build_schedule(const tqs_plan *p, uint64_t first0, uint64_t last0, s
             st.pop_back();
             continue;
         }
+        // the chunk takes nodes until its computed states fill the level's
+        // slots; nodes that share an earlier node's state take no slot
         const uint64_t c0 = f.next;
-        const uint64_t c1 = std::min<uint64_t>(c_end, c0 + p->chunk[l]);
+        slot.clear();
+        rep.clear();
+        cnode.clear();
+        csrc.clear();
+        seen.clear();
+        uint64_t c = c0;
+        for (; c < c_end; c++) {
+            const uint32_t node = (uint32_t)(p->level_offset[l] + c);
+            const uint32_t from = l == 0 ? kInit : f.pslot[c / A - f.p0];
+            int64_t hit = -1;
+            uint64_t key = 0;
+            if (hm) {
+                key = history_hash(*hm, node) * 0x9E3779B97F4A7C15ull + from;
+                auto range = seen.equal_range(key);
+                for (auto it = range.first; it != range.second && hit < 0; ++it) {
+                    const uint32_t j = it->second;
+                    if (csrc[j] == from && same_history(*hm, cnode[j], node)) hit = j;
+                }
+            }
+            if (hit < 0) {
+                if (cnode.size() == p->chunk[l]) break;
+                hit = (int64_t)cnode.size();
+                cnode.push_back(node);
+                csrc.push_back(from);
+                if (hm) seen.emplace(key, (uint32_t)hit);
+            }
+            rep.push_back((uint32_t)hit);
+            slot.push_back(slot_base[l] + (uint32_t)hit);
+        }
+        const uint64_t c1 = c;
         f.next = c1;
+        const uint32_t cnt = (uint32_t)(c1 - c0);
         Task t;
         t.level = l;
         t.first = c0;
-        t.count = (uint32_t)(c1 - c0);
+        t.count = cnt;
+        t.ccount = (uint32_t)cnode.size();
         t.sched = sched->size();
-        for (uint64_t c = c0; c < c1; c++) sched->push_back((uint32_t)(p->level_offset[l] + c));
-        for (uint64_t c = c0; c < c1; c++)
-            sched->push_back(l == 0 ? kInit : slot_base[l - 1] + (uint32_t)(c / A - f.p0));
-        for (uint64_t c = c0; c < c1; c++) sched->push_back(slot_base[l] + (uint32_t)(c - c0));
+        for (uint64_t cc = c0; cc < c1; cc++) sched->push_back((uint32_t)(p->level_offset[l] + cc));
+        sched->insert(sched->end(), slot.begin(), slot.end());
+        sched->insert(sched->end(), rep.begin(), rep.end());
+        sched->insert(sched->end(), cnode.begin(), cnode.end());
+        sched->insert(sched->end(), csrc.begin(), csrc.end());
+        for (uint32_t j = 0; j < t.ccount; j++) sched->push_back(slot_base[l] + j);
         tasks->push_back(t);
-        if (l + 1 < L) st.push_back({l + 1, c0, c1, c0 * p->arity[l + 1]});
+        if (l + 1 < L) st.push_back({l + 1, c0, c1, c0 * p->arity[l + 1], slot});
     }
 }
 
@@ -569,6 +627,29 @@ struct HostMeta {
     std::vector<uint32_t> leaf_fx;
     std::vector<Frame> leaf_frame;
 };
+
+// Two nodes compute the same state from the same parent state when they
+// start from the same frame and meet the same events at the same places.
+static bool same_history(const HostMeta &hm, uint32_t a, uint32_t b) {
+    if (hm.frame0[2 * a] != hm.frame0[2 * b] || hm.frame0[2 * a + 1] != hm.frame0[2 * b + 1]) return false;
+    const uint32_t na = hm.ev_off[a + 1] - hm.ev_off[a], nb = hm.ev_off[b + 1] - hm.ev_off[b];
+    if (na != nb) return false;
+    for (uint32_t i = 0; i < na; i++) {
+        const uint32_t ea = hm.ev_off[a] + i, eb = hm.ev_off[b] + i;
+        if (hm.ev_pos[ea] != hm.ev_pos[eb] || hm.ev_dx[ea] != hm.ev_dx[eb] || hm.ev_dz[ea] != hm.ev_dz[eb])
+            return false;
+    }
+    return true;
+}
+
+static uint64_t history_hash(const HostMeta &hm, uint32_t a) {
+    uint64_t h = ((uint64_t)hm.frame0[2 * a] << 32) ^ hm.frame0[2 * a + 1];
+    for (uint32_t e = hm.ev_off[a]; e < hm.ev_off[a + 1]; e++) {
+        h = (h ^ hm.ev_pos[e]) * 0x100000001B3ull;
+        h = (h ^ ((uint64_t)hm.ev_dx[e] << 32 | hm.ev_dz[e])) * 0x100000001B3ull;
+    }
+    return h;
+}
 
 // Map the insertion list onto pass positions and Pauli masks, and compose
 // each node's frame from its parent's (Sec. 3.1: a child continues from a
@@ -643,12 +724,12 @@ static PassArgs<R> pass_args(const tqs_plan *p, const Layout &Ly, unsigned char 
     PassArgs<R> a;
     a.states = reinterpret_cast<cplx<R> *>(ws + Ly.off_states);
     a.slot_amps = 1ull << p->n;
-    const uint32_t *sched = reinterpret_cast<const uint32_t *>(ws + Ly.off_sched) + t.sched;
-    a.node_ids = sched;
-    a.src_slot = first ? sched + t.count : sched + 2 * t.count;
-    a.dst_slot = sched + 2 * t.count;
-    a.count = t.count;
-    a.work = t.count * (1u << pd.nfree);
+    const uint32_t *sched = reinterpret_cast<const uint32_t *>(ws + Ly.off_sched);
+    a.node_ids = sched + t.cnode();
+    a.src_slot = sched + (first ? t.csrc() : t.cdst());
+    a.dst_slot = sched + t.cdst();
+    a.count = t.ccount;
+    a.work = t.ccount * (1u << pd.nfree);
     a.pass_key = pass_idx << 16;
     a.wg_begin = 0;
     a.pass = reinterpret_cast<const PassDesc *>(ws + Ly.off_passes) + pass_idx;
@@ -728,11 +809,14 @@ static SampleArgs<R> sample_args(const tqs_plan *p, const Layout &Ly, unsigned c
                                  uint64_t leaf_first) {
     SampleArgs<R> a;
     std::memset(&a, 0, sizeof a);
-    const uint32_t *sched = reinterpret_cast<const uint32_t *>(ws + Ly.off_sched) + t.sched;
+    const uint32_t *sched = reinterpret_cast<const uint32_t *>(ws + Ly.off_sched);
     a.states = reinterpret_cast<const cplx<R> *>(ws + Ly.off_states);
     a.slot_amps = 1ull << p->n;
-    a.slots = sched + 2 * t.count;
-    a.node_ids = sched;
+    a.slots = sched + t.slot_of();
+    a.node_ids = sched + t.node_ids();
+    a.rep = sched + t.rep_of();
+    a.rep_slots = sched + t.cdst();
+    a.reps = t.ccount;
     a.part = reinterpret_cast<double *>(ws + Ly.off_part);
     a.sums = reinterpret_cast<double *>(ws + Ly.off_sums);
     a.leaf_u = reinterpret_cast<const double *>(ws + Ly.off_leafu);
@@ -748,8 +832,8 @@ static SampleArgs<R> sample_args(const tqs_plan *p, const Layout &Ly, unsigned c
 // Workgroups of the partials / gather / sample launches for one segment.
 template <typename R>
 static void sample_grid(const SampleArgs<R> &a, uint32_t g[3]) {
-    g[0] = a.count << (a.m.n - a.m.c);
-    g[1] = (uint32_t)((((uint64_t)a.count << (a.m.n - a.m.b)) + kThreads - 1) / kThreads);
+    g[0] = a.reps << (a.m.n - a.m.c);
+    g[1] = (uint32_t)((((uint64_t)a.reps << (a.m.n - a.m.b)) + kThreads - 1) / kThreads);
     g[2] = a.count;
 }
 
@@ -844,7 +928,7 @@ static tqs_status run_t(tqs_plan *p, const tqs_noise *nz, unsigned char *ws, uin
     std::vector<Task> tasks;
     std::vector<uint32_t> sched;
     Layout Ly0 = make_layout(p, nz->ev_gate.size(), n_out, 0);
-    build_schedule(p, first, last, &tasks, &sched, Ly0.slot_base);
+    build_schedule(p, first, last, &tasks, &sched, Ly0.slot_base, p->tune.no_merge ? nullptr : &hm);
     Layout Ly = make_layout(p, nz->ev_gate.size(), n_out, sched.size());
     if (ws_bytes < Ly.total)
         return fail(TQS_E_WORKSPACE, "workspace has %llu bytes, the run needs %llu",
@@ -871,12 +955,13 @@ static tqs_status run_t(tqs_plan *p, const tqs_noise *nz, unsigned char *ws, uin
         cap_host.resize(Ly.state_bytes);
     }
 
-    uint64_t launches = 0, pass_launches = 0, pass_states = 0, bytes_passes = 0, bytes_sample = 0;
+    uint64_t launches = 0, pass_launches = 0, pass_states = 0, bytes_passes = 0, bytes_sample = 0, merged = 0;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pass_ev, samp_ev;
     const uint64_t state_bytes = Ly.state_bytes;
     const uint32_t b = p->sample_b;
     for (const Task &t : tasks) {
         const tqs::Level &lv = p->levels[t.level];
+        merged += t.count - t.ccount;
         hipEvent_t ea = nullptr, eb = nullptr, ec = nullptr;
         if (stats) {
             ea = pool_event(p, ev_i++);
@@ -888,9 +973,9 @@ static tqs_status run_t(tqs_plan *p, const tqs_noise *nz, unsigned char *ws, uin
             launch_pass<R>(p, Ly, ws, s, t, lv.pass_begin + k, k == 0);
             launches++;
             pass_launches++;
-            pass_states += t.count;
+            pass_states += t.ccount;
             const bool init = (k == 0 && t.level == 0);
-            bytes_passes += (uint64_t)t.count * state_bytes * (init ? 1 : 2);
+            bytes_passes += (uint64_t)t.ccount * state_bytes * (init ? 1 : 2);
         }
         if (stats) {
             HIP_TRY(hipEventRecord(eb, s), "hipEventRecord");
@@ -899,7 +984,7 @@ static tqs_status run_t(tqs_plan *p, const tqs_noise *nz, unsigned char *ws, uin
         if (t.level == L - 1) {
             launch_sample<R>(p, Ly, ws, s, t, leaf_first);
             launches += 3;
-            bytes_sample += (uint64_t)t.count * (state_bytes + (Ly.amp_bytes << b));
+            bytes_sample += (uint64_t)t.ccount * state_bytes + (uint64_t)t.count * (Ly.amp_bytes << b);
             if (stats) {
                 ec = pool_event(p, ev_i++);
                 if (!ec) return fail(TQS_E_HIP, "hipEventCreate failed");
@@ -914,7 +999,7 @@ static tqs_status run_t(tqs_plan *p, const tqs_noise *nz, unsigned char *ws, uin
                     for (uint64_t ci = 0; ci < cap.n; ci++) {
                         if (cap.leaves[ci] != lam) continue;
                         const Frame &f = hm.leaf_frame[lam];
-                        const uint32_t slot = Ly.slot_base[L - 1] + i;
+                        const uint32_t slot = sched[t.slot_of() + i];
                         const uint64_t amps = 1ull << p->n;
                         const cplx<R> *in = reinterpret_cast<const cplx<R> *>(ws + Ly.off_states) + (uint64_t)slot * amps;
                         cplx<R> *out = reinterpret_cast<cplx<R> *>(ws + Ly.off_states) + (uint64_t)Ly.scratch_slot * amps;
@@ -963,6 +1048,7 @@ static tqs_status run_t(tqs_plan *p, const tqs_noise *nz, unsigned char *ws, uin
         stats->bytes_passes = bytes_passes;
         stats->bytes_sample = bytes_sample;
         stats->events = nz->ev_gate.size();
+        stats->nodes_merged = merged;
         stats->ms_wall =
             std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }
@@ -1148,16 +1234,22 @@ extern "C" {
 tqs_status tqs_workspace_bytes(const tqs_plan *p, const tqs_noise *nz, uint64_t *bytes) {
     TQS_GUARD_BEGIN
     if (!p || !bytes) return fail(TQS_E_ARG, "plan or bytes is NULL");
-    uint64_t ev = 0;
     if (nz) {
+        // exact: the schedule of this list (merged states shorten it)
         tqs_status st = check_noise(p, nz);
         if (st) return st;
-        ev = nz->ev_gate.size();
-    } else {
-        for (size_t l = 0; l < p->arity.size(); l++)
-            ev += p->level_nodes[l] * (uint64_t)(p->cut[l + 1] - p->cut[l]);
+        HostMeta hm;
+        build_meta(p, nz, &hm);
+        std::vector<Task> tasks;
+        std::vector<uint32_t> sched;
+        Layout Ly0 = make_layout(p, nz->ev_gate.size(), p->n_leaves, 0);
+        build_schedule(p, 0, p->arity[0], &tasks, &sched, Ly0.slot_base, p->tune.no_merge ? nullptr : &hm);
+        *bytes = make_layout(p, nz->ev_gate.size(), p->n_leaves, sched.size()).total;
+        return TQS_OK;
     }
-    Layout Ly = make_layout(p, ev, p->n_leaves, 3 * p->n_nodes);
+    uint64_t ev = 0;
+    for (size_t l = 0; l < p->arity.size(); l++) ev += p->level_nodes[l] * (uint64_t)(p->cut[l + 1] - p->cut[l]);
+    Layout Ly = make_layout(p, ev, p->n_leaves, 6 * p->n_nodes);
     *bytes = Ly.total;
     return TQS_OK;
     TQS_GUARD_END
@@ -1255,7 +1347,8 @@ extern "C" tqs_status tqs_batch_create(tqs_plan *const *plans, const tqs_noise *
         it.nz = noises[i];
         build_meta(p, it.nz, &it.hm);
         Layout Ly0 = make_layout(p, it.nz->ev_gate.size(), p->n_leaves, 0);
-        build_schedule(p, 0, p->arity[0], &it.tasks, &it.sched, Ly0.slot_base);
+        build_schedule(p, 0, p->arity[0], &it.tasks, &it.sched, Ly0.slot_base,
+                       p->tune.no_merge ? nullptr : &it.hm);
         it.Ly = make_layout(p, it.nz->ev_gate.size(), p->n_leaves, it.sched.size(), states, 0);
         states = align256(states + (uint64_t)it.Ly.slots_total * it.Ly.state_bytes);
         it.leaf_base = B->leaves;

@@ -29,13 +29,13 @@ class TqsTree(C.Structure):
 
 class TqsTuning(C.Structure):
     _fields_ = [("tile_qubits", u32), ("max_ops_per_pass", u32), ("chunk_states", u32),
-                ("sample_block_log", u32), ("pass_cost", u32)]
+                ("sample_block_log", u32), ("pass_cost", u32), ("no_merge", u32)]
 
 
 class TqsRunStats(C.Structure):
     _fields_ = [("ms_wall", dbl), ("ms_device", dbl), ("ms_passes", dbl), ("ms_sample", dbl),
                 ("launches", u64), ("pass_launches", u64), ("pass_states", u64), ("bytes_passes", u64),
-                ("bytes_sample", u64), ("events", u64)]
+                ("bytes_sample", u64), ("events", u64), ("nodes_merged", u64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -90,6 +90,10 @@ def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError("libtqsim.so is not built (%s); run python -m paper_2203_13892_amd.build"
                           % LIB_PATH)
+    # Load torch's HIP runtime first so that the library binds to it: one
+    # runtime per process, to which the streams and device pointers handed
+    # over from torch belong (a second runtime copy cannot open the device).
+    import torch  # noqa: F401
     L = C.CDLL(LIB_PATH)
     for name, (res, args) in SIGNATURES.items():
         f = getattr(L, name)

@@ -458,3 +458,91 @@ def test_batch_equals_separate_runs(T, prec):
     onz = oracle.sample_noise(wcs[0].gates, trees[0], 20)
     oout, ost = oracle.run_leaves(wcs[0].n, wcs[0].gates, trees[0], onz, states=True)
     check_outcomes(outs[0], oout, ost, onz.leaf_u, DELTA[prec])
+
+
+def _repeating_events(wc, tree, rng, rate=0.05, copy=0.35):
+    """Insertion list where many siblings repeat an earlier sibling's events
+    (or have none), so that merged states are common."""
+    A, cut = tree
+    node_off, eg, ec = [0], [], []
+    for l in range(len(A)):
+        I = int(np.prod(A[:l + 1]))
+        prev = None
+        for m in range(I):
+            if prev is not None and m % A[l] != 0 and rng.random() < copy:
+                ev = prev
+            else:
+                ev = [(g, int(rng.integers(1, 4 ** len(wc.gates[g][0]))))
+                      for g in range(cut[l], cut[l + 1]) if rng.random() < rate]
+            for g, k in ev:
+                eg.append(g)
+                ec.append(k)
+            node_off.append(len(eg))
+            prev = ev
+    return (np.array(node_off, np.uint64), np.array(eg, np.uint32), np.array(ec, np.uint8),
+            rng.random(int(np.prod(A))))
+
+
+def _distinct_histories(tree, arr):
+    """Nodes per level minus distinct (parent class, own event set) classes."""
+    A, _ = tree
+    node_off, eg, ec = arr[0].astype(np.int64), arr[1], arr[2]
+    merged, cls_prev, nu = 0, None, 0
+    for l in range(len(A)):
+        I = int(np.prod(A[:l + 1]))
+        ids, cls = {}, []
+        for m in range(I):
+            par = 0 if l == 0 else cls_prev[m // A[l]]
+            ev = tuple(sorted(zip(eg[node_off[nu]:node_off[nu + 1]].tolist(),
+                                  ec[node_off[nu]:node_off[nu + 1]].tolist())))
+            cls.append(ids.setdefault((par, ev), len(ids)))
+            nu += 1
+        merged += I - len(ids)
+        cls_prev = cls
+    return merged
+
+
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+def test_merged_states_equal_separate_states(T, prec):
+    # nodes with equal parent state, frame and events share one state: the
+    # outcomes are bit-identical to computing every node, the captured
+    # leaves match the oracle, and the merge count is the number of
+    # repeated histories (one chunk per level here)
+    rng = np.random.default_rng(31)
+    wc = mixed_gates(12, 48, rng)
+    tree = ([4, 8, 8], [0, 16, 32, 48])
+    arr = _repeating_events(wc, tree, rng)
+    c = T.Circuit.from_workload(wc)
+    nz = T.Noise.from_arrays(c, tree, *arr)
+    merged_plan = T.Plan(c, tree, prec, {"chunk_states": 512})
+    plain_plan = T.Plan(c, tree, prec, {"chunk_states": 512, "no_merge": 1})
+    out_m, st_m = T.run(merged_plan, nz, stats=True)
+    out_p, st_p = T.run(plain_plan, nz, stats=True)
+    assert np.array_equal(out_m, out_p)
+    assert st_p["nodes_merged"] == 0
+    want = _distinct_histories(tree, arr)
+    assert want > 100
+    assert st_m["nodes_merged"] == want
+    assert st_m["pass_states"] < st_p["pass_states"]
+    leaves = np.arange(256)
+    out, amps, oout, ost, _ = run_both(T, wc, tree, 0, prec, leaves, noise_arrays=arr)
+    assert np.max(np.abs(amps - ost)) < TOL[prec]
+    check_outcomes(out, oout, ost, arr[3], DELTA[prec])
+
+
+def test_merged_states_small_chunks_and_ranges(T):
+    # merging inside small ragged chunks, and over subtree ranges, gives the
+    # unmerged outcomes
+    rng = np.random.default_rng(32)
+    wc = mixed_gates(11, 45, rng)
+    tree = ([5, 6, 7], [0, 12, 30, 45])
+    arr = _repeating_events(wc, tree, rng, rate=0.04)
+    c = T.Circuit.from_workload(wc)
+    nz = T.Noise.from_arrays(c, tree, *arr)
+    base = T.run(T.Plan(c, tree, "c64", {"chunk_states": 5, "no_merge": 1}), nz)
+    plan = T.Plan(c, tree, "c64", {"chunk_states": 5, "max_ops_per_pass": 6})
+    out, st = T.run(plan, nz, stats=True)
+    assert st["nodes_merged"] > 0
+    assert np.array_equal(out, base)
+    parts = [T.run(plan, nz, subtrees=(a, b)) for a, b in [(0, 2), (2, 3), (3, 5)]]
+    assert np.array_equal(np.concatenate(parts), base)

@@ -308,3 +308,11 @@ def test_planner_schedule_reproduces_trajectories(n, tree, tuning):
             for e in range(int(nz.node_off[node]), int(nz.node_off[node + 1])):
                 events.append((int(nz.ev_gate[e]), int(nz.ev_code[e])))
         assert np.max(np.abs(_emulate(text, events) - st[lam])) < 1e-12
+
+
+def test_one_hip_runtime_per_process():
+    # the library binds to the HIP runtime torch loaded, so that streams and
+    # device pointers from torch belong to the runtime the library calls
+    maps = open("/proc/self/maps").read().splitlines()
+    hip = {ln.split()[-1] for ln in maps if "libamdhip64" in ln}
+    assert len(hip) == 1, hip
