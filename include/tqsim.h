@@ -132,6 +132,13 @@ tqs_status tqs_circuit_add_gate(tqs_circuit *c, uint32_t arity, const uint32_t *
  * Paulis.  Replaces any per-gate probabilities. */
 tqs_status tqs_circuit_set_depolarizing(tqs_circuit *c, double p1, double p2);
 
+/* Read-out channel (Sec. 4.3, read-out: a measured bit flips with a given
+ * probability): p_flip[n_qubits] in [0, 1], bit q of every outcome flips
+ * independently with probability p_flip[q] after the measurement.  NULL
+ * removes it.  The flips are drawn with the insertion list (tqs_noise_sample)
+ * and do not change any state. */
+tqs_status tqs_circuit_set_readout(tqs_circuit *c, const double *p_flip);
+
 /* Number of qubits and gates. */
 tqs_status tqs_circuit_info(const tqs_circuit *c, uint32_t *n_qubits, uint32_t *n_gates);
 
@@ -158,7 +165,9 @@ tqs_status tqs_dcp(const tqs_circuit *c, uint64_t shots, double z, double eps,
 
 /* Sample the noise insertion list of every tree node plus one measurement
  * uniform per leaf (Sec. 2.4 and Sec. 3.1; generator in the header
- * comment).  Host only. */
+ * comment).  With a read-out channel each leaf then takes n_qubits more
+ * uniforms v_q and its flip mask has bit q set when v_q < p_flip[q].
+ * Host only. */
 tqs_status tqs_noise_sample(const tqs_circuit *c, const tqs_tree *tree, uint64_t seed,
                             tqs_noise **out);
 
@@ -174,6 +183,13 @@ tqs_status tqs_noise_import(const tqs_circuit *c, const tqs_tree *tree,
 tqs_status tqs_noise_view(const tqs_noise *nz, const uint64_t **node_off,
                           const uint32_t **ev_gate, const uint8_t **ev_code,
                           const double **leaf_u, uint64_t *n_nodes, uint64_t *n_leaves);
+
+/* Set explicit read-out flip masks, leaf_flip[n_leaves] (copied; bit q
+ * flips qubit q's measured bit), or remove them with NULL. */
+tqs_status tqs_noise_set_flips(tqs_noise *nz, const uint32_t *leaf_flip);
+
+/* Borrowed view of the flip masks: *leaf_flip = NULL when there are none. */
+tqs_status tqs_noise_flips(const tqs_noise *nz, const uint32_t **leaf_flip);
 
 void tqs_noise_destroy(tqs_noise *nz);
 

@@ -59,6 +59,8 @@ def lib():
         L.orc_noise_count.argtypes = [u64, i32, P, P, P, P, P, P]
         L.orc_noise_fill.restype = i32
         L.orc_noise_fill.argtypes = [u64, i32, P, P, P, P, P, P, P, P, P]
+        L.orc_readout_fill.restype = i32
+        L.orc_readout_fill.argtypes = [u64, i32, P, P, P, P, P, i32, P, P]
         L.orc_apply_gate.restype = None
         L.orc_apply_gate.argtypes = [i32, P, i32, P, P]
         L.orc_apply_pauli.restype = None
@@ -120,6 +122,7 @@ class Noise:
     ev_gate: np.ndarray    # uint32 [events]
     ev_code: np.ndarray    # uint8  [events]
     leaf_u: np.ndarray     # float64 [leaves]
+    leaf_flip: np.ndarray = None  # uint32 [leaves] read-out flip masks, or None
 
 
 def tree_arrays(tree):
@@ -137,8 +140,10 @@ def n_nodes(A) -> int:
     return tot
 
 
-def sample_noise(gates, tree, seed: int) -> Noise:
-    """The seeded insertion list (definition in the header of orc.c)."""
+def sample_noise(gates, tree, seed: int, readout=None) -> Noise:
+    """The seeded insertion list (definition in the header of orc.c);
+    ``readout`` (per-qubit flip probabilities, Sec. 4.3 read-out channel)
+    adds each leaf's flip mask."""
     L = lib()
     f = flatten(gates)
     A, cut = tree_arrays(tree)
@@ -153,11 +158,18 @@ def sample_noise(gates, tree, seed: int) -> Noise:
     leaf_u = np.zeros(leaves, np.float64)
     L.orc_noise_fill(seed, A.size, _p(A), _p(cut), _p(f.arity), _p(f.probs),
                      _p(f.prob_off), _p(node_off), _p(ev_gate), _p(ev_code), _p(leaf_u))
-    return Noise(node_off, ev_gate[:ne], ev_code[:ne], leaf_u)
+    flips = None
+    if readout is not None:
+        r = np.ascontiguousarray(np.asarray(readout, np.float64))
+        flips = np.zeros(leaves, np.uint32)
+        L.orc_readout_fill(seed, A.size, _p(A), _p(cut), _p(f.arity), _p(f.probs),
+                           _p(f.prob_off), r.size, _p(r), _p(flips))
+    return Noise(node_off, ev_gate[:ne], ev_code[:ne], leaf_u, flips)
 
 
 def run_leaves(n, gates, tree, noise: Noise, leaves=None, states=False, threads=None):
-    """Simulate the listed leaves from scratch, one full trajectory each.
+    """Simulate the listed leaves from scratch, one full trajectory each,
+    and apply their read-out flips if the list has them.
 
     Returns (outcomes uint64 [len(leaves)], states complex128 [len, 2^n] or None).
     """
@@ -184,7 +196,11 @@ def run_leaves(n, gates, tree, noise: Noise, leaves=None, states=False, threads=
                           _p(st) if st is not None else None, int(threads))
     if rc != 0:
         raise RuntimeError("oracle run failed")
-    return outcomes[:leaves.size], st
+    outcomes = outcomes[:leaves.size]
+    if noise.leaf_flip is not None:
+        # read-out channel: the measured bits flip after the measurement
+        outcomes = outcomes ^ np.asarray(noise.leaf_flip, np.uint64)[leaves.astype(np.int64)]
+    return outcomes, st
 
 
 def run_events(n, gates, events=(), u: float = 0.0, state=True):

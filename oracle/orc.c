@@ -28,7 +28,10 @@
  * uniform u2 picks the code c as the first one whose running sum of
  * probabilities exceeds u2 * p_g (falling back to the largest code with a
  * nonzero probability).  A leaf node then draws one more uniform: its
- * measurement uniform.
+ * measurement uniform.  With read-out noise (Sec. 4.3, read-out channel:
+ * each measured bit flips with its own probability r_q) the leaf then draws
+ * n more uniforms v_0 .. v_{n-1}, and bit q of its outcome flips when
+ * v_q < r_q.
  */
 #include <math.h>
 #include <pthread.h>
@@ -96,11 +99,12 @@ static int pick_code(const double *pr, int ncodes, double u2) {
 
 /* Sample one node: gates [g0, g1).  Writes events if ev_gate != NULL.
  * Returns the number of events; *leaf_u gets the measurement uniform when
- * is_leaf. */
+ * is_leaf; *j_end (if not NULL) the index of the node's next draw. */
 static uint64_t sample_node(uint64_t seed, uint64_t nu, uint64_t g0, uint64_t g1,
                             const int *arity, const double *probs,
                             const int64_t *prob_off, int is_leaf,
-                            uint32_t *ev_gate, uint8_t *ev_code, double *leaf_u) {
+                            uint32_t *ev_gate, uint8_t *ev_code, double *leaf_u,
+                            uint64_t *j_end) {
     uint64_t j = 0, ne = 0;
     for (uint64_t g = g0; g < g1; g++) {
         double u1 = orc_uniform(seed, nu, j++);
@@ -119,7 +123,11 @@ static uint64_t sample_node(uint64_t seed, uint64_t nu, uint64_t g0, uint64_t g1
             ne++;
         }
     }
-    if (is_leaf && leaf_u) *leaf_u = orc_uniform(seed, nu, j++);
+    if (is_leaf) {
+        double u = orc_uniform(seed, nu, j++);
+        if (leaf_u) *leaf_u = u;
+    }
+    if (j_end) *j_end = j;
     return ne;
 }
 
@@ -133,7 +141,7 @@ int orc_noise_count(uint64_t seed, int levels, const uint64_t *A, const uint64_t
         uint64_t I = level_nodes(A, l);
         for (uint64_t m = 0; m < I; m++, nu++) {
             uint64_t ne = sample_node(seed, nu, cut[l], cut[l + 1], arity, probs,
-                                      prob_off, 0, NULL, NULL, NULL);
+                                      prob_off, 0, NULL, NULL, NULL, NULL);
             node_off[nu + 1] = node_off[nu] + ne;
         }
     }
@@ -152,8 +160,28 @@ int orc_noise_fill(uint64_t seed, int levels, const uint64_t *A, const uint64_t 
         for (uint64_t m = 0; m < I; m++, nu++) {
             sample_node(seed, nu, cut[l], cut[l + 1], arity, probs, prob_off, is_leaf,
                         ev_gate + node_off[nu], ev_code + node_off[nu],
-                        is_leaf ? &leaf_u[m] : NULL);
+                        is_leaf ? &leaf_u[m] : NULL, NULL);
         }
+    }
+    return 0;
+}
+
+/* Read-out flips: leaf_flip[m] gets bit q set when leaf m's draw v_q is
+ * below r[q] (the n draws after its measurement uniform). */
+int orc_readout_fill(uint64_t seed, int levels, const uint64_t *A, const uint64_t *cut,
+                     const int *arity, const double *probs, const int64_t *prob_off,
+                     int n, const double *r, uint32_t *leaf_flip) {
+    uint64_t nu = 0;
+    for (int l = 0; l < levels - 1; l++) nu += level_nodes(A, l);
+    const int L = levels - 1;
+    uint64_t I = level_nodes(A, L);
+    for (uint64_t m = 0; m < I; m++, nu++) {
+        uint64_t j = 0;
+        sample_node(seed, nu, cut[L], cut[L + 1], arity, probs, prob_off, 1, NULL, NULL, NULL, &j);
+        uint32_t f = 0;
+        for (int q = 0; q < n; q++)
+            if (orc_uniform(seed, nu, j++) < r[q]) f |= 1u << q;
+        leaf_flip[m] = f;
     }
     return 0;
 }

@@ -116,6 +116,7 @@ struct SampleArgs {
     double *part, *sums;       // partial and block sums per distinct state
     const double *leaf_u;
     const uint32_t *leaf_fx;
+    const uint32_t *leaf_flip;  // read-out flip mask per leaf
     uint64_t *outcomes;
     uint64_t leaf_first;       // first leaf of the run's outcome array
     uint32_t leaf_off, count;  // node id of leaf 0, leaves in the chunk
@@ -396,7 +397,8 @@ __global__ __launch_bounds__(kThreads) void sample_kernel(SampleLaunch<R> sl) {
                 if ((double)v.re * v.re + (double)v.im * v.im > 0.0) y = i;
             }
         }
-        outcomes[lam - leaf_first] = ((uint64_t)BL << b) | y;
+        // read-out channel: measured bits flip after the measurement
+        outcomes[lam - leaf_first] = (((uint64_t)BL << b) | y) ^ sa.leaf_flip[lam];
     }
 }
 
@@ -460,7 +462,7 @@ struct Layout {
     uint32_t scratch_slot;
     uint64_t off_states;  // first state slot
     uint64_t off_meta, off_mats, off_ops, off_passes, off_terms, off_dgates, off_frame0, off_evoff,
-        off_evpos, off_evdx, off_evdz, off_leafu, off_leaffx, off_sched, off_sums, off_part, off_out, total;
+        off_evpos, off_evdx, off_evdz, off_leafu, off_leaffx, off_flip, off_sched, off_sums, off_part, off_out, total;
     uint64_t n_sched;
 };
 
@@ -505,6 +507,8 @@ static Layout make_layout(const tqs_plan *p, uint64_t n_events, uint64_t n_leave
     L.off_leafu = o;
     o = align256(o + p->n_leaves * 8);
     L.off_leaffx = o;
+    o = align256(o + p->n_leaves * 4);
+    L.off_flip = o;
     o = align256(o + p->n_leaves * 4);
     L.off_sched = o;
     L.n_sched = n_sched;
@@ -821,6 +825,7 @@ static SampleArgs<R> sample_args(const tqs_plan *p, const Layout &Ly, unsigned c
     a.sums = reinterpret_cast<double *>(ws + Ly.off_sums);
     a.leaf_u = reinterpret_cast<const double *>(ws + Ly.off_leafu);
     a.leaf_fx = reinterpret_cast<const uint32_t *>(ws + Ly.off_leaffx);
+    a.leaf_flip = reinterpret_cast<const uint32_t *>(ws + Ly.off_flip);
     a.outcomes = reinterpret_cast<uint64_t *>(ws + Ly.off_out);
     a.leaf_first = leaf_first;
     a.leaf_off = (uint32_t)p->level_offset.back();
@@ -901,6 +906,7 @@ static void pack_meta(const tqs_plan *p, const tqs_noise *nz, const HostMeta &hm
     put(Ly.off_evdz, hm.ev_dz.data(), hm.ev_dz.size() * 4);
     put(Ly.off_leafu, nz->leaf_u.data(), nz->leaf_u.size() * 8);
     put(Ly.off_leaffx, hm.leaf_fx.data(), hm.leaf_fx.size() * 4);
+    put(Ly.off_flip, nz->leaf_flip.data(), nz->leaf_flip.size() * 4);  // zeros when absent
     put(Ly.off_sched, sched.data(), sched.size() * 4);
 }
 

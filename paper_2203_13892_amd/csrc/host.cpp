@@ -181,6 +181,19 @@ tqs_status tqs_circuit_set_depolarizing(tqs_circuit *c, double p1, double p2) {
     return TQS_OK;
 }
 
+tqs_status tqs_circuit_set_readout(tqs_circuit *c, const double *p_flip) {
+    if (!c) return fail(TQS_E_ARG, "circuit is NULL");
+    if (!p_flip) {
+        c->readout.clear();
+        return TQS_OK;
+    }
+    for (uint32_t q = 0; q < c->n; q++)
+        if (!(p_flip[q] >= 0.0 && p_flip[q] <= 1.0))
+            return fail(TQS_E_ARG, "read-out probability of qubit %u not in [0, 1]", q);
+    c->readout.assign(p_flip, p_flip + c->n);
+    return TQS_OK;
+}
+
 tqs_status tqs_circuit_info(const tqs_circuit *c, uint32_t *n_qubits, uint32_t *n_gates) {
     if (!c) return fail(TQS_E_ARG, "circuit is NULL");
     if (n_qubits) *n_qubits = c->n;
@@ -280,6 +293,7 @@ tqs_status tqs_noise_sample(const tqs_circuit *c, const tqs_tree *tree, uint64_t
     nz->n_leaves = level_nodes(A, L - 1);
     nz->node_off.assign(nodes + 1, 0);
     nz->leaf_u.assign(nz->n_leaves, 0.0);
+    if (!c->readout.empty()) nz->leaf_flip.assign(nz->n_leaves, 0);
     uint64_t nu = 0;
     for (uint32_t l = 0; l < L; l++) {
         const uint64_t I = level_nodes(A, l);
@@ -313,7 +327,15 @@ tqs_status tqs_noise_sample(const tqs_circuit *c, const tqs_tree *tree, uint64_t
                     nz->ev_code.push_back((uint8_t)code);
                 }
             }
-            if (leaf) nz->leaf_u[m] = rs.next();
+            if (leaf) {
+                nz->leaf_u[m] = rs.next();
+                if (!c->readout.empty()) {
+                    uint32_t f = 0;
+                    for (uint32_t q = 0; q < c->n; q++)
+                        if (rs.next() < c->readout[q]) f |= 1u << q;
+                    nz->leaf_flip[m] = f;
+                }
+            }
             nz->node_off[nu + 1] = nz->ev_gate.size();
         }
     }
@@ -386,6 +408,21 @@ tqs_status tqs_noise_view(const tqs_noise *nz, const uint64_t **node_off, const 
     if (leaf_u) *leaf_u = nz->leaf_u.data();
     if (n_nodes) *n_nodes = nz->n_nodes;
     if (n_leaves) *n_leaves = nz->n_leaves;
+    return TQS_OK;
+}
+
+tqs_status tqs_noise_set_flips(tqs_noise *nz, const uint32_t *leaf_flip) {
+    TQS_GUARD_BEGIN
+    if (!nz) return fail(TQS_E_ARG, "noise is NULL");
+    if (!leaf_flip) nz->leaf_flip.clear();
+    else nz->leaf_flip.assign(leaf_flip, leaf_flip + nz->n_leaves);
+    return TQS_OK;
+    TQS_GUARD_END
+}
+
+tqs_status tqs_noise_flips(const tqs_noise *nz, const uint32_t **leaf_flip) {
+    if (!nz || !leaf_flip) return fail(TQS_E_ARG, "noise or leaf_flip is NULL");
+    *leaf_flip = nz->leaf_flip.empty() ? nullptr : nz->leaf_flip.data();
     return TQS_OK;
 }
 

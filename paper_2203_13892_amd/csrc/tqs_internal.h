@@ -37,6 +37,7 @@ struct Gate {
 struct tqs_circuit {
     uint32_t n = 0;
     std::vector<tqs::Gate> gates;
+    std::vector<double> readout;  // per-qubit read-out flip probability (empty: none)
 };
 
 struct tqs_noise {
@@ -48,6 +49,7 @@ struct tqs_noise {
     std::vector<uint32_t> ev_gate;
     std::vector<uint8_t> ev_code;
     std::vector<double> leaf_u;
+    std::vector<uint32_t> leaf_flip;  // read-out flip mask per leaf (empty: none)
 };
 
 namespace tqs {

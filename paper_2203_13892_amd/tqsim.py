@@ -57,6 +57,9 @@ SIGNATURES = {
     "tqs_plan_info": (i32, [vp, u32, P(u32), P(u32), P(u32)]),
     "tqs_workspace_bytes": (i32, [vp, vp, P(u64)]),
     "tqs_plan_destroy": (None, [vp]),
+    "tqs_circuit_set_readout": (i32, [vp, P(dbl)]),
+    "tqs_noise_set_flips": (i32, [vp, P(u32)]),
+    "tqs_noise_flips": (i32, [vp, P(P(u32))]),
     "tqs_run": (i32, [vp, vp, vp, u64, vp, P(u64), P(TqsRunStats)]),
     "tqs_run_range": (i32, [vp, vp, vp, u64, vp, u64, u64, P(u64), P(TqsRunStats)]),
     "tqs_run_capture": (i32, [vp, vp, vp, u64, vp, P(u64), P(u64), u64, P(dbl)]),
@@ -141,6 +144,15 @@ class Circuit:
         _check(lib.tqs_circuit_set_depolarizing(self.h, p1, p2))
         return self
 
+    def set_readout(self, p_flip):
+        """Per-qubit read-out flip probabilities (None removes the channel)."""
+        if p_flip is None:
+            _check(lib.tqs_circuit_set_readout(self.h, None))
+        else:
+            r = np.ascontiguousarray(np.broadcast_to(np.asarray(p_flip, np.float64), (self.n,)))
+            _check(lib.tqs_circuit_set_readout(self.h, _ptr(r, dbl)))
+        return self
+
     @property
     def n_gates(self) -> int:
         n, g = u32(), u32()
@@ -153,6 +165,8 @@ class Circuit:
         c = cls(wc.n)
         for q, m, p in wc.gates:
             c.add_gate(q, m, p)
+        if getattr(wc, "readout", None) is not None:
+            c.set_readout(wc.readout)
         return c
 
     def __del__(self):
@@ -197,7 +211,8 @@ class Noise:
         return cls(h)
 
     @classmethod
-    def from_arrays(cls, circuit: Circuit, tree, node_off, ev_gate, ev_code, leaf_u) -> "Noise":
+    def from_arrays(cls, circuit: Circuit, tree, node_off, ev_gate, ev_code, leaf_u,
+                    leaf_flip=None) -> "Noise":
         t = _Tree(*tree)
         no = np.ascontiguousarray(np.asarray(node_off, np.uint64))
         eg = np.ascontiguousarray(np.asarray(ev_gate, np.uint32))
@@ -208,7 +223,22 @@ class Noise:
         h = vp()
         _check(lib.tqs_noise_import(circuit.h, C.byref(t.s), _ptr(no, u64), _ptr(eg, u32),
                                     _ptr(ec, C.c_uint8), _ptr(lu, dbl), C.byref(h)))
-        return cls(h)
+        nz = cls(h)
+        if leaf_flip is not None:
+            lf = np.ascontiguousarray(np.asarray(leaf_flip, np.uint32))
+            assert lf.size == lu.size
+            _check(lib.tqs_noise_set_flips(h, _ptr(lf, u32)))
+        return nz
+
+    def flips(self):
+        """Copy of the read-out flip masks (uint32 per leaf), or None."""
+        f = P(u32)()
+        _check(lib.tqs_noise_flips(self.h, C.byref(f)))
+        if not f:
+            return None
+        nl = u64()
+        _check(lib.tqs_noise_view(self.h, None, None, None, None, None, C.byref(nl)))
+        return np.ctypeslib.as_array(f, (nl.value,)).copy()
 
     def arrays(self):
         """Copies of (node_off, ev_gate, ev_code, leaf_u)."""

@@ -154,6 +154,7 @@ class Circuit:
     n: int
     gates: list = field(default_factory=list)
     name: str = ""
+    readout: object = None  # per-qubit read-out flip probabilities, or None
 
     def add(self, qubits, mat, probs=None):
         self.gates.append((tuple(int(q) for q in qubits), np.asarray(mat, np.complex128),
@@ -170,6 +171,7 @@ class Circuit:
         for q, m, _ in self.gates:
             p = p1 if len(q) == 1 else p2
             out.add(q, m, depolarizing_probs(p, len(q)) if p > 0 else None)
+        out.readout = self.readout
         return out
 
     def with_noise(self, p1: float, p2: float, gamma: float = 0.0, lam: float = 0.0) -> "Circuit":
@@ -183,6 +185,14 @@ class Circuit:
             dep = depolarizing_probs(p1 if a == 1 else p2, a)
             pr = compose_pauli_channels(dep, per_qubit_channel(ch, a), a)
             out.add(q, m, pr if pr[0] < 1.0 else None)
+        out.readout = self.readout
+        return out
+
+    def with_readout(self, r) -> "Circuit":
+        """Copy with a read-out channel: bit q of each outcome flips with
+        probability r[q] (a scalar applies to every qubit)."""
+        out = Circuit(self.n, list(self.gates), self.name)
+        out.readout = np.broadcast_to(np.asarray(r, np.float64), (self.n,)).copy()
         return out
 
     def noiseless(self) -> "Circuit":

@@ -546,3 +546,29 @@ def test_merged_states_small_chunks_and_ranges(T):
     assert np.array_equal(out, base)
     parts = [T.run(plan, nz, subtrees=(a, b)) for a, b in [(0, 2), (2, 3), (3, 5)]]
     assert np.array_equal(np.concatenate(parts), base)
+
+
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+def test_readout_flips_on_device(T, prec):
+    # read-out flips XOR the measured bits on the device: outcomes equal the
+    # oracle's (trajectory, measurement, then flips), also for leaves that
+    # share a merged state, in single runs and in a batch
+    wc = W.qft(12).with_depolarizing(2e-3, 2e-2).with_readout(np.linspace(0.0, 0.3, 12))
+    G = len(wc)
+    tree = ([4, 8, 16], [0, G // 3, 2 * G // 3, G])
+    c = T.Circuit.from_workload(wc)
+    nz = T.Noise.sample(c, tree, 4)
+    onz = oracle.sample_noise(wc.gates, tree, 4, readout=wc.readout)
+    assert np.array_equal(nz.flips(), onz.leaf_flip)
+    plan = T.Plan(c, tree, prec)
+    out, st = T.run(plan, nz, stats=True)
+    assert st["nodes_merged"] > 0
+    oout, ost = oracle.run_leaves(wc.n, wc.gates, tree, onz, states=True)
+    bad = check_outcomes(out ^ onz.leaf_flip, oout ^ onz.leaf_flip, ost, onz.leaf_u, DELTA[prec])
+    assert bad <= 2
+    c0 = T.Circuit.from_workload(wc)
+    c0.set_readout(None)
+    plain = T.run(T.Plan(c0, tree, prec), T.Noise.sample(c0, tree, 4))
+    assert np.array_equal(out, plain ^ onz.leaf_flip.astype(np.uint64))
+    outs = T.Batch([plan, plan], [nz, nz]).run()
+    assert np.array_equal(outs[0], out) and np.array_equal(outs[1], out)

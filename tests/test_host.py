@@ -316,3 +316,22 @@ def test_one_hip_runtime_per_process():
     maps = open("/proc/self/maps").read().splitlines()
     hip = {ln.split()[-1] for ln in maps if "libamdhip64" in ln}
     assert len(hip) == 1, hip
+
+
+def test_readout_flips_match_oracle():
+    # the library's sampler draws the same read-out flips as the oracle's
+    wc = W.random_circuit(6, 40, seed=8, p1=0.1, p2=0.2).with_readout([0.02, 0.1, 0.3, 0.5, 0.0, 1.0])
+    tree = ([4, 6, 5], [0, 10, 25, 40])
+    c = T.Circuit.from_workload(wc)
+    nz = T.Noise.sample(c, tree, 123)
+    o = oracle.sample_noise(wc.gates, tree, 123, readout=wc.readout)
+    assert _same_noise(nz.arrays(), o)
+    assert np.array_equal(nz.flips(), o.leaf_flip)
+    # without the channel there are no masks; explicit masks round-trip
+    c.set_readout(None)
+    nz2 = T.Noise.sample(c, tree, 123)
+    assert nz2.flips() is None and _same_noise(nz2.arrays(), o)
+    nz3 = T.Noise.from_arrays(c, tree, *nz2.arrays(), leaf_flip=o.leaf_flip)
+    assert np.array_equal(nz3.flips(), o.leaf_flip)
+    with pytest.raises(T.TqsError):
+        c.set_readout([0.1, 0.2, 0.3, 0.4, 0.5, 1.5])

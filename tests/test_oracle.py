@@ -454,3 +454,69 @@ def test_adam_first_step_moves_by_lr():
     g = np.array([0.5, -2.0, 1e-3])
     p1, m, v = mlp.adam(np.zeros(3), g, np.zeros(3), np.zeros(3), 1, 0.01)
     assert np.allclose(p1, -0.01 * g / (np.abs(g) + 1e-8), atol=1e-12)
+
+
+# ------------------------------------------------------- read-out channel --
+
+def test_readout_extremes_and_unchanged_streams():
+    # r = 0 flips nothing, r = 1 flips every bit; the read-out draws come
+    # after every other draw of a leaf, so events and measurement uniforms
+    # are those of the same list without read-out
+    n, x = 5, 0b10110
+    wc = W.concat(W.basis_prep(n, x), W.qft(n), W.inverse(W.qft(n))).with_depolarizing(0.0, 0.0)
+    tree = ([4, 8], [0, 10, len(wc)])
+    base = oracle.sample_noise(wc.gates, tree, 5)
+    for r, mask in ((0.0, 0), (1.0, (1 << n) - 1)):
+        nz = oracle.sample_noise(wc.gates, tree, 5, readout=[r] * n)
+        assert np.array_equal(nz.node_off, base.node_off) and np.array_equal(nz.leaf_u, base.leaf_u)
+        assert np.all(nz.leaf_flip == mask)
+        out, _ = oracle.run_leaves(n, wc.gates, tree, nz)
+        assert np.all(out == (x ^ mask))
+
+
+def test_readout_draw_positions():
+    # leaf nu's flips are its draws j0 .. j0+n-1 with j0 = gates of its
+    # subcircuit (one uniform each) + its events (one more each) + 1
+    wc = W.random_circuit(4, 30, seed=3, p1=0.2, p2=0.3)
+    tree = ([3, 5], [0, 12, 30])
+    r = np.array([0.1, 0.5, 0.3, 0.9])
+    seed = 77
+    nz = oracle.sample_noise(wc.gates, tree, seed, readout=r)
+    first_leaf = 3
+    for m in range(15):
+        nu = first_leaf + m
+        ne = int(nz.node_off[nu + 1] - nz.node_off[nu])
+        j0 = (30 - 12) + ne + 1
+        want = sum(1 << q for q in range(4) if oracle.uniform(seed, nu, j0 + q) < r[q])
+        assert int(nz.leaf_flip[m]) == want
+
+
+def test_readout_histogram_matches_confusion_of_density_matrix():
+    # trajectories with read-out flips sample p'(y) = sum_x p(x) prod_q
+    # (r_q if x_q != y_q else 1 - r_q), p = diagonal of the noisy density
+    # matrix (an implementation independent of the trajectory code)
+    wc = W.brickwall(3, 3, seed=4).with_depolarizing(0.05, 0.1).with_readout([0.05, 0.2, 0.35])
+    rho = density.dm_run(wc.n, wc.gates)
+    p = np.real(np.diag(rho))
+    d = 1 << wc.n
+    conf = np.ones((d, d))
+    for y in range(d):
+        for x in range(d):
+            for q in range(wc.n):
+                conf[y, x] *= wc.readout[q] if ((x ^ y) >> q) & 1 else 1 - wc.readout[q]
+    want = conf @ p
+    S = 20000
+    tree = ([S], [0, len(wc)])
+    nz = oracle.sample_noise(wc.gates, tree, 9, readout=wc.readout)
+    out, _ = oracle.run_leaves(wc.n, wc.gates, tree, nz)
+    cnt = np.bincount(out.astype(np.int64), minlength=d)
+    sd = np.sqrt(S * want * (1 - want))
+    assert np.all(np.abs(cnt - S * want) <= 5 * sd + 1)
+    # and the flip masks alone: bit q set with rate r_q, bits independent
+    f = nz.leaf_flip
+    for q in range(wc.n):
+        k = int(np.sum((f >> q) & 1))
+        assert abs(k - S * wc.readout[q]) <= 5 * math.sqrt(S * wc.readout[q] * (1 - wc.readout[q]))
+    both = int(np.sum((f & 3) == 3))
+    r01 = wc.readout[0] * wc.readout[1]
+    assert abs(both - S * r01) <= 5 * math.sqrt(S * r01 * (1 - r01))
