@@ -51,15 +51,19 @@ def equal_cuts(G, levels):
 
 
 def time_form(T, torch, circuit, tree, seed, steps, warmup, tuning=None):
+    t0 = time.perf_counter()
     plan = T.Plan(circuit, tree, "c64", tuning)
+    t1 = time.perf_counter()
     nz = T.Noise.sample(circuit, tree, seed)
+    t2 = time.perf_counter()
     ws = T.Workspace(plan.workspace_bytes(nz))
     stream = torch.cuda.current_stream()
     for _ in range(warmup):
         T.run(plan, nz, ws, stream)
     torch.cuda.synchronize()
     agg = {"ms_passes": 0.0, "ms_sample": 0.0, "bytes_passes": 0, "bytes_sample": 0,
-           "pass_launches": 0, "ms_device": 0.0, "launches": 0, "nodes_merged": 0}
+           "pass_launches": 0, "ms_device": 0.0, "launches": 0, "nodes_merged": 0,
+           "host_plan_ms": (t1 - t0) * 1e3, "host_noise_ms": (t2 - t1) * 1e3}
     t0 = time.perf_counter()
     for _ in range(steps):
         out, st = T.run(plan, nz, ws, stream, stats=True)
@@ -280,7 +284,8 @@ def cpu_baseline(wc, seed, budget_s=15.0):
     import oracle
     n = wc.n
     G = len(wc)
-    threads = os.cpu_count() or 1
+    # the host cores this process may use (at most the job's share of 16)
+    threads = max(1, min(len(os.sched_getaffinity(0)), int(os.environ.get("OMP_NUM_THREADS", "16"))))
     tree = ([16384], [0, G])
     nz = oracle.sample_noise(wc.gates, tree, seed)
     # calibrate on one round of `threads` shots, then fill the budget
@@ -293,9 +298,22 @@ def cpu_baseline(wc, seed, budget_s=15.0):
     t0 = time.perf_counter()
     oracle.run_leaves(n, wc.gates, tree, nz, np.arange(S, S + S2, dtype=np.uint64), threads=threads)
     dt = time.perf_counter() - t0
+    # one thread, two trajectories
+    t0 = time.perf_counter()
+    oracle.run_leaves(n, wc.gates, tree, nz, np.arange(S + S2, S + S2 + 2, dtype=np.uint64), threads=1)
+    dt1 = time.perf_counter() - t0
+    model = ""
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": S2 / dt, "unit": "noisy shots/s", "cores": threads, "kind": "oracle",
             "sample": "%d of the 16384 per-shot trajectories of the same workload "
-                      "(complex128, %d threads, %.1f s)" % (S2, threads, dt)}
+                      "(complex128, %d threads, %.1f s)" % (S2, threads, dt),
+            "single_thread_shots_per_s": 2 / dt1, "cpu_model": model}
 
 
 def main():
@@ -383,6 +401,7 @@ def main():
                          "pass_launches_per_step": agg["pass_launches_per_step"],
                          "pass_launches": agg["pass_launches"],
                          "nodes_merged": agg["nodes_merged"],
+                         "host_plan_ms": agg["host_plan_ms"], "host_noise_ms": agg["host_noise_ms"],
                          "bytes_per_launch": agg["bytes_passes"] / max(agg["pass_launches"], 1),
                          "us_per_launch": agg["ms_passes"] * 1e3 / max(agg["pass_launches"], 1)}
         print("# %s: %.1f shots/s, %.2f ms/step, pass %.0f GB/s" %
@@ -411,7 +430,8 @@ def main():
                      "kernel": "pass_kernel<float>",
                      "algorithmic_bytes_per_launch": h["bytes_per_launch"],
                      "us_per_launch": h["us_per_launch"], "launches": h["pass_launches"]},
-        "forms": {k: {kk: v[kk] for kk in ("shots_per_s", "ms_per_step", "pass_GBps", "shape", "nodes_merged")}
+        "forms": {k: {kk: v[kk] for kk in ("shots_per_s", "ms_per_step", "pass_GBps", "shape", "nodes_merged",
+                                           "host_plan_ms", "host_noise_ms")}
                   for k, v in results.items()},
     }
     # per-shot without merged states is the baseline the tree is measured

@@ -183,7 +183,7 @@ def run_leaves(n, gates, tree, noise: Noise, leaves=None, states=False, threads=
     outcomes = np.zeros(max(leaves.size, 1), np.uint64)
     st = np.zeros((leaves.size, 1 << n), np.complex128) if states else None
     if threads is None:
-        threads = os.cpu_count() or 1
+        threads = max(1, min(len(os.sched_getaffinity(0)), 16))
     ev_gate = np.ascontiguousarray(noise.ev_gate, np.uint32)
     ev_code = np.ascontiguousarray(noise.ev_code, np.uint8)
     if ev_gate.size == 0:

@@ -171,7 +171,8 @@ class Circuit:
 
     def __del__(self):
         h = getattr(self, "h", None)
-        if h is not None and h.value:
+        # (at interpreter exit the module globals may already be gone)
+        if h is not None and h.value and lib is not None:
             lib.tqs_circuit_destroy(h)
             self.h = vp()
 
@@ -255,7 +256,8 @@ class Noise:
 
     def __del__(self):
         h = getattr(self, "h", None)
-        if h is not None and h.value:
+        # (at interpreter exit the module globals may already be gone)
+        if h is not None and h.value and lib is not None:
             lib.tqs_noise_destroy(h)
             self.h = vp()
 
@@ -299,7 +301,8 @@ class Plan:
 
     def __del__(self):
         h = getattr(self, "h", None)
-        if h is not None and h.value:
+        # (at interpreter exit the module globals may already be gone)
+        if h is not None and h.value and lib is not None:
             lib.tqs_plan_destroy(h)
             self.h = vp()
 
@@ -416,7 +419,8 @@ class Batch:
 
     def __del__(self):
         h = getattr(self, "h", None)
-        if h is not None and h.value:
+        # (at interpreter exit the module globals may already be gone)
+        if h is not None and h.value and lib is not None:
             lib.tqs_batch_destroy(h)
 
 
