@@ -183,18 +183,19 @@ def batch_bench(T, W, torch, seed, shots=2048, budget_gib=32):
     (default tuning) against batches (runs grouped in qubit order up to a
     workspace budget, each batch advancing its runs together), with the
     default tuning and with the tile width and pass bound autotuned per
-    family and size; also the 12-16 qubit runs alone, where launches, not
-    bytes, dominate."""
+    family and size, and with the launches replayed from a recorded graph;
+    the same runs as (8, 16, 16) trees, one after another and batched; also
+    the 12-16 qubit runs alone, where launches, not bytes, dominate."""
     import numpy as np
     from paper_2203_13892_amd import autotune as AT
     circs = batch_workload(W)
 
-    def build(tunings):
+    def build(tunings, shape=None):
         items = []
         for i, (name, wc) in enumerate(circs):
             G = len(wc)
             c = T.Circuit.from_workload(wc)
-            tree = ([shots], [0, G])
+            tree = ([shots], [0, G]) if shape is None else (list(shape), equal_cuts(G, len(shape)))
             tun = dict(tunings.get(name.split("_")[0], {}))
             # live states per run: about 256 MiB of states, at most 512
             tun["chunk_states"] = int(max(1, min(512, (256 << 20) // (8 << wc.n))))
@@ -211,7 +212,7 @@ def batch_bench(T, W, torch, seed, shots=2048, budget_gib=32):
         out = [T.run(p, nz, ws) for _, p, nz, _ in items]
         return time.perf_counter() - t0, out
 
-    def batched(items):
+    def batched(items, graph=False):
         order = sorted(range(len(items)), key=lambda k: (items[k][3], items[k][0]))
         groups, cur, cur_b, cur_t = [], [], 0, None
         for k in order:
@@ -225,7 +226,13 @@ def batch_bench(T, W, torch, seed, shots=2048, budget_gib=32):
         groups.append(cur)
         batches = [T.Batch([items[k][1] for k in g], [items[k][2] for k in g]) for g in groups]
         ws = T.Workspace(max(bt.info()["workspace_bytes"] for bt in batches))
-        batches[0].run(ws)
+        if graph:
+            # record each batch's launches once; the timed runs replay them
+            for bt in batches:
+                bt.use_graph(True)
+                bt.run(ws)
+        else:
+            batches[0].run(ws)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         res = [bt.run(ws) for bt in batches]
@@ -249,6 +256,10 @@ def batch_bench(T, W, torch, seed, shots=2048, budget_gib=32):
     note("batched %.2f s in %d batches" % (t_bat, nb))
     rec["sequential_s"], rec["batched_s"], rec["batches"] = t_seq, t_bat, nb
     rec["outcomes_identical"] = bool(all(np.array_equal(a, b) for a, b in zip(seq, bat)))
+    t_bg, bat_g, _ = batched(items, graph=True)
+    note("batched, graph replay %.2f s" % t_bg)
+    rec["batched_graph_s"] = t_bg
+    rec["graph_outcomes_identical"] = bool(all(np.array_equal(a, b) for a, b in zip(seq, bat_g)))
     # autotuned tile width and pass bound per family and size
     tunings, t_tune = {}, time.perf_counter()
     for name, wc in circs:
@@ -262,18 +273,29 @@ def batch_bench(T, W, torch, seed, shots=2048, budget_gib=32):
     note("autotuned batched %.2f s" % t_auto)
     rec["autotuned_batched_s"], rec["autotune_s"], rec["autotuned_batches"] = t_auto, t_tune, nb_a
     rec["tunings"] = tunings
+    # the same runs as trees (8, 16, 16): tree reuse and batching together
+    items_tree = build({}, (8, 16, 16))
+    t_tseq, tseq = sequential(items_tree)
+    t_tbat, tbat, _ = batched(items_tree)
+    note("trees (8, 16, 16): one after another %.2f s, batched %.2f s" % (t_tseq, t_tbat))
+    rec["tree_shape"] = [8, 16, 16]
+    rec["tree_sequential_s"], rec["tree_batched_s"] = t_tseq, t_tbat
+    rec["tree_outcomes_identical"] = bool(all(np.array_equal(a, b) for a, b in zip(tseq, tbat)))
+    del items_tree, tseq, tbat
     # the small runs alone
     small = [it for it in items if it[0] <= 16]
     t_ss, _ = sequential(small)
     t_sb, _, _ = batched(small)
+    t_sg, _, _ = batched(small, graph=True)
     rec["small_runs"] = len(small)
-    rec["small_sequential_s"], rec["small_batched_s"] = t_ss, t_sb
-    for k in ("sequential", "batched", "autotuned_batched"):
+    rec["small_sequential_s"], rec["small_batched_s"], rec["small_batched_graph_s"] = t_ss, t_sb, t_sg
+    for k in ("sequential", "batched", "batched_graph", "autotuned_batched", "tree_sequential", "tree_batched"):
         rec[k + "_shots_per_s"] = rec["shots_total"] / rec[k + "_s"]
     rec["small_batch_speedup"] = t_ss / t_sb
+    rec["small_batch_graph_speedup"] = t_ss / t_sg
     print("# batch: sequential %.2f s, batched %.2f s (%d batches, identical %s), autotuned batched %.2f s; "
-          "12-16q runs: sequential %.3f s, batched %.3f s" % (t_seq, t_bat, nb, rec["outcomes_identical"], t_auto,
-                                                              t_ss, t_sb), file=sys.stderr, flush=True)
+          "12-16q runs: sequential %.3f s, batched %.3f s, graph replay %.3f s" % (
+              t_seq, t_bat, nb, rec["outcomes_identical"], t_auto, t_ss, t_sb, t_sg), file=sys.stderr, flush=True)
     return rec
 
 

@@ -272,6 +272,14 @@ tqs_status tqs_batch_info(const tqs_batch *b, uint64_t *workspace_bytes, uint64_
  * stats (nullable) gets ms_device, ms_wall and launches. */
 tqs_status tqs_batch_run(tqs_batch *b, void *d_workspace, uint64_t ws_bytes, void *stream,
                          uint64_t *outcomes, tqs_run_stats *stats);
+/* Replay (on != 0) or plain launches (0, the default) for later runs: with
+ * replay, the batch's kernel launches are recorded once into a HIP graph on
+ * a private stream (for the workspace address of that run; a run with
+ * another workspace records again) and each run launches the graph on its
+ * stream after the usual metadata upload, which cuts the host cost of the
+ * many small launches of small circuits.  Outcomes are the same either way. */
+tqs_status tqs_batch_use_graph(tqs_batch *b, uint32_t on);
+
 void tqs_batch_destroy(tqs_batch *b);
 
 /* ------------------------------------------------- learned tree shape ---

@@ -1105,6 +1105,12 @@ struct tqs_batch {
     std::vector<uint32_t> npass, nsamp;  // segments per step
     uint64_t table_at = 0, table_bytes = 0, total = 0, leaves = 0;
     std::vector<void *> events;
+    // launch replay: the steps' kernels recorded once into a HIP graph on a
+    // private stream, for the workspace they were recorded with
+    bool use_graph = false;
+    void *graph_exec = nullptr;    // hipGraphExec_t
+    void *capture_stream = nullptr;  // hipStream_t
+    const unsigned char *graph_ws = nullptr;
 };
 
 namespace tqs {
@@ -1178,24 +1184,62 @@ static tqs_status batch_run_t(tqs_batch *B, unsigned char *ws, uint64_t ws_bytes
         }
     }
     HIP_TRY(hipMemcpyAsync(ws + B->table_at, tb.data(), tb.size(), hipMemcpyHostToDevice, s), "table upload");
-    for (uint32_t k = 0; k < B->steps; k++) {
-        if (B->npass[k]) {
-            PassLaunch<R> pl;
-            std::memset(&pl, 0, sizeof pl);
-            pl.segs = reinterpret_cast<const PassArgs<R> *>(ws + B->table_at + pass_at[k]);
-            pl.nseg = B->npass[k];
-            pl.total = pass_total[k];
-            launch_pass_kernel<R>(B->reg_bits, pass_d2[k] != 0, pl, s);
+    // the kernel arguments depend only on the batch and the workspace
+    // address, so one recording serves every later run with that workspace
+    auto launch_steps = [&](hipStream_t ls) -> tqs_status {
+        for (uint32_t k = 0; k < B->steps; k++) {
+            if (B->npass[k]) {
+                PassLaunch<R> pl;
+                std::memset(&pl, 0, sizeof pl);
+                pl.segs = reinterpret_cast<const PassArgs<R> *>(ws + B->table_at + pass_at[k]);
+                pl.nseg = B->npass[k];
+                pl.total = pass_total[k];
+                launch_pass_kernel<R>(B->reg_bits, pass_d2[k] != 0, pl, ls);
+            }
+            if (B->nsamp[k]) {
+                SampleLaunch<R> sl;
+                std::memset(&sl, 0, sizeof sl);
+                sl.segs = reinterpret_cast<const SampleArgs<R> *>(ws + B->table_at + samp_at[k]);
+                sl.nseg = B->nsamp[k];
+                const uint32_t g[3] = {samp_total[k][0], samp_total[k][1], samp_total[k][2]};
+                launch_sample_kernels(sl, g, ls);
+            }
+            HIP_TRY(hipGetLastError(), "kernel launch");
         }
-        if (B->nsamp[k]) {
-            SampleLaunch<R> sl;
-            std::memset(&sl, 0, sizeof sl);
-            sl.segs = reinterpret_cast<const SampleArgs<R> *>(ws + B->table_at + samp_at[k]);
-            sl.nseg = B->nsamp[k];
-            const uint32_t g[3] = {samp_total[k][0], samp_total[k][1], samp_total[k][2]};
-            launch_sample_kernels(sl, g, s);
+        return TQS_OK;
+    };
+    if (B->use_graph) {
+        if (!B->graph_exec || B->graph_ws != ws) {
+            if (B->graph_exec) {
+                (void)hipGraphExecDestroy((hipGraphExec_t)B->graph_exec);
+                B->graph_exec = nullptr;
+            }
+            if (!B->capture_stream) {
+                hipStream_t cs = nullptr;
+                HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "hipStreamCreate");
+                B->capture_stream = (void *)cs;
+            }
+            hipStream_t cs = (hipStream_t)B->capture_stream;
+            HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed), "hipStreamBeginCapture");
+            tqs_status st = launch_steps(cs);
+            hipGraph_t g = nullptr;
+            const hipError_t ec = hipStreamEndCapture(cs, &g);
+            if (st) {
+                if (g) (void)hipGraphDestroy(g);
+                return st;
+            }
+            HIP_TRY(ec, "hipStreamEndCapture");
+            hipGraphExec_t ex = nullptr;
+            const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            HIP_TRY(ei, "hipGraphInstantiate");
+            B->graph_exec = (void *)ex;
+            B->graph_ws = ws;
         }
-        HIP_TRY(hipGetLastError(), "kernel launch");
+        HIP_TRY(hipGraphLaunch((hipGraphExec_t)B->graph_exec, s), "hipGraphLaunch");
+    } else {
+        tqs_status st = launch_steps(s);
+        if (st) return st;
     }
     for (BatchItem &it : B->items)
         HIP_TRY(hipMemcpyAsync(outcomes + it.leaf_base, ws + it.Ly.off_out, it.p->n_leaves * 8,
@@ -1409,8 +1453,16 @@ extern "C" tqs_status tqs_batch_run(tqs_batch *b, void *d_workspace, uint64_t ws
     TQS_GUARD_END
 }
 
+extern "C" tqs_status tqs_batch_use_graph(tqs_batch *b, uint32_t on) {
+    if (!b) return fail(TQS_E_ARG, "batch is NULL");
+    b->use_graph = on != 0;
+    return TQS_OK;
+}
+
 extern "C" void tqs_batch_destroy(tqs_batch *b) {
     if (!b) return;
     for (void *e : b->events) (void)hipEventDestroy((hipEvent_t)e);
+    if (b->graph_exec) (void)hipGraphExecDestroy((hipGraphExec_t)b->graph_exec);
+    if (b->capture_stream) (void)hipStreamDestroy((hipStream_t)b->capture_stream);
     delete b;
 }

@@ -68,6 +68,7 @@ SIGNATURES = {
     "tqs_plan_describe": (i32, [vp, C.c_char_p, u64, P(u64)]),
     "tqs_batch_create": (i32, [P(vp), P(vp), u32, P(vp)]),
     "tqs_batch_info": (i32, [vp, P(u64), P(u64), P(u32)]),
+    "tqs_batch_use_graph": (i32, [vp, u32]),
     "tqs_batch_run": (i32, [vp, vp, u64, vp, P(u64), P(TqsRunStats)]),
     "tqs_batch_destroy": (None, [vp]),
     "tqs_mlp_param_count": (u64, [u32, u32, u32]),
@@ -401,6 +402,12 @@ class Batch:
         ws, lv, st = u64(), u64(), u32()
         _check(lib.tqs_batch_info(self.h, C.byref(ws), C.byref(lv), C.byref(st)))
         return {"workspace_bytes": ws.value, "leaves": lv.value, "steps": st.value}
+
+    def use_graph(self, on: bool = True):
+        """Record the launches once into a HIP graph and replay it on later
+        runs (per workspace address)."""
+        _check(lib.tqs_batch_use_graph(self.h, 1 if on else 0))
+        return self
 
     def run(self, workspace=None, stream=None, stats=False):
         """Per-run outcome arrays (and the stats dict with ``stats``)."""

@@ -572,3 +572,39 @@ def test_readout_flips_on_device(T, prec):
     assert np.array_equal(out, plain ^ onz.leaf_flip.astype(np.uint64))
     outs = T.Batch([plan, plan], [nz, nz]).run()
     assert np.array_equal(outs[0], out) and np.array_equal(outs[1], out)
+
+
+def test_batch_graph_replay_equals_plain_launches(T):
+    # the recorded launches replayed several times, with other device work
+    # and synchronisations in between, and again after a workspace change,
+    # give the plain launches' outcomes every time
+    import torch
+    specs = [(W.qft(10).with_depolarizing(1e-2, 5e-2), [32]),
+             (W.ghz(12).with_depolarizing(1e-2, 5e-2), [4, 4, 2]),
+             (W.brickwall(11, 6, seed=2).with_depolarizing(1e-2, 3e-2), [6, 6])]
+    plans, noises = [], []
+    for i, (wc, A) in enumerate(specs):
+        G = len(wc)
+        tree = (A, [round(j * G / len(A)) for j in range(len(A) + 1)])
+        c = T.Circuit.from_workload(wc)
+        plans.append(T.Plan(c, tree, "c64", {"chunk_states": 5}))
+        noises.append(T.Noise.sample(c, tree, 40 + i))
+    b = T.Batch(plans, noises)
+    need = b.info()["workspace_bytes"]
+    ws = T.Workspace(need)
+    want = b.run(ws)
+    b.use_graph(True)
+    other = T.Plan(T.Circuit.from_workload(specs[0][0]), ([8], [0, len(specs[0][0])]), "c64")
+    other_nz = T.Noise.sample(T.Circuit.from_workload(specs[0][0]), ([8], [0, len(specs[0][0])]), 3)
+    for rep in range(3):
+        got = b.run(ws)
+        assert all(np.array_equal(g, w) for g, w in zip(got, want)), rep
+        T.run(other, other_nz)
+        torch.cuda.synchronize()
+    ws2 = T.Workspace(need)
+    for rep in range(2):
+        got = b.run(ws2)
+        assert all(np.array_equal(g, w) for g, w in zip(got, want)), rep
+    b.use_graph(False)
+    got = b.run(ws)
+    assert all(np.array_equal(g, w) for g, w in zip(got, want))
