@@ -96,6 +96,9 @@ typedef struct {
                                   noise events are equal share one state (Sec. 6,
                                   inter-shot redundancy; most often siblings without an
                                   event), each leaf still sampled with its own draw */
+    uint32_t separate_sampling; /* 1: sampling reads the final states in kernels of its own.
+                                  Default 0: the last pass of the leaf level also writes
+                                  the FP64 sampling partial sums when its tile allows */
 } tqs_tuning;
 
 /* Timing and traffic of one run. */
@@ -222,6 +225,9 @@ tqs_status tqs_workspace_bytes(const tqs_plan *p, const tqs_noise *nz, uint64_t 
  *   pass <p> <op count> regs <register positions...>
  *   dense <arity> <phys q0> <phys q1> <slot0> <slot1> | <row-major matrix, re im ...>
  *   diag <slot0> <slot1> | <arity> <phys q0> <phys q1> <diagonal, re im ...> | ...
+ *   sampling <tiled> <pattern bits> <tile bits> <in-block tile bits> <summed bits> | <source
+ *        of each block-index bit: 128 + pattern bit, or tile bit>  (tiled = 1: the last
+ *        leaf pass writes per-tile partial masses, lane positions first, then registers)
  * Ops run in the listed order; gate slot s of a pass lies between ops whose
  * slot ranges end at s and begin at s.  A dense op with no circuit gate in
  * its slot is a lane exchange (a swap of two positions). */

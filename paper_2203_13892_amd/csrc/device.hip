@@ -102,6 +102,11 @@ struct SampleMap {
     uint32_t cmask;     // positions of logical qubits b..n-1 (block bits)
     uint32_t smask;     // positions of logical qubits 0..b-1
     uint8_t lay[32];    // logical qubit -> physical position
+    // partials written per tile by the last leaf pass instead (tiled != 0):
+    // pattern bits, tile-index bits, tile-index bits inside a block, and
+    // per block-index bit its source (0x80 | pattern bit, or tile bit)
+    uint32_t tiled, kv, nfree, tfree;
+    uint8_t bsrc[32];
 };
 
 // Sampling of one chunk of leaves of one plan (a segment of a launch).
@@ -239,9 +244,37 @@ __global__ __launch_bounds__(kThreads) void block_gather_kernel(SampleLaunch<R> 
     const uint32_t nblocks = 1u << (m.n - m.b);
     const uint64_t gid = (uint64_t)local * kThreads + threadIdx.x;
     if (gid >= (uint64_t)sa.reps * nblocks) return;
-    const uint32_t k = (uint32_t)(gid / nblocks), B = (uint32_t)(gid % nblocks);
     const double *part = sa.part;
     double *sums = sa.sums;
+    if (m.tiled) {
+        // partials per tile: thread = (state, fixed block bits, pattern), so
+        // neighbouring threads read neighbouring patterns; the sum runs over
+        // the tiles that differ in in-block positions only, in increasing order
+        const uint32_t k = (uint32_t)(gid / nblocks), r = (uint32_t)(gid % nblocks);
+        const uint32_t jv = r & ((1u << m.kv) - 1u), tc = r >> m.kv;
+        uint32_t B = 0, tfix = 0;
+        for (uint32_t i = 0, nf = 0; i < m.n - m.b; i++) {
+            const uint32_t src = m.bsrc[i];
+            uint32_t bit;
+            if (src & 0x80u) {
+                bit = (jv >> (src & 0x7Fu)) & 1u;
+            } else {
+                bit = (tc >> nf++) & 1u;
+                tfix |= bit << src;
+            }
+            B |= bit << i;
+        }
+        const double *pk = part + ((uint64_t)k << (m.nfree + m.kv));
+        double acc = 0.0;
+        uint32_t sub = 0;
+        do {
+            acc += pk[((uint64_t)(tfix | sub) << m.kv) | jv];
+            sub = (sub - m.tfree) & m.tfree;  // next subset of tfree, increasing
+        } while (sub != 0);
+        sums[(uint64_t)k * nblocks + B] = acc;
+        return;
+    }
+    const uint32_t k = (uint32_t)(gid / nblocks), B = (uint32_t)(gid % nblocks);
     uint32_t pb = 0;
     for (uint32_t q = m.b; q < m.n; q++) pb |= ((B >> (q - m.b)) & 1u) << m.lay[q];
     uint32_t j = 0, nc = 0;
@@ -517,7 +550,8 @@ static Layout make_layout(const tqs_plan *p, uint64_t n_events, uint64_t n_leave
     const uint64_t nblocks = 1ull << (p->n - p->sample_b);
     o = align256(o + (uint64_t)p->chunk.back() * nblocks * 8);
     L.off_part = o;
-    o = align256(o + ((uint64_t)p->chunk.back() << p->part_log) * 8);
+    o = align256(o + std::max((uint64_t)p->chunk.back() << p->part_log,
+                              (uint64_t)p->chunk.back() << (p->samp_nfree + p->samp_kv)) * 8);
     L.off_out = o;
     o = align256(o + n_leaves_out * 8);
     L.total = o;
@@ -746,6 +780,15 @@ static PassArgs<R> pass_args(const tqs_plan *p, const Layout &Ly, unsigned char 
     a.meta.ev_dz = reinterpret_cast<const uint32_t *>(ws + Ly.off_evdz);
     a.terms = reinterpret_cast<const DiagTerm *>(ws + Ly.off_terms);
     a.dgates = reinterpret_cast<const DiagGate *>(ws + Ly.off_dgates);
+    // the last pass of the leaf level writes the sampling partials
+    const tqs::Level &ll = p->levels.back();
+    a.part = nullptr;
+    a.psum = 0;
+    a.pad = 0;
+    if (p->samp_tiled && t.level + 1 == p->levels.size() && pass_idx + 1 == ll.pass_begin + ll.pass_count) {
+        a.part = reinterpret_cast<double *>(ws + Ly.off_part);
+        a.psum = p->samp_psum;
+    }
     return a;
 }
 
@@ -798,6 +841,11 @@ static SampleMap sample_map(const tqs_plan *p) {
     }
     m.kc = (uint32_t)__builtin_popcount(m.cmask & ((1u << m.c) - 1u));
     m.part_log = p->part_log;
+    m.tiled = p->samp_tiled;
+    m.kv = p->samp_kv;
+    m.nfree = p->samp_nfree;
+    m.tfree = p->samp_tfree;
+    std::memcpy(m.bsrc, p->samp_bsrc, sizeof m.bsrc);
     return m;
 }
 
@@ -837,14 +885,14 @@ static SampleArgs<R> sample_args(const tqs_plan *p, const Layout &Ly, unsigned c
 // Workgroups of the partials / gather / sample launches for one segment.
 template <typename R>
 static void sample_grid(const SampleArgs<R> &a, uint32_t g[3]) {
-    g[0] = a.reps << (a.m.n - a.m.c);
+    g[0] = a.m.tiled ? 0u : a.reps << (a.m.n - a.m.c);
     g[1] = (uint32_t)((((uint64_t)a.reps << (a.m.n - a.m.b)) + kThreads - 1) / kThreads);
     g[2] = a.count;
 }
 
 template <typename R>
 static void launch_sample_kernels(const SampleLaunch<R> &sl, const uint32_t grid[3], hipStream_t s) {
-    hipLaunchKernelGGL(block_partials_kernel<R>, dim3(grid[0]), dim3(kThreads), 0, s, sl);
+    if (grid[0]) hipLaunchKernelGGL(block_partials_kernel<R>, dim3(grid[0]), dim3(kThreads), 0, s, sl);
     hipLaunchKernelGGL(block_gather_kernel<R>, dim3(grid[1]), dim3(kThreads), 0, s, sl);
     hipLaunchKernelGGL(sample_kernel<R>, dim3(grid[2]), dim3(kThreads), 0, s, sl);
 }

@@ -106,6 +106,12 @@ struct PassArgs {
     const DiagTerm *terms;
     const DiagGate *dgates;
     NodeMeta meta;
+    // sampling partials of the written states (last pass of the leaf level;
+    // NULL otherwise): per state and tile, the FP64 mass of each pattern of
+    // the block-index bits that vary inside the tile
+    double *part;
+    uint32_t psum;  // lane bits summed (bits 0-7), register bits summed (8-15), pattern bits (16-23)
+    uint32_t pad;
 };
 
 // A launch: one segment passed by value, or a table of segments (passes
@@ -709,6 +715,59 @@ struct PassWaves {
     static constexpr int value = (sizeof(R) == 4 && RB <= 5) ? 3 : 1;
 };
 
+// Sampling partials of a full tile (64 lanes, RB registers) in the final
+// layout: |amplitude|^2 in FP64, summed over the in-block positions that
+// vary inside the tile (registers by pairs, lanes by shuffles), leaving one
+// mass per pattern of the block-index positions that vary inside it.
+// Pattern bits: the block-index lane positions in increasing order, then
+// the block-index register bits in register order.  Written to
+// part[(state * tiles + tile) << kv | pattern], each lane holding a pattern
+// of its own for every remaining register index.
+template <typename R, int RB>
+__device__ __forceinline__ void tile_partials(const cplx<R> (&v)[1 << RB], const PassArgs<R> &a, uint32_t traj,
+                                              uint32_t tile, uint32_t nfree, uint32_t L) {
+    constexpr int NJ = 1 << RB;
+    const uint32_t fold_l = a.psum & 0xFFu, fold_r = (a.psum >> 8) & 0xFFu, kv = (a.psum >> 16) & 0xFFu;
+    double p[NJ];
+    sfor<NJ>([&](auto Jc) __attribute__((always_inline)) {
+        constexpr int j = decltype(Jc)::value;
+        p[j] = (double)v[j].re * (double)v[j].re + (double)v[j].im * (double)v[j].im;
+    });
+    sfor<RB>([&](auto Ic) __attribute__((always_inline)) {
+        constexpr int i = decltype(Ic)::value;
+        if ((fold_r >> i) & 1u) {
+            sfor<NJ>([&](auto Jc) __attribute__((always_inline)) {
+                constexpr int j = decltype(Jc)::value;
+                if constexpr (!(j & (1 << i))) p[j] += p[j | (1 << i)];
+            });
+        }
+    });
+    for (uint32_t b = 0; b < kLaneBits; b++) {
+        if (!((fold_l >> b) & 1u)) continue;
+        sfor<NJ>([&](auto Jc) __attribute__((always_inline)) {
+            constexpr int j = decltype(Jc)::value;
+            if (((uint32_t)j & fold_r) == 0) p[j] += __shfl_xor(p[j], (int)(1u << b));
+        });
+    }
+    if (L & fold_l) return;
+    // lane pattern: the lane's block-index bits, compressed
+    uint32_t lp = 0, nlc = 0;
+    for (uint32_t b = 0; b < kLaneBits; b++)
+        if (!((fold_l >> b) & 1u)) lp |= ((L >> b) & 1u) << nlc++;
+    double *out = a.part + (((uint64_t)traj << nfree | tile) << kv);
+    sfor<NJ>([&](auto Jc) __attribute__((always_inline)) {
+        constexpr int j = decltype(Jc)::value;
+        if (((uint32_t)j & fold_r) == 0) {
+            uint32_t rp = 0, nrc = 0;
+            sfor<RB>([&](auto Ic) __attribute__((always_inline)) {
+                constexpr int i = decltype(Ic)::value;
+                if (!((fold_r >> i) & 1u)) rp |= (uint32_t)((j >> i) & 1) << nrc++;
+            });
+            out[lp | (rp << nlc)] = p[j];
+        }
+    });
+}
+
 template <typename R, int RB, bool D2>
 __global__ __launch_bounds__(64, (PassWaves<R, RB>::value)) void pass_kernel(PassLaunch<R> pl) {
     constexpr int NJ = 1 << RB;
@@ -855,6 +914,7 @@ __global__ __launch_bounds__(64, (PassWaves<R, RB>::value)) void pass_kernel(Pas
             if ((uint32_t)j < jmax && lane_ok) (dst + reg_off(Jc))[L] = v[j];
         });
     }
+    if (a.part && full) tile_partials<R, RB>(v, a, traj, tile, nfree, L);
 }
 
 }  // namespace tqs

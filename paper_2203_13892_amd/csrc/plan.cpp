@@ -512,6 +512,50 @@ extern "C" tqs_status tqs_plan_create(const tqs_circuit *c, const tqs_tree *tree
         for (uint32_t q = p->sample_b; q < n; q++) cmask |= 1u << lay[q];
         const uint32_t kc = (uint32_t)__builtin_popcount(cmask & ((1u << cbits) - 1u));
         p->part_log = n - cbits + kc;
+        // partials from the final tile of the last leaf pass
+        const tqs::Level &ll = p->levels.back();
+        if (!tu.separate_sampling && ll.pass_count > 0) {
+            const tqs::PassDesc &pd = p->passes[ll.pass_begin + ll.pass_count - 1];
+            uint32_t smask = 0;
+            for (uint32_t q = 0; q < p->sample_b; q++) smask |= 1u << lay[q];
+            const uint32_t rb = p->reg_bits;
+            if (pd.nl == kLaneBits && pd.nr == rb) {
+                const uint32_t fold_l = smask & ((1u << kLaneBits) - 1u);
+                uint32_t fold_r = 0;
+                for (uint32_t i = 0; i < rb; i++)
+                    if ((smask >> pd.rq[i]) & 1u) fold_r |= 1u << i;
+                const uint32_t nlc = kLaneBits - (uint32_t)__builtin_popcount(fold_l);
+                const uint32_t kv = nlc + rb - (uint32_t)__builtin_popcount(fold_r);
+                if (kv + 3 <= kLaneBits + rb) {
+                    p->samp_tiled = 1;
+                    p->samp_psum = fold_l | fold_r << 8 | kv << 16;
+                    p->samp_kv = kv;
+                    p->samp_nfree = pd.nfree;
+                    for (uint32_t t = 0; t < pd.nfree; t++)
+                        if ((smask >> pd.fbits[t]) & 1u) p->samp_tfree |= 1u << t;
+                    for (uint32_t q = p->sample_b; q < n; q++) {
+                        const uint32_t P = lay[q];
+                        uint8_t src = 0;
+                        if (P < kLaneBits) {
+                            src = (uint8_t)(0x80u | (uint32_t)__builtin_popcount(~fold_l & ((1u << P) - 1u)));
+                        } else {
+                            bool found = false;
+                            for (uint32_t i = 0; i < rb && !found; i++)
+                                if (pd.rq[i] == P) {
+                                    src = (uint8_t)(0x80u | (nlc + (uint32_t)__builtin_popcount(~fold_r & ((1u << i) - 1u))));
+                                    found = true;
+                                }
+                            for (uint32_t t = 0; t < pd.nfree && !found; t++)
+                                if (pd.fbits[t] == P) {
+                                    src = (uint8_t)t;
+                                    found = true;
+                                }
+                        }
+                        p->samp_bsrc[q - p->sample_b] = src;
+                    }
+                }
+            }
+        }
     }
     if (p->passes.size() >= (1u << 16)) {
         delete p;
@@ -580,6 +624,9 @@ extern "C" tqs_status tqs_plan_describe(const tqs_plan *p, char *buf, uint64_t c
             s += "\n";
         }
     }
+    put("sampling %u %u %u %u %u |", p->samp_tiled, p->samp_kv, p->samp_nfree, p->samp_tfree, p->samp_psum);
+    for (uint32_t q = p->sample_b; q < p->n; q++) put(" %u", (uint32_t)p->samp_bsrc[q - p->sample_b]);
+    s += "\n";
     *len = s.size() + 1;
     if (buf && cap) {
         const uint64_t k = std::min<uint64_t>(cap - 1, s.size());

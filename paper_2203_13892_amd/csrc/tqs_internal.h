@@ -163,6 +163,13 @@ struct tqs_plan {
     // (swap gates and the planner's lane exchanges permute positions)
     std::vector<uint32_t> lay_final;
     uint32_t part_log = 0;  // log2 of the sampling partial sums per state
+    // sampling partials written by the last pass of the leaf level (when
+    // its final tile is full and leaves at least 8 amplitudes per partial):
+    // lane bits summed | register bits summed << 8 | pattern bits << 16,
+    // tile-index bits, tile-index bits inside a block, and per block-index
+    // bit its source: 0x80 | pattern bit, or the tile-index bit
+    uint32_t samp_tiled = 0, samp_psum = 0, samp_kv = 0, samp_nfree = 0, samp_tfree = 0;
+    uint8_t samp_bsrc[32] = {0};
     std::vector<uint32_t> chunk;  // live states per level
     uint32_t sample_b = 12;
     std::vector<void *> events;  // hipEvent_t pool for run statistics

@@ -608,3 +608,33 @@ def test_batch_graph_replay_equals_plain_launches(T):
     b.use_graph(False)
     got = b.run(ws)
     assert all(np.array_equal(g, w) for g, w in zip(got, want))
+
+
+@pytest.mark.parametrize("case", ["qft14", "bw13", "swaps16"])
+def test_partials_from_last_pass_equal_separate_sampling(T, case):
+    # the last leaf pass writes the sampling partials (per tile, in the
+    # final layout); outcomes equal the separate partials kernel's and the
+    # oracle's except at CDF-boundary leaves
+    rng = np.random.default_rng(50)
+    if case == "qft14":
+        wc = W.qft(14).with_depolarizing(2e-3, 2e-2)
+    elif case == "bw13":
+        wc = W.brickwall(13, 10, seed=4).with_depolarizing(2e-3, 2e-2)
+    else:
+        wc = mixed_gates(16, 50, rng)
+        for i in range(8):
+            wc.add((i, 15 - i), W.swap())
+    G = len(wc)
+    tree = ([4, 4, 4], [0, G // 3, 2 * G // 3, G])
+    c = T.Circuit.from_workload(wc)
+    arr = event_arrays(wc, tree, rng, rate=0.02) if case == "swaps16" else None
+    nz = T.Noise.from_arrays(c, tree, *arr) if arr is not None else T.Noise.sample(c, tree, 6)
+    fused = T.Plan(c, tree, "c64", {"sample_block_log": 8})
+    assert [ln for ln in fused.describe().split("\n") if ln.startswith("sampling")][0].split()[1] == "1"
+    sep = T.Plan(c, tree, "c64", {"sample_block_log": 8, "separate_sampling": 1})
+    a, b = T.run(fused, nz), T.run(sep, nz)
+    onz = oracle.Noise(*[np.asarray(x) for x in arr]) if arr is not None else oracle.sample_noise(wc.gates, tree, 6)
+    oout, ost = oracle.run_leaves(wc.n, wc.gates, tree, onz, states=True)
+    check_outcomes(a, oout, ost, onz.leaf_u, DELTA["c64"])
+    check_outcomes(b, oout, ost, onz.leaf_u, DELTA["c64"])
+    assert np.sum(a != b) <= 2

@@ -335,3 +335,74 @@ def test_readout_flips_match_oracle():
     assert np.array_equal(nz3.flips(), o.leaf_flip)
     with pytest.raises(T.TqsError):
         c.set_readout([0.1, 0.2, 0.3, 0.4, 0.5, 1.5])
+
+
+def _tiled_block_masses(text, psi_phys, b):
+    """Block masses from per-tile partials built as the described plan says
+    the last leaf pass writes them (lane positions, then registers), summed
+    over tiles that differ in in-block positions only."""
+    lines = text.strip().split("\n")
+    n = int(lines[0].split()[1])
+    lay = [int(v) for v in lines[1].split()[1:]]
+    regs = [int(v) for v in [ln for ln in lines if ln.startswith("pass ")][-1].split()[4:]]
+    head, _, rest = [ln for ln in lines if ln.startswith("sampling")][0].partition("|")
+    tiled, kv, nfree, tfree, psum = map(int, head.split()[1:])
+    bsrc = [int(v) for v in rest.split()]
+    assert tiled == 1
+    fold_l, fold_r = psum & 0xFF, (psum >> 8) & 0xFF
+    fixed = [q for q in range(n) if q >= 6 and q not in regs]
+    assert len(fixed) == nfree
+    part = np.zeros((1 << nfree) << kv)
+    p = np.abs(psi_phys) ** 2
+    for x in range(1 << n):
+        lane = x & 63
+        tile = sum(((x >> P) & 1) << t for t, P in enumerate(fixed))
+        pat, k = 0, 0
+        for bb in range(6):
+            if not (fold_l >> bb) & 1:
+                pat |= ((lane >> bb) & 1) << k
+                k += 1
+        for i, P in enumerate(regs):
+            if not (fold_r >> i) & 1:
+                pat |= ((x >> P) & 1) << k
+                k += 1
+        part[(tile << kv) | pat] += p[x]
+    nb = 1 << (n - b)
+    S = np.zeros(nb)
+    for B in range(nb):
+        jv, tfix = 0, 0
+        for i, src in enumerate(bsrc):
+            bit = (B >> i) & 1
+            if src & 0x80:
+                jv |= bit << (src & 0x7F)
+            else:
+                tfix |= bit << src
+        sub = 0
+        while True:
+            S[B] += part[((tfix | sub) << kv) | jv]
+            sub = (sub - tfree) & tfree
+            if sub == 0:
+                break
+    return S
+
+
+@pytest.mark.parametrize("n,count,seed", [(13, 40, 1), (14, 60, 2), (12, 30, 3)])
+def test_tiled_sampling_partials_give_block_masses(n, count, seed):
+    # the plan's map from per-tile partials to logical blocks reproduces the
+    # block masses of the logical-order state (random state, layouts moved
+    # by swap gates and lane exchanges)
+    rng = np.random.default_rng(seed)
+    wc = _random_gates(n, count, rng)
+    for i in range(n // 2):
+        wc.add((i, n - 1 - i), W.swap())
+    c = T.Circuit.from_workload(wc)
+    G = len(wc)
+    text = T.Plan(c, ([2, 2], [0, G // 2, G]), "c64", {"sample_block_log": 8}).describe()
+    lay = [int(v) for v in text.split("\n")[1].split()[1:]]
+    psi = rng.normal(size=1 << n) + 1j * rng.normal(size=1 << n)
+    psi_phys = np.zeros_like(psi)
+    for y in range(1 << n):
+        psi_phys[sum(((y >> q) & 1) << lay[q] for q in range(n))] = psi[y]
+    S = _tiled_block_masses(text, psi_phys, 8)
+    want = (np.abs(psi) ** 2).reshape(-1, 1 << 8).sum(1)
+    assert np.allclose(S, want, rtol=1e-12, atol=0)
