@@ -110,7 +110,8 @@ typedef struct {
     uint64_t launches;         /* kernels launched */
     uint64_t pass_launches;    /* of which gate-apply passes */
     uint64_t pass_states;      /* sum over pass launches of states processed */
-    uint64_t bytes_passes;     /* algorithmic HBM bytes of the passes (read + write) */
+    uint64_t bytes_passes;     /* algorithmic HBM bytes of the passes (read + write, with the
+                                  sampling partials the last leaf pass writes) */
     uint64_t bytes_sample;     /* algorithmic HBM bytes of sampling */
     uint64_t events;           /* noise events in the insertion list */
     uint64_t nodes_merged;     /* nodes whose state is an identical earlier node's */

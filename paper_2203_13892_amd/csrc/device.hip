@@ -265,13 +265,21 @@ __global__ __launch_bounds__(kThreads) void block_gather_kernel(SampleLaunch<R> 
             B |= bit << i;
         }
         const double *pk = part + ((uint64_t)k << (m.nfree + m.kv));
-        double acc = 0.0;
+        // four loads in flight per thread: subsets of tfree in increasing
+        // order, dealt round-robin to four accumulators
+        const uint32_t cnt = 1u << __popc(m.tfree);
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
         uint32_t sub = 0;
-        do {
-            acc += pk[((uint64_t)(tfix | sub) << m.kv) | jv];
-            sub = (sub - m.tfree) & m.tfree;  // next subset of tfree, increasing
-        } while (sub != 0);
-        sums[(uint64_t)k * nblocks + B] = acc;
+        for (uint32_t i = 0; i < cnt; i += 4) {
+            const uint32_t s1 = (sub - m.tfree) & m.tfree, s2 = (s1 - m.tfree) & m.tfree;
+            const uint32_t s3 = (s2 - m.tfree) & m.tfree;
+            a0 += pk[((uint64_t)(tfix | sub) << m.kv) | jv];
+            if (i + 1 < cnt) a1 += pk[((uint64_t)(tfix | s1) << m.kv) | jv];
+            if (i + 2 < cnt) a2 += pk[((uint64_t)(tfix | s2) << m.kv) | jv];
+            if (i + 3 < cnt) a3 += pk[((uint64_t)(tfix | s3) << m.kv) | jv];
+            sub = (s3 - m.tfree) & m.tfree;
+        }
+        sums[(uint64_t)k * nblocks + B] = (a0 + a1) + (a2 + a3);
         return;
     }
     const uint32_t k = (uint32_t)(gid / nblocks), B = (uint32_t)(gid % nblocks);
@@ -1030,6 +1038,8 @@ static tqs_status run_t(tqs_plan *p, const tqs_noise *nz, unsigned char *ws, uin
             pass_states += t.ccount;
             const bool init = (k == 0 && t.level == 0);
             bytes_passes += (uint64_t)t.ccount * state_bytes * (init ? 1 : 2);
+            if (p->samp_tiled && t.level == L - 1 && k + 1 == lv.pass_count)
+                bytes_passes += (uint64_t)t.ccount * (8ull << (p->samp_nfree + p->samp_kv));
         }
         if (stats) {
             HIP_TRY(hipEventRecord(eb, s), "hipEventRecord");
@@ -1038,7 +1048,10 @@ static tqs_status run_t(tqs_plan *p, const tqs_noise *nz, unsigned char *ws, uin
         if (t.level == L - 1) {
             launch_sample<R>(p, Ly, ws, s, t, leaf_first);
             launches += 3;
-            bytes_sample += (uint64_t)t.ccount * state_bytes + (uint64_t)t.count * (Ly.amp_bytes << b);
+            // partial masses (the states themselves when the pass wrote none),
+            // then one block of each leaf
+            bytes_sample += (uint64_t)t.ccount * (p->samp_tiled ? (8ull << (p->samp_nfree + p->samp_kv)) : state_bytes) +
+                            (uint64_t)t.count * (Ly.amp_bytes << b);
             if (stats) {
                 ec = pool_event(p, ev_i++);
                 if (!ec) return fail(TQS_E_HIP, "hipEventCreate failed");
