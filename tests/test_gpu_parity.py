@@ -638,3 +638,51 @@ def test_partials_from_last_pass_equal_separate_sampling(T, case):
     check_outcomes(a, oout, ost, onz.leaf_u, DELTA["c64"])
     check_outcomes(b, oout, ost, onz.leaf_u, DELTA["c64"])
     assert np.sum(a != b) <= 2
+
+
+def test_largest_sizes(T):
+    # 30 qubits at complex64 (8 GiB states) and 29 at complex128: GHZ
+    # outcomes are all-zeros or all-ones before the read-out flips; a
+    # 28-qubit QFT round trip returns its input on every shot
+    for n, prec in ((30, "c64"), (29, "c128")):
+        wc = W.ghz(n).with_readout(0.25)
+        G = len(wc)
+        tree = ([2, 2], [0, G // 2, G])
+        c = T.Circuit.from_workload(wc)
+        nz = T.Noise.sample(c, tree, 1)
+        out = T.run(T.Plan(c, tree, prec), nz)
+        flips = nz.flips().astype(np.uint64)
+        base = out ^ flips
+        assert np.all((base == 0) | (base == (1 << n) - 1)), (n, base)
+        del nz, c
+    n, x = 28, 0xA5C3E1F & ((1 << 28) - 1)
+    wc = W.concat(W.basis_prep(n, x), W.qft(n), W.inverse(W.qft(n)))
+    G = len(wc)
+    tree = ([3], [0, G])
+    c = T.Circuit.from_workload(wc)
+    out = T.run(T.Plan(c, tree, "c64"), T.Noise.sample(c, tree, 0))
+    assert np.all(out == x), out
+
+
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+def test_degenerate_trees(T, prec):
+    # arity-1 levels, a level of swap gates only (a pass with no ops), a
+    # one-gate level, and a list without events: outcomes and amplitudes
+    # match the oracle
+    rng = np.random.default_rng(61)
+    wc = mixed_gates(12, 20, rng)
+    wc.add((0, 7), W.swap())
+    wc.add((3, 11), W.swap())
+    wc.add((5,), W.haar_unitary(2, rng))
+    G = len(wc)
+    for tree in (([1, 1, 3], [0, 10, 20, G]), ([2, 3, 2], [0, 20, 22, G]), ([1], [0, G])):
+        arr = event_arrays(wc, tree, rng, rate=0.3)
+        leaves = np.arange(int(np.prod(tree[0])))
+        out, amps, oout, ost, _ = run_both(T, wc, tree, 0, prec, leaves, noise_arrays=arr)
+        assert np.max(np.abs(amps - ost)) < TOL[prec]
+        check_outcomes(out, oout, ost, arr[3], DELTA[prec])
+    tree = ([4, 4], [0, 10, G])
+    none = (np.zeros(1 + 4 + 16, np.uint64), np.zeros(0, np.uint32), np.zeros(0, np.uint8), rng.random(16))
+    out, amps, oout, ost, _ = run_both(T, wc, tree, 0, prec, np.arange(16), noise_arrays=none)
+    assert np.max(np.abs(amps - ost)) < TOL[prec]
+    check_outcomes(out, oout, ost, none[3], DELTA[prec])
