@@ -649,7 +649,19 @@ __device__ __forceinline__ void op_diag_run(cplx<R> (&v)[1 << RB], const OpDesc 
         }
     });
     const uint32_t lm = o.lam_mask;
-    if (__builtin_popcount(lm) <= 2) {
+    if (__builtin_popcount(lm) == 1) {
+        // one register-dependent factor: e^{2 pi i C} on the registers with
+        // the bit clear, e^{2 pi i (C + lam_i)} on the others
+        with_reg<RB>((uint32_t)__builtin_ctz(lm), [&](auto Ic) __attribute__((always_inline)) {
+            constexpr int I = decltype(Ic)::value;
+            const cplx<R> w0 = expi_turns(C);
+            const cplx<R> w1 = cmul(w0, expi_turns(lam[I]));
+            sfor<NJ>([&](auto Jc) __attribute__((always_inline)) {
+                constexpr int j = decltype(Jc)::value;
+                v[j] = cmul(((j >> I) & 1) ? w1 : w0, v[j]);
+            });
+        });
+    } else if (__builtin_popcount(lm) <= 2) {
         // few register-dependent factors: e^{2 pi i C}, then e^{2 pi i lam_i}
         // on the registers with bit i set
         const cplx<R> w0 = expi_turns(C);
@@ -699,7 +711,8 @@ __device__ __forceinline__ void op_diag_run(cplx<R> (&v)[1 << RB], const OpDesc 
         const uint32_t msk = (1u << nr) - 1u;
         sfor<NJ>([&](auto Jc) __attribute__((always_inline)) {
             constexpr int j = decltype(Jc)::value;
-            v[j] = cmul(T[((uint32_t)j ^ fr) & msk], v[j]);
+            const uint32_t t = ((uint32_t)j ^ fr) & msk;
+            if (t >= 32u || ((o.tmask >> t) & 1u)) v[j] = cmul(T[t], v[j]);
         });
     }
 }

@@ -337,7 +337,9 @@ extern "C" tqs_status tqs_plan_create(const tqs_circuit *c, const tqs_tree *tree
                     o.n_lanereg[b] = (uint16_t)g_lanereg[b].size();
                     for (const DiagTerm &tm : g_lanereg[b]) p->terms.push_back(tm);
                 }
-                o.nterms = (uint32_t)(p->terms.size() - o.terms);
+                o.tmask = 0;  // (entries from 32 on are always applied)
+                for (uint32_t t = 0; t < std::min(nt, 32u); t++)
+                    if (tab[t] != cd(1.0, 0.0)) o.tmask |= 1u << t;
                 o.ngates = (uint32_t)(j - i);
                 for (uint32_t t = 0; t < nt; t++) p->mats.push_back(tab[t]);
                 // per-gate diagonal entries for the gate-by-gate path

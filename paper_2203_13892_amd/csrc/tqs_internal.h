@@ -81,7 +81,7 @@ struct OpDesc {
     uint16_t slot0, slot1;  // gate slots [slot0, slot1) of the pass covered by the op
     uint32_t mat;      // DENSE1/DENSE2: matrix offset; DIAGRUN: table offset (2^nr entries)
     uint32_t terms;    // DIAGRUN: first term touching a non-register qubit
-    uint32_t nterms;
+    uint32_t tmask;    // DIAGRUN: register-table entries that are not exactly 1
     uint32_t gates;    // DIAGRUN: first per-gate record (slow path)
     uint32_t ngates;
     // DIAGRUN term groups, stored in this order: fixed-only terms, then
