@@ -26,9 +26,10 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "pass_kernel_qft20_tree16x32x32_traffic.json")
 
 
-def measured_traffic():
-    """HBM bytes per pass launch from the committed rocprofv3 FETCH/WRITE
-    counts, or None when the kernel or planner sources changed since."""
+def profiled_record():
+    """The committed rocprofv3 figures of the pass kernel (FETCH/WRITE bytes
+    per launch, VALU instructions of the full leaf launches), or None when
+    the kernel, planner or executor sources changed since."""
     import hashlib
     try:
         rec = json.load(open(TRAFFIC_JSON))
@@ -37,9 +38,29 @@ def measured_traffic():
             h.update(open(os.path.join(ROOT, s), "rb").read())
         if h.hexdigest() != rec["sources_sha256"]:
             return None
-        return rec["hbm_read_bytes_per_launch"] + rec["hbm_write_bytes_per_launch"]
+        return rec
     except (OSError, KeyError, ValueError):
         return None
+
+
+def measured_traffic():
+    """HBM bytes per pass launch from the committed counters, or None."""
+    rec = profiled_record()
+    if rec is None:
+        return None
+    return rec["hbm_read_bytes_per_launch"] + rec["hbm_write_bytes_per_launch"]
+
+
+def valu_issue_frac():
+    """Share of the VALU issue limit used by a full leaf pass launch: its
+    VALU instructions x 4 cycles (a wave64 FP32 instruction per SIMD) over
+    1024 SIMDs at 2.4 GHz, against its measured duration; None without a
+    current profile."""
+    rec = profiled_record()
+    if rec is None or "leaf_valu_per_wave" not in rec:
+        return None
+    cycles = rec["leaf_waves"] * rec["leaf_valu_per_wave"] * 4.0 / 1024
+    return cycles / 2.4e9 / (rec["leaf_launch_us"] * 1e-6)
 
 
 def equal_cuts(G, levels):
@@ -404,8 +425,12 @@ def main():
         copy_cost = copy_us / gate_us
         dcp_shape = T.dcp(circuit, shots, 1.96, 0.01, copy_cost, 8)
         forms["dcp"] = dcp_shape
-        if "dcp" not in args.forms.split(","):
-            args.forms += ",dcp"
+        # the branch copy rides on the children's first pass here, so its
+        # marginal cost is about one gate: DCP with that copy cost
+        forms["dcp_fused"] = T.dcp(circuit, shots, 1.96, 0.01, 1.0, 8)
+        for f in ("dcp", "dcp_fused"):
+            if f not in args.forms.split(","):
+                args.forms += "," + f
     results = {}
     for name in args.forms.split(","):
         tree = forms[name]
@@ -449,6 +474,7 @@ def main():
                    "tree": h["shape"], "cut": h["cut"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
+                     "valu_issue_frac": valu_issue_frac(),
                      "kernel": "pass_kernel<float>",
                      "algorithmic_bytes_per_launch": h["bytes_per_launch"],
                      "us_per_launch": h["us_per_launch"], "launches": h["pass_launches"]},
