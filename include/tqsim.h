@@ -44,6 +44,12 @@
  * workspace (for example a torch uint8 tensor) of at least the size that
  * tqs_workspace_bytes reports, and a HIP stream (NULL = the null stream).
  *
+ * Threads: calls on different objects may run concurrently.  Runs that use
+ * the same plan or batch must not overlap (a run keeps its timing events in
+ * the plan or batch), and runs that share a workspace must be ordered on
+ * the device (same stream, or synchronised) since each run owns the whole
+ * workspace until it returns.
+ *
  * Errors: every call returns a tqs_status; a negative value means failure,
  * and tqs_last_error() gives a message for the calling thread.  No call
  * aborts or throws across this boundary.
