@@ -406,3 +406,21 @@ def test_tiled_sampling_partials_give_block_masses(n, count, seed):
     S = _tiled_block_masses(text, psi_phys, 8)
     want = (np.abs(psi) ** 2).reshape(-1, 1 << 8).sum(1)
     assert np.allclose(S, want, rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_workspace_bound_holds_for_any_list(seed):
+    # the list-free workspace size bounds the exact size of any list, with
+    # shared states on or off and either sampling form
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(8, 15))
+    wc = _random_gates(n, int(rng.integers(20, 60)), rng)
+    G = len(wc)
+    A = [int(a) for a in rng.integers(1, 6, 3)]
+    tree = (A, [0, G // 3, 2 * G // 3, G])
+    c = T.Circuit.from_workload(wc.with_depolarizing(0.2, 0.3))
+    for tun in ({}, {"no_merge": 1}, {"separate_sampling": 1}, {"chunk_states": 2}):
+        p = T.Plan(c, tree, "c64", tun)
+        bound = p.workspace_bytes(None)
+        for s in range(3):
+            assert p.workspace_bytes(T.Noise.sample(c, tree, s)) <= bound
