@@ -320,6 +320,26 @@ def batch_bench(T, W, torch, seed, shots=2048, budget_gib=32):
     return rec
 
 
+def parity_sample(T, wc, tree, seed, count=16):
+    """The headline run against the oracle on `count` leaves spread over the
+    tree: max-abs amplitude error (complex64 against complex128) and how many
+    outcomes agree (a disagreement is counted at a CDF boundary only)."""
+    import numpy as np
+    import oracle
+    c = T.Circuit.from_workload(wc)
+    plan = T.Plan(c, tree, "c64")
+    nz = T.Noise.sample(c, tree, seed)
+    leaves = np.linspace(0, plan.n_leaves - 1, count).astype(np.uint64)
+    out, amps = T.run_capture(plan, nz, leaves)
+    onz = oracle.sample_noise(wc.gates, tree, seed)
+    threads = max(1, min(len(os.sched_getaffinity(0)), int(os.environ.get("OMP_NUM_THREADS", "16"))))
+    oout, ost = oracle.run_leaves(wc.n, wc.gates, tree, onz, leaves, states=True, threads=threads)
+    err = float(np.max(np.abs(amps - ost)))
+    same = int(np.sum(out[leaves.astype(np.int64)] == oout))
+    return {"leaves": count, "max_abs_amplitude_error": err, "tolerance": 1e-5,
+            "outcomes_equal": "%d of %d" % (same, count)}
+
+
 def cpu_baseline(wc, seed, budget_s=15.0):
     """The oracle (per-shot, complex128, threads over shots) on a bounded
     sample of the same workload's shots."""
@@ -524,7 +544,9 @@ def main():
                                             seed=args.seed,
                                             log=lambda m: print("# learned " + m, file=sys.stderr, flush=True))
     if not args.no_cpu:
+        # the oracle leg: its timing, and the headline run checked against it
         line["cpu_baseline"] = cpu_baseline(wc, args.seed, args.cpu_budget)
+        line["cpu_baseline"]["gpu_parity"] = parity_sample(T, wc, forms[head], args.seed)
     print(json.dumps(line), flush=True)
 
 
