@@ -242,46 +242,77 @@ __global__ __launch_bounds__(kThreads) void block_gather_kernel(SampleLaunch<R> 
     const SampleArgs<R> sa = sample_seg(sl, 1, blockIdx.x, &local);
     const SampleMap &m = sa.m;
     const uint32_t nblocks = 1u << (m.n - m.b);
-    const uint64_t gid = (uint64_t)local * kThreads + threadIdx.x;
-    if (gid >= (uint64_t)sa.reps * nblocks) return;
     const double *part = sa.part;
     double *sums = sa.sums;
     if (m.tiled) {
-        // partials per tile: thread = (state, fixed block bits, pattern), so
-        // neighbouring threads read neighbouring patterns; the sum runs over
-        // the tiles that differ in in-block positions only, in increasing order
-        const uint32_t k = (uint32_t)(gid / nblocks), r = (uint32_t)(gid % nblocks);
-        const uint32_t jv = r & ((1u << m.kv) - 1u), tc = r >> m.kv;
-        uint32_t B = 0, tfix = 0;
-        for (uint32_t i = 0, nf = 0; i < m.n - m.b; i++) {
-            const uint32_t src = m.bsrc[i];
-            uint32_t bit;
-            if (src & 0x80u) {
-                bit = (jv >> (src & 0x7Fu)) & 1u;
-            } else {
-                bit = (tc >> nf++) & 1u;
-                tfix |= bit << src;
+        // partials per tile.  A workgroup takes RW consecutive (state, fixed
+        // block bits, pattern) items, so neighbouring threads read
+        // neighbouring patterns, and splits each item's tiles (those that
+        // differ in in-block positions only) into 2^ls interleaved shares;
+        // every share sums its tiles in increasing order, then the shares
+        // are added in order (a fixed order: the result is deterministic)
+        __shared__ double red[kThreads];
+        const uint32_t nb = __popc(m.tfree);
+        const uint32_t ls = nb < 3u ? nb : 3u;
+        const uint32_t RW = kThreads >> ls;
+        const uint32_t sidx = threadIdx.x / RW, ri = threadIdx.x % RW;
+        const uint64_t gid = (uint64_t)local * RW + ri;
+        const bool live = gid < (uint64_t)sa.reps * nblocks;
+        // the share's fixed low part: sidx deposited into the lowest ls bits of tfree
+        uint32_t mlo = 0, low = 0;
+        for (uint32_t bits = m.tfree, i = 0; i < ls; i++) {
+            const uint32_t bt = bits & (0u - bits);
+            mlo |= bt;
+            if ((sidx >> i) & 1u) low |= bt;
+            bits ^= bt;
+        }
+        const uint32_t mhi = m.tfree ^ mlo;
+        double acc = 0.0;
+        uint32_t k = 0, B = 0;
+        if (live) {
+            k = (uint32_t)(gid / nblocks);
+            const uint32_t r = (uint32_t)(gid % nblocks);
+            const uint32_t jv = r & ((1u << m.kv) - 1u), tc = r >> m.kv;
+            uint32_t tfix = 0;
+            for (uint32_t i = 0, nf = 0; i < m.n - m.b; i++) {
+                const uint32_t src = m.bsrc[i];
+                uint32_t bit;
+                if (src & 0x80u) {
+                    bit = (jv >> (src & 0x7Fu)) & 1u;
+                } else {
+                    bit = (tc >> nf++) & 1u;
+                    tfix |= bit << src;
+                }
+                B |= bit << i;
             }
-            B |= bit << i;
+            const double *pk = part + ((uint64_t)k << (m.nfree + m.kv)) + jv;
+            const uint32_t base = tfix | low;
+            const uint32_t cnt = 1u << (nb - ls);
+            // four loads in flight: subsets of mhi in increasing order, dealt
+            // round-robin to four accumulators
+            double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+            uint32_t h = 0;
+            for (uint32_t i = 0; i < cnt; i += 4) {
+                const uint32_t h1 = (h - mhi) & mhi, h2 = (h1 - mhi) & mhi, h3 = (h2 - mhi) & mhi;
+                a0 += pk[(uint64_t)(base | h) << m.kv];
+                if (i + 1 < cnt) a1 += pk[(uint64_t)(base | h1) << m.kv];
+                if (i + 2 < cnt) a2 += pk[(uint64_t)(base | h2) << m.kv];
+                if (i + 3 < cnt) a3 += pk[(uint64_t)(base | h3) << m.kv];
+                h = (h3 - mhi) & mhi;
+            }
+            acc = (a0 + a1) + (a2 + a3);
         }
-        const double *pk = part + ((uint64_t)k << (m.nfree + m.kv));
-        // four loads in flight per thread: subsets of tfree in increasing
-        // order, dealt round-robin to four accumulators
-        const uint32_t cnt = 1u << __popc(m.tfree);
-        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-        uint32_t sub = 0;
-        for (uint32_t i = 0; i < cnt; i += 4) {
-            const uint32_t s1 = (sub - m.tfree) & m.tfree, s2 = (s1 - m.tfree) & m.tfree;
-            const uint32_t s3 = (s2 - m.tfree) & m.tfree;
-            a0 += pk[((uint64_t)(tfix | sub) << m.kv) | jv];
-            if (i + 1 < cnt) a1 += pk[((uint64_t)(tfix | s1) << m.kv) | jv];
-            if (i + 2 < cnt) a2 += pk[((uint64_t)(tfix | s2) << m.kv) | jv];
-            if (i + 3 < cnt) a3 += pk[((uint64_t)(tfix | s3) << m.kv) | jv];
-            sub = (s3 - m.tfree) & m.tfree;
+        red[threadIdx.x] = acc;
+        __syncthreads();
+        if (live && sidx == 0) {
+            double t = 0.0;
+            for (uint32_t q = 0; q < (1u << ls); q++) t += red[q * RW + ri];
+            sums[(uint64_t)k * nblocks + B] = t;
         }
-        sums[(uint64_t)k * nblocks + B] = (a0 + a1) + (a2 + a3);
         return;
     }
+    const uint64_t gid = (uint64_t)local * kThreads + threadIdx.x;
+    if (gid >= (uint64_t)sa.reps * nblocks) return;
     const uint32_t k = (uint32_t)(gid / nblocks), B = (uint32_t)(gid % nblocks);
     uint32_t pb = 0;
     for (uint32_t q = m.b; q < m.n; q++) pb |= ((B >> (q - m.b)) & 1u) << m.lay[q];
@@ -894,7 +925,13 @@ static SampleArgs<R> sample_args(const tqs_plan *p, const Layout &Ly, unsigned c
 template <typename R>
 static void sample_grid(const SampleArgs<R> &a, uint32_t g[3]) {
     g[0] = a.m.tiled ? 0u : a.reps << (a.m.n - a.m.c);
-    g[1] = (uint32_t)((((uint64_t)a.reps << (a.m.n - a.m.b)) + kThreads - 1) / kThreads);
+    {
+        // tiled partials: each workgroup takes kThreads >> ls items (ls =
+        // log2 of the shares per item), else one item per thread
+        const uint32_t nb = (uint32_t)__builtin_popcount(a.m.tfree);
+        const uint32_t per = a.m.tiled ? (kThreads >> (nb < 3u ? nb : 3u)) : kThreads;
+        g[1] = (uint32_t)((((uint64_t)a.reps << (a.m.n - a.m.b)) + per - 1) / per);
+    }
     g[2] = a.count;
 }
 
