@@ -433,10 +433,28 @@ __global__ __launch_bounds__(kThreads) void sample_kernel(SampleLaunch<R> sl) {
     const uint32_t nb = 1u << b;
     const uint32_t iseg = (nb + kThreads - 1) / kThreads;
     const uint32_t y0 = tid * iseg, y1 = min(nb, y0 + iseg);
+    // (blocks of up to 16 values per thread are read once and kept)
+    constexpr uint32_t kKeep = 16;
+    const bool keep = iseg <= kKeep;
+    double pv[kKeep];
     s = 0.0;
-    for (uint32_t y = y0; y < y1; y++) {
-        const cplx<R> v = blk[plow(y ^ xlow)];
-        s += (double)v.re * (double)v.re + (double)v.im * (double)v.im;
+    if (keep) {
+#pragma unroll
+        for (uint32_t i = 0; i < kKeep; i++) {
+            const uint32_t y = y0 + i;
+            double a2 = 0.0;
+            if (y < y1) {
+                const cplx<R> v = blk[plow(y ^ xlow)];
+                a2 = (double)v.re * (double)v.re + (double)v.im * (double)v.im;
+            }
+            pv[i] = a2;
+            s += a2;
+        }
+    } else {
+        for (uint32_t y = y0; y < y1; y++) {
+            const cplx<R> v = blk[plow(y ^ xlow)];
+            s += (double)v.re * (double)v.re + (double)v.im * (double)v.im;
+        }
     }
     part[tid] = s;
     __syncthreads();
@@ -450,12 +468,24 @@ __global__ __launch_bounds__(kThreads) void sample_kernel(SampleLaunch<R> sl) {
     __syncthreads();
     {
         double run = pre[tid];
-        for (uint32_t y = y0; y < y1; y++) {
-            const cplx<R> v = blk[plow(y ^ xlow)];
-            run += (double)v.re * (double)v.re + (double)v.im * (double)v.im;
-            if (run > t) {
-                atomicMin(&hit, y);
-                break;
+        if (keep) {
+            bool found = false;
+#pragma unroll
+            for (uint32_t i = 0; i < kKeep; i++) {
+                run += pv[i];
+                if (!found && y0 + i < y1 && run > t) {
+                    atomicMin(&hit, y0 + i);
+                    found = true;
+                }
+            }
+        } else {
+            for (uint32_t y = y0; y < y1; y++) {
+                const cplx<R> v = blk[plow(y ^ xlow)];
+                run += (double)v.re * (double)v.re + (double)v.im * (double)v.im;
+                if (run > t) {
+                    atomicMin(&hit, y);
+                    break;
+                }
             }
         }
     }
