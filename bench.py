@@ -142,9 +142,11 @@ def precision_sweep(T, W, torch, seed):
     Pauli-twirled amplitude damping with gamma = p2 on each gate's qubits,
     8192 shots in the tree (8, 4, 4, 4, 4, 4): complex64 evolution (FP64 CDF)
     over all leaves against complex128 over level-0 subtree 0 (1024 leaves).
-    Reports rates and how many of the common leaves draw the same outcome.
-    (The amplitude error of either precision against the FP64 oracle is a
-    GPU parity test on the same circuit family.)"""
+    Reports rates, how many of the common leaves draw the same outcome, and
+    the complex64 amplitude error against complex128 on two captured
+    trajectories
+    (the complex128 path itself is checked against the FP64 oracle by a GPU
+    parity test on the same circuit family at 22 qubits)."""
     import numpy as np
     n, depth, shape = 26, 24, [8, 4, 4, 4, 4, 4]
     out = []
@@ -168,6 +170,17 @@ def precision_sweep(T, W, torch, seed):
             rec[prec] = {"leaves": int(o.size), "shots_per_s": o.size / dt, "s": dt,
                          "pass_GBps": st["bytes_passes"] / (st["ms_passes"] * 1e-3) / 1e9}
             del ws
+        # complex64 against complex128 amplitudes of two trajectories of the
+        # same circuit and noise model
+        cap = {}
+        tree_c = ([2], [0, G])
+        nz_c = T.Noise.sample(c, tree_c, seed)
+        for prec in ("c64", "c128"):
+            _, amps = T.run_capture(T.Plan(c, tree_c, prec), nz_c, [0, 1])
+            cap[prec] = amps
+        rec["c64_max_abs_error_vs_c128"] = float(np.max(np.abs(cap["c64"] - cap["c128"])))
+        rec["max_abs_amplitude"] = float(np.max(np.abs(cap["c128"])))
+        del cap
         same = outs["c64"][:per] == outs["c128"]
         rec["outcomes_equal_c64_c128"] = "%d of %d" % (int(same.sum()), per)
         # a rounding-level difference moves the inverse-CDF pick across a
@@ -175,9 +188,10 @@ def precision_sweep(T, W, torch, seed):
         gap = np.abs(outs["c64"][:per].astype(np.int64) - outs["c128"].astype(np.int64))
         rec["largest_outcome_index_gap"] = int(gap.max())
         out.append(rec)
-        print("# precision p2=%g: c64 %.1f shots/s, c128 %.1f shots/s, equal outcomes %s, largest index gap %d" %
+        print("# precision p2=%g: c64 %.1f shots/s, c128 %.1f shots/s, equal outcomes %s, largest index gap %d, "
+              "c64 amplitude error %.2e" %
               (p2, rec["c64"]["shots_per_s"], rec["c128"]["shots_per_s"], rec["outcomes_equal_c64_c128"],
-               rec["largest_outcome_index_gap"]), file=sys.stderr, flush=True)
+               rec["largest_outcome_index_gap"], rec["c64_max_abs_error_vs_c128"]), file=sys.stderr, flush=True)
     return out
 
 
