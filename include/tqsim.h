@@ -289,8 +289,9 @@ tqs_status tqs_batch_run(tqs_batch *b, void *d_workspace, uint64_t ws_bytes, voi
  * replay, the batch's kernel launches are recorded once into a HIP graph on
  * a private stream (for the workspace address of that run; a run with
  * another workspace records again) and each run launches the graph on its
- * stream after the usual metadata upload, which cuts the host cost of the
- * many small launches of small circuits.  Outcomes are the same either way. */
+ * stream after the usual metadata upload.  This removes the host's cost of
+ * issuing the launches, which matters only when it is comparable to the
+ * kernels' own time.  Outcomes are the same either way. */
 tqs_status tqs_batch_use_graph(tqs_batch *b, uint32_t on);
 
 void tqs_batch_destroy(tqs_batch *b);
