@@ -138,9 +138,12 @@ struct SampleLaunch {
     uint32_t nseg;  // 0: `one` is the launch
 };
 
+// The segment of workgroup `wg`, by reference into the launch argument or
+// the segment table: its arrays (block map, layout) are then read in place
+// (a local copy indexed by a loop variable would live in scratch memory).
 template <typename R>
-__device__ __forceinline__ SampleArgs<R> sample_seg(const SampleLaunch<R> &sl, int stage, uint32_t wg,
-                                                    uint32_t *local) {
+__device__ __forceinline__ const SampleArgs<R> &sample_seg(const SampleLaunch<R> &sl, int stage, uint32_t wg,
+                                                           uint32_t *local) {
     if (sl.nseg == 0) {
         *local = wg;
         return sl.one;
@@ -152,9 +155,8 @@ __device__ __forceinline__ SampleArgs<R> sample_seg(const SampleLaunch<R> &sl, i
         if (segs[mid].wg_begin[stage] <= wg) lo = mid;
         else hi = mid;
     }
-    const SampleArgs<R> a = segs[lo];
-    *local = wg - a.wg_begin[stage];
-    return a;
+    *local = wg - segs[lo].wg_begin[stage];
+    return segs[lo];
 }
 
 // Partial masses: one workgroup per (state, chunk).  Thread t reads the
@@ -168,7 +170,7 @@ __global__ __launch_bounds__(kThreads) void block_partials_kernel(SampleLaunch<R
     constexpr uint32_t kQ = 16;  // values per thread (chunk of at most 4096)
     __shared__ double buf[kThreads * kQ];
     uint32_t local;
-    const SampleArgs<R> sa = sample_seg(sl, 0, blockIdx.x, &local);
+    const SampleArgs<R> &sa = sample_seg(sl, 0, blockIdx.x, &local);
     const SampleMap &m = sa.m;
     const uint32_t nch = 1u << (m.n - m.c);
     if (local >= sa.reps * nch) return;
@@ -239,7 +241,7 @@ __global__ __launch_bounds__(kThreads) void block_partials_kernel(SampleLaunch<R
 template <typename R>
 __global__ __launch_bounds__(kThreads) void block_gather_kernel(SampleLaunch<R> sl) {
     uint32_t local;
-    const SampleArgs<R> sa = sample_seg(sl, 1, blockIdx.x, &local);
+    const SampleArgs<R> &sa = sample_seg(sl, 1, blockIdx.x, &local);
     const SampleMap &m = sa.m;
     const uint32_t nblocks = 1u << (m.n - m.b);
     const double *part = sa.part;
@@ -347,7 +349,7 @@ __global__ __launch_bounds__(kThreads) void sample_kernel(SampleLaunch<R> sl) {
     __shared__ uint32_t hit;
     __shared__ double tsh, cum_sh;
     uint32_t k;
-    const SampleArgs<R> sa = sample_seg(sl, 2, blockIdx.x, &k);
+    const SampleArgs<R> &sa = sample_seg(sl, 2, blockIdx.x, &k);
     if (k >= sa.count) return;
     const SampleMap &m = sa.m;
     const uint32_t tid = threadIdx.x;
