@@ -256,7 +256,7 @@ def held_out_circuits(n=24):
 
 
 def evaluate(T, torch, model, circuits, shots=16384, copy_cost=26.0, max_deff=4.0, seed=0, log=print):
-    """Per-shot (the judge), the DCP shape and the learned shape on each
+    """Per-shot (the exact reference), the DCP shape and the learned shape on each
     circuit: measured time, and the normalised linear fidelity
     F = (mean p_ideal(x) - 2^-n) / (sum p_ideal^2 - 2^-n) (1 for the ideal
     output, 0 for the uniform one; for a single ideal outcome it is the
