@@ -246,13 +246,15 @@ def choose_shape(T, model, wc, shots, copy_cost=26.0, max_deff=4.0, max_levels=4
 def held_out_circuits(n=24):
     """Circuits of a size the model never saw: a depth-24 brick-wall, QAOA
     p = 2 on a random 3-regular graph, and the QFT round trip from a basis
-    state, with depolarizing p1 = 1e-3, p2 = 1e-2."""
+    state at n qubits, and QAOA p = 2 at n + 2 qubits, with depolarizing
+    p1 = 1e-3, p2 = 1e-2."""
     from . import workloads as W
     x = 0xA5A5A5 & ((1 << n) - 1)
     return [("brickwall%d" % n, W.brickwall(n, 24, seed=7).with_noise(1e-3, 1e-2)),
             ("qaoa%d" % n, W.qaoa(n, 2, seed=7).with_noise(1e-3, 1e-2)),
             ("qft%d_roundtrip" % n, W.concat(W.basis_prep(n, x), W.qft(n),
-                                             W.inverse(W.qft(n))).with_noise(1e-3, 1e-2))]
+                                             W.inverse(W.qft(n))).with_noise(1e-3, 1e-2)),
+            ("qaoa%d" % (n + 2), W.qaoa(n + 2, 2, seed=7).with_noise(1e-3, 1e-2))]
 
 
 def evaluate(T, torch, model, circuits, shots=16384, copy_cost=26.0, max_deff=4.0, seed=0, log=print):
