@@ -686,3 +686,15 @@ def test_degenerate_trees(T, prec):
     out, amps, oout, ost, _ = run_both(T, wc, tree, 0, prec, np.arange(16), noise_arrays=none)
     assert np.max(np.abs(amps - ost)) < TOL[prec]
     check_outcomes(out, oout, ost, none[3], DELTA[prec])
+
+
+def test_c2_20q_tree_sampled_leaves_c128(T):
+    # the same 20-qubit QFT tree in complex128 (16 MiB states) on a handful
+    # of leaves: amplitudes within 1e-12 of the oracle
+    wc = W.qft(20).with_depolarizing(1e-3, 1e-2)
+    G = len(wc)
+    tree = ([16, 32, 32], [0, G // 3, 2 * G // 3, G])
+    leaves = np.array([0, 1, 5000, 16383])
+    out, amps, oout, ost, onz = run_both(T, wc, tree, 0, "c128", leaves)
+    assert np.max(np.abs(amps - ost)) < 1e-12
+    check_outcomes(out[leaves], oout, ost, onz.leaf_u[leaves], DELTA["c128"])
