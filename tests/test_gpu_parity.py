@@ -698,3 +698,37 @@ def test_c2_20q_tree_sampled_leaves_c128(T):
     out, amps, oout, ost, onz = run_both(T, wc, tree, 0, "c128", leaves)
     assert np.max(np.abs(amps - ost)) < 1e-12
     check_outcomes(out[leaves], oout, ost, onz.leaf_u[leaves], DELTA["c128"])
+
+
+@pytest.mark.parametrize("seed", range(32))
+def test_random_configurations(T, seed):
+    # random circuits (every op class, swap networks), trees, tunings,
+    # insertion lists with repeated histories, and read-out flips: every
+    # leaf's amplitudes and outcome against the oracle
+    rng = np.random.default_rng(900 + seed)
+    n = int(rng.integers(11, 15))
+    wc = mixed_gates(n, int(rng.integers(30, 70)), rng)
+    for i in range(int(rng.integers(0, n // 2))):
+        a, b = [int(x) for x in rng.choice(n, 2, replace=False)]
+        wc.add((a, b), W.swap())
+    G = len(wc)
+    levels = int(rng.integers(1, 4))
+    cut = [0] + sorted(rng.choice(np.arange(1, G), levels - 1, replace=False).tolist()) + [G]
+    A = [int(a) for a in rng.integers(2, 6, levels)]
+    tree = (A, cut)
+    tuning = {"chunk_states": int(rng.integers(1, 8)), "tile_qubits": int(rng.choice([10, 11])),
+              "sample_block_log": int(rng.integers(8, 13)), "separate_sampling": int(rng.integers(0, 2)),
+              "no_merge": int(rng.integers(0, 2)), "pass_cost": int(rng.choice([120, 480]))}
+    arr = _repeating_events(wc, tree, rng, rate=float(rng.uniform(0.01, 0.1)))
+    flips = rng.integers(0, 1 << n, arr[3].size).astype(np.uint32) if seed % 2 else None
+    c = T.Circuit.from_workload(wc)
+    nz = T.Noise.from_arrays(c, tree, *arr, leaf_flip=flips)
+    prec = "c128" if seed % 3 == 0 else "c64"
+    plan = T.Plan(c, tree, prec, tuning)
+    leaves = np.arange(int(np.prod(A)))
+    out, amps = T.run_capture(plan, nz, leaves)
+    onz = oracle.Noise(*[np.asarray(x) for x in arr], flips)
+    oout, ost = oracle.run_leaves(wc.n, wc.gates, tree, onz, leaves, states=True)
+    assert np.max(np.abs(amps - ost)) < TOL[prec], tuning
+    f = np.zeros(leaves.size, np.uint64) if flips is None else flips.astype(np.uint64)
+    check_outcomes(out ^ f, oout ^ f, ost, arr[3], DELTA[prec])
