@@ -424,3 +424,20 @@ def test_workspace_bound_holds_for_any_list(seed):
         bound = p.workspace_bytes(None)
         for s in range(3):
             assert p.workspace_bytes(T.Noise.sample(c, tree, s)) <= bound
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    # without the built library the binding raises at import: there is no
+    # fallback path
+    import shutil
+    import subprocess
+    import sys
+    env = dict(os.environ)
+    # a copy of the package without the shared library
+    pkg = tmp_path / "paper_2203_13892_amd"
+    shutil.copytree(os.path.join(ROOT, "paper_2203_13892_amd"), pkg,
+                    ignore=shutil.ignore_patterns("*.so", "__pycache__", "csrc", "data"))
+    code = "import sys; sys.path.insert(0, %r)\nimport paper_2203_13892_amd.tqsim\n" % str(tmp_path)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=300)
+    assert r.returncode != 0
+    assert "libtqsim.so is not built" in r.stderr
