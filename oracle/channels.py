@@ -3,7 +3,8 @@
 Only tests, smoke() and the CPU-baseline leg of the bench use this module.
 Written from the definitions, not from the closed forms the product side
 uses: amplitude damping (decay probability gamma) and phase damping
-(parameter lambda) as Kraus operators (the noise models named in Sec. 4.3),
+(parameter lambda) as Kraus operators and thermal relaxation (T1, T2, gate
+time) by its action on matrix elements (the noise models named in Sec. 4.3),
 the Pauli twirl as the Pauli-diagonal part of a channel's process matrix,
 p_P = sum_k |tr(P^dagger K_k)|^2 / 4, and density-matrix application of a
 Kraus channel and of a Pauli channel for checks on small systems.
@@ -50,6 +51,33 @@ def apply_pauli_channel(rho, probs):
         # index bit 0 is the first qubit: operator = P_{c1} (x) P_{c0}
         P = np.kron(PAULI[c >> 2], PAULI[c & 3])
         out += p * P @ rho @ P.conj().T
+    return out
+
+
+def thermal_relaxation(rho, t, T1, T2):
+    """Thermal relaxation toward |0> for a time t (one qubit, T2 <= 2 T1),
+    by its definition on matrix elements: the excited population decays as
+    e^{-t/T1} into |0>, coherences decay as e^{-t/T2}."""
+    g = 1.0 - np.exp(-t / T1)
+    c = np.exp(-t / T2)
+    out = np.empty_like(rho)
+    out[0, 0] = rho[0, 0] + g * rho[1, 1]
+    out[1, 1] = (1.0 - g) * rho[1, 1]
+    out[0, 1] = c * rho[0, 1]
+    out[1, 0] = c * rho[1, 0]
+    return out
+
+
+def pauli_twirl_of_map(f):
+    """Pauli probabilities (I, X, Y, Z) of the twirl of a one-qubit linear
+    map f, from its Pauli transfer diagonal lambda_Q = tr(Q f(Q)) / 2:
+    p_P = (1/4) sum_Q s(P, Q) lambda_Q, s = +1 if P and Q commute, else -1."""
+    lam = [np.real(np.trace(Q @ f(Q))) / 2.0 for Q in PAULI]
+    out = np.zeros(4)
+    for a, P in enumerate(PAULI):
+        for b, Q in enumerate(PAULI):
+            sgn = 1.0 if np.allclose(P @ Q, Q @ P) else -1.0
+            out[a] += sgn * lam[b] / 4.0
     return out
 
 

@@ -112,6 +112,18 @@ def phase_damping_probs(lam: float) -> np.ndarray:
     return np.array([1.0 - pz, 0.0, 0.0, pz], np.float64)
 
 
+def thermal_relaxation_params(t: float, T1: float, T2: float):
+    """(gamma, lambda) such that amplitude damping gamma followed by phase
+    damping lambda is thermal relaxation over a time t: populations relax
+    with e^{-t/T1}, coherences with e^{-t/T2} (requires 0 < T2 <= 2 T1)."""
+    if not (T1 > 0 and 0 < T2 <= 2 * T1 and t >= 0):
+        raise ValueError("need T1 > 0, 0 < T2 <= 2 T1, t >= 0")
+    gamma = 1.0 - float(np.exp(-t / T1))
+    # sqrt(1 - gamma) sqrt(1 - lambda) = e^{-t/T2}
+    lam = 1.0 - float(np.exp(-2.0 * t / T2 + t / T1))
+    return gamma, max(lam, 0.0)
+
+
 # one-qubit Pauli codes (0 I, 1 X, 2 Y, 3 Z) multiply, up to phase, as their
 # (x, z) bit pairs xor: I (0,0), X (1,0), Y (1,1), Z (0,1)
 _CODE_XZ = [(0, 0), (1, 0), (1, 1), (0, 1)]
@@ -182,6 +194,22 @@ class Circuit:
         out = Circuit(self.n, [], self.name)
         for q, m, _ in self.gates:
             a = len(q)
+            dep = depolarizing_probs(p1 if a == 1 else p2, a)
+            pr = compose_pauli_channels(dep, per_qubit_channel(ch, a), a)
+            out.add(q, m, pr if pr[0] < 1.0 else None)
+        out.readout = self.readout
+        return out
+
+    def with_thermal_relaxation(self, p1: float, p2: float, t1: float, t2: float,
+                                T1: float, T2: float) -> "Circuit":
+        """Copy with, after every gate, the depolarizing channel (p1 / p2) and
+        then on each of its qubits the Pauli-twirled thermal relaxation over
+        the gate's duration (t1 for one-qubit, t2 for two-qubit gates)."""
+        out = Circuit(self.n, [], self.name)
+        for q, m, _ in self.gates:
+            a = len(q)
+            g, lam = thermal_relaxation_params(t1 if a == 1 else t2, T1, T2)
+            ch = compose_pauli_channels(amplitude_damping_twirl(g), phase_damping_probs(lam), 1)
             dep = depolarizing_probs(p1 if a == 1 else p2, a)
             pr = compose_pauli_channels(dep, per_qubit_channel(ch, a), a)
             out.add(q, m, pr if pr[0] < 1.0 else None)

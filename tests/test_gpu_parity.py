@@ -348,12 +348,14 @@ def test_damping_channels(T, prec):
     # depolarizing plus twirled amplitude damping and phase damping on each
     # gate's qubits (one Pauli channel per gate), a 13-qubit brick-wall in a
     # 3-level tree, at rates high enough that most nodes draw events
-    wc = W.brickwall(13, 10, seed=4).with_noise(0.01, 0.05, gamma=0.05, lam=0.03)
-    G = len(wc)
-    tree = ([4, 3, 3], [0, G // 3, 2 * G // 3, G])
-    out, amps, oout, ost, onz = run_both(T, wc, tree, 9, prec, np.arange(36))
-    assert np.max(np.abs(amps - ost)) < TOL[prec]
-    check_outcomes(out, oout, ost, onz.leaf_u, DELTA[prec])
+    # (and thermal relaxation over the gate times, twirled the same way)
+    for wc in (W.brickwall(13, 10, seed=4).with_noise(0.01, 0.05, gamma=0.05, lam=0.03),
+               W.qft(12).with_thermal_relaxation(0.005, 0.02, 0.05, 0.3, 8.0, 6.0)):
+        G = len(wc)
+        tree = ([4, 3, 3], [0, G // 3, 2 * G // 3, G])
+        out, amps, oout, ost, onz = run_both(T, wc, tree, 9, prec, np.arange(36))
+        assert np.max(np.abs(amps - ost)) < TOL[prec]
+        check_outcomes(out, oout, ost, onz.leaf_u, DELTA[prec])
 
 
 def test_c4_precision_brickwall_22q(T):

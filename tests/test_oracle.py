@@ -520,3 +520,35 @@ def test_readout_histogram_matches_confusion_of_density_matrix():
     both = int(np.sum((f & 3) == 3))
     r01 = wc.readout[0] * wc.readout[1]
     assert abs(both - S * r01) <= 5 * math.sqrt(S * r01 * (1 - r01))
+
+
+@pytest.mark.parametrize("t,T1,T2", [(0.0, 20.0, 15.0), (0.05, 20.0, 15.0), (0.5, 10.0, 20.0),
+                                     (2.0, 5.0, 1.0), (1.0, 3.0, 6.0)])
+def test_thermal_relaxation_is_damping_in_sequence(t, T1, T2):
+    # thermal relaxation by its definition equals amplitude damping then
+    # phase damping with the parameters the workloads derive, and its twirl
+    # (from the Pauli transfer diagonal) is their composed Pauli channel
+    from oracle import channels as ch
+    g, lam = W.thermal_relaxation_params(t, T1, T2)
+    rng = np.random.default_rng(int(t * 100 + T1))
+    rho = _random_rho(2, rng)
+    seq = ch.apply_kraus(ch.apply_kraus(rho, ch.kraus_amplitude_damping(g)), ch.kraus_phase_damping(lam))
+    assert np.allclose(ch.thermal_relaxation(rho, t, T1, T2), seq, atol=1e-14)
+    tw = ch.pauli_twirl_of_map(lambda r: ch.thermal_relaxation(r, t, T1, T2))
+    want = W.compose_pauli_channels(W.amplitude_damping_twirl(g), W.phase_damping_probs(lam), 1)
+    assert np.allclose(tw, want, atol=1e-14)
+    # t = 0 is the identity channel
+    if t == 0.0:
+        assert np.allclose(tw, [1, 0, 0, 0])
+
+
+def test_thermal_relaxation_circuit_trajectories_match_density_matrix():
+    from oracle import density
+    wc = W.brickwall(4, 4, seed=5).with_thermal_relaxation(0.01, 0.02, 0.05, 0.3, 8.0, 6.0)
+    rho = density.dm_run(wc.n, wc.gates)
+    tree = ([3000], [0, len(wc)])
+    nz = oracle.sample_noise(wc.gates, tree, 12)
+    _, st = oracle.run_leaves(wc.n, wc.gates, tree, nz, states=True)
+    mean = np.mean(np.abs(st) ** 2, axis=0)
+    sd = np.std(np.abs(st) ** 2, axis=0) / np.sqrt(st.shape[0])
+    assert np.all(np.abs(mean - np.real(np.diag(rho))) <= 4 * sd + 1e-12)
