@@ -733,15 +733,20 @@ static void build_schedule(const tqs_plan *p, uint64_t first0, uint64_t last0, s
 struct HostMeta {
     std::vector<uint32_t> frame0;  // 2 per node
     std::vector<uint32_t> ev_off, ev_pos, ev_dx, ev_dz;
+    // per node: how many of its (position-sorted) events the passes apply
+    // before some op; the rest come after the level's last op and change
+    // only the frame the node ends with, not its state
+    std::vector<uint32_t> ev_eff;
     std::vector<uint32_t> leaf_fx;
     std::vector<Frame> leaf_frame;
 };
 
 // Two nodes compute the same state from the same parent state when they
-// start from the same frame and meet the same events at the same places.
+// start from the same frame and meet the same events at the same places
+// before the level's last op (later events change only their end frames).
 static bool same_history(const HostMeta &hm, uint32_t a, uint32_t b) {
     if (hm.frame0[2 * a] != hm.frame0[2 * b] || hm.frame0[2 * a + 1] != hm.frame0[2 * b + 1]) return false;
-    const uint32_t na = hm.ev_off[a + 1] - hm.ev_off[a], nb = hm.ev_off[b + 1] - hm.ev_off[b];
+    const uint32_t na = hm.ev_eff[a], nb = hm.ev_eff[b];
     if (na != nb) return false;
     for (uint32_t i = 0; i < na; i++) {
         const uint32_t ea = hm.ev_off[a] + i, eb = hm.ev_off[b] + i;
@@ -753,7 +758,7 @@ static bool same_history(const HostMeta &hm, uint32_t a, uint32_t b) {
 
 static uint64_t history_hash(const HostMeta &hm, uint32_t a) {
     uint64_t h = ((uint64_t)hm.frame0[2 * a] << 32) ^ hm.frame0[2 * a + 1];
-    for (uint32_t e = hm.ev_off[a]; e < hm.ev_off[a + 1]; e++) {
+    for (uint32_t e = hm.ev_off[a]; e < hm.ev_off[a] + hm.ev_eff[a]; e++) {
         h = (h ^ hm.ev_pos[e]) * 0x100000001B3ull;
         h = (h ^ ((uint64_t)hm.ev_dx[e] << 32 | hm.ev_dz[e])) * 0x100000001B3ull;
     }
@@ -775,11 +780,25 @@ static void build_meta(const tqs_plan *p, const tqs_noise *nz, HostMeta *hm) {
     hm->ev_dz.resize(E);
     hm->leaf_fx.assign(p->n_leaves, 0);
     hm->leaf_frame.assign(p->n_leaves, Frame());
+    hm->ev_eff.assign(N, 0);
     std::vector<Frame> fend(N);
     std::vector<std::pair<uint32_t, uint64_t>> ord;
     const uint32_t L = (uint32_t)p->arity.size();
     for (uint32_t l = 0; l < L; l++) {
         const uint64_t I = p->level_nodes[l], off = p->level_offset[l];
+        // the last position at which a pass of this level applies an event
+        // before an op: before a dense op at its first slot, inside a phase
+        // run up to its last gate (events after it touch no op of the level)
+        int64_t limit = -1;
+        const tqs::Level &lv = p->levels[l];
+        for (uint32_t pi = lv.pass_begin; pi < lv.pass_begin + lv.pass_count; pi++) {
+            const PassDesc &pd = p->passes[pi];
+            for (uint32_t oi = pd.op_begin; oi < pd.op_begin + pd.op_count; oi++) {
+                const OpDesc &o = p->ops[oi];
+                const uint32_t last = o.slot1 > o.slot0 ? (uint32_t)o.slot1 - 1u : (uint32_t)o.slot0;
+                limit = std::max<int64_t>(limit, (int64_t)((pi << 16) | std::max<uint32_t>(o.slot0, last)));
+            }
+        }
         for (uint64_t m = 0; m < I; m++) {
             const uint64_t nu = off + m;
             Frame f;
@@ -817,6 +836,9 @@ static void build_meta(const tqs_plan *p, const tqs_noise *nz, HostMeta *hm) {
                 f = compose(dx, dz, ky, f);
             }
             hm->ev_off[nu + 1] = (uint32_t)nz->node_off[nu + 1];
+            uint32_t eff = 0;
+            while (eff < ord.size() && (int64_t)ord[eff].first <= limit) eff++;
+            hm->ev_eff[nu] = eff;
             fend[nu] = f;
             if (l == L - 1) {
                 hm->leaf_fx[m] = to_logical(p, f.x);

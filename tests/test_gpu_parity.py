@@ -508,8 +508,9 @@ def _distinct_histories(tree, arr):
 def test_merged_states_equal_separate_states(T, prec):
     # nodes with equal parent state, frame and events share one state: the
     # outcomes are bit-identical to computing every node, the captured
-    # leaves match the oracle, and the merge count is the number of
-    # repeated histories (one chunk per level here)
+    # leaves match the oracle, and at least every repeated history is
+    # merged (one chunk per level here; events after a level's last op may
+    # merge more)
     rng = np.random.default_rng(31)
     wc = mixed_gates(12, 48, rng)
     tree = ([4, 8, 8], [0, 16, 32, 48])
@@ -524,7 +525,7 @@ def test_merged_states_equal_separate_states(T, prec):
     assert st_p["nodes_merged"] == 0
     want = _distinct_histories(tree, arr)
     assert want > 100
-    assert st_m["nodes_merged"] == want
+    assert st_m["nodes_merged"] >= want
     assert st_m["pass_states"] < st_p["pass_states"]
     leaves = np.arange(256)
     out, amps, oout, ost, _ = run_both(T, wc, tree, 0, prec, leaves, noise_arrays=arr)
@@ -734,3 +735,36 @@ def test_random_configurations(T, seed):
     assert np.max(np.abs(amps - ost)) < TOL[prec], tuning
     f = np.zeros(leaves.size, np.uint64) if flips is None else flips.astype(np.uint64)
     check_outcomes(out ^ f, oout ^ f, ost, arr[3], DELTA[prec])
+
+
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+def test_events_after_the_last_op_share_states(T, prec):
+    # events on trailing relabelled swap gates (after a level's last op)
+    # change only the end frame: such nodes share their sibling's state, and
+    # outcomes and amplitudes (frame applied) still match the oracle
+    rng = np.random.default_rng(70)
+    wc = mixed_gates(12, 30, rng)
+    for i in range(5):
+        wc.add((i, 11 - i), W.swap())
+    G = len(wc)
+    tree = ([3, 8], [0, 15, G])
+    # every leaf: one event on a trailing swap, or none
+    node_off, eg, ec = [0, 0, 0, 0], [], []
+    for m in range(24):
+        if m % 3:
+            eg.append(G - 1 - (m % 5))
+            ec.append(int(rng.integers(1, 16)))
+        node_off.append(len(eg))
+    arr = (np.array(node_off, np.uint64), np.array(eg, np.uint32), np.array(ec, np.uint8), rng.random(24))
+    c = T.Circuit.from_workload(wc)
+    nz = T.Noise.from_arrays(c, tree, *arr)
+    plan = T.Plan(c, tree, prec, {"chunk_states": 64})
+    out, st = T.run(plan, nz, stats=True)
+    # the 3 roots have no events and share one state, so all 24 leaves start
+    # from it and share one state whatever their trailing events
+    assert st["nodes_merged"] == 2 + 23
+    plain = T.run(T.Plan(c, tree, prec, {"chunk_states": 64, "no_merge": 1}), nz)
+    assert np.array_equal(out, plain)
+    out2, amps, oout, ost, _ = run_both(T, wc, tree, 0, prec, np.arange(24), noise_arrays=arr)
+    assert np.max(np.abs(amps - ost)) < TOL[prec]
+    check_outcomes(out2, oout, ost, arr[3], DELTA[prec])
