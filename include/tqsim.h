@@ -195,7 +195,8 @@ tqs_status tqs_noise_view(const tqs_noise *nz, const uint64_t **node_off,
                           const double **leaf_u, uint64_t *n_nodes, uint64_t *n_leaves);
 
 /* Set explicit read-out flip masks, leaf_flip[n_leaves] (copied; bit q
- * flips qubit q's measured bit), or remove them with NULL. */
+ * flips qubit q's measured bit), or remove them with NULL.  A run refuses
+ * masks with bits at or above the plan's qubit count (TQS_E_ARG). */
 tqs_status tqs_noise_set_flips(tqs_noise *nz, const uint32_t *leaf_flip);
 
 /* Borrowed view of the flip masks: *leaf_flip = NULL when there are none. */

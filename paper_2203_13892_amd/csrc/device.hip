@@ -1011,6 +1011,14 @@ static tqs_status check_noise(const tqs_plan *p, const tqs_noise *nz) {
     if (!nz) return fail(TQS_E_ARG, "noise is NULL");
     if (nz->n_gates != p->n_gates || nz->arity != p->arity || nz->cut != p->cut)
         return fail(TQS_E_ARG, "noise list was sampled for another circuit or tree");
+    if (!nz->leaf_flip.empty()) {
+        if (nz->leaf_flip.size() != p->n_leaves) return fail(TQS_E_ARG, "read-out flips: one mask per leaf");
+        const uint64_t lim = 1ull << p->n;
+        for (uint64_t i = 0; i < nz->leaf_flip.size(); i++)
+            if (nz->leaf_flip[i] >= lim)
+                return fail(TQS_E_ARG, "read-out flip mask of leaf %llu has bits beyond qubit %u",
+                            (unsigned long long)i, p->n - 1);
+    }
     return TQS_OK;
 }
 

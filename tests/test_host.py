@@ -335,6 +335,12 @@ def test_readout_flips_match_oracle():
     assert np.array_equal(nz3.flips(), o.leaf_flip)
     with pytest.raises(T.TqsError):
         c.set_readout([0.1, 0.2, 0.3, 0.4, 0.5, 1.5])
+    # masks with bits beyond the circuit's qubits are refused before any run
+    bad = o.leaf_flip.copy()
+    bad[3] = 1 << 6
+    nz4 = T.Noise.from_arrays(c, tree, *nz2.arrays(), leaf_flip=bad)
+    with pytest.raises(T.TqsError, match="beyond qubit"):
+        T.Plan(c, tree, "c64").workspace_bytes(nz4)
 
 
 def _tiled_block_masses(text, psi_phys, b):
