@@ -109,8 +109,8 @@ def time_form(T, torch, circuit, tree, seed, steps, warmup, tuning=None):
 def fidelity_loss(T, W, torch, seeds, n=20, shots=16384):
     """Normalised fidelity (F_s of a peaked ideal distribution, normalised
     against the uniform one) of the 20-qubit QFT round trip from a basis state,
-    tree (16, 32, 32) against per-shot, over noise seeds; difference +- its
-    standard error."""
+    trees (16, 32, 32) and (8, 8, 16, 16) against per-shot, over noise seeds;
+    differences +- their standard errors."""
     import numpy as np
     x = 0x5A5A5 & ((1 << n) - 1)
     wc = W.concat(W.basis_prep(n, x), W.qft(n), W.inverse(W.qft(n))).with_depolarizing(1e-3, 1e-2)
@@ -118,7 +118,8 @@ def fidelity_loss(T, W, torch, seeds, n=20, shots=16384):
     c = T.Circuit.from_workload(wc)
     u = 2.0 ** -n
     out = {}
-    for name, tree in (("pershot", ([shots], [0, G])), ("tree", ([16, 32, 32], equal_cuts(G, 3)))):
+    for name, tree in (("pershot", ([shots], [0, G])), ("tree", ([16, 32, 32], equal_cuts(G, 3))),
+                       ("tree4b", ([8, 8, 16, 16], equal_cuts(G, 4)))):
         plan = T.Plan(c, tree, "c64")
         ws = None
         vals = []
@@ -131,9 +132,12 @@ def fidelity_loss(T, W, torch, seeds, n=20, shots=16384):
             vals.append((fs - u) / (1 - u))
         out[name] = np.array(vals)
     d = out["tree"] - out["pershot"]
+    d4 = out["tree4b"] - out["pershot"]
     return {"workload": "qft%d round trip from |x>, depolarizing(1e-3,1e-2), %d shots" % (n, shots),
             "F_pershot": float(out["pershot"].mean()), "F_tree": float(out["tree"].mean()),
             "delta_F": float(d.mean()), "delta_F_se": float(d.std(ddof=1) / np.sqrt(len(d))),
+            "F_tree4b": float(out["tree4b"].mean()), "delta_F_tree4b": float(d4.mean()),
+            "delta_F_tree4b_se": float(d4.std(ddof=1) / np.sqrt(len(d4))),
             "seeds": seeds}
 
 
