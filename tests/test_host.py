@@ -447,3 +447,26 @@ def test_missing_library_fails_loudly(tmp_path):
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=300)
     assert r.returncode != 0
     assert "libtqsim.so is not built" in r.stderr
+
+
+def test_host_code_under_address_and_undefined_behaviour_sanitizers(tmp_path):
+    # the planner, noise sampler, importer, DCP and histogram (pure host
+    # code) on random circuits, trees and tunings, built with g++ under
+    # AddressSanitizer and UndefinedBehaviorSanitizer; any report aborts
+    import shutil
+    import subprocess
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("g++ not available")
+    exe = str(tmp_path / "host_sanitize")
+    csrc = os.path.join(ROOT, "paper_2203_13892_amd", "csrc")
+    cmd = [gxx, "-std=c++17", "-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+           "-fno-omit-frame-pointer", "-I", os.path.join(ROOT, "include"), "-I", csrc,
+           os.path.join(csrc, "plan.cpp"), os.path.join(csrc, "host.cpp"),
+           os.path.join(ROOT, "tests", "host_sanitize.cpp"), "-o", exe]
+    subprocess.run(cmd, check=True, capture_output=True, timeout=600)
+    # (another preloaded library may come before the sanitizer runtime)
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=1:verify_asan_link_order=0")
+    r = subprocess.run([exe, "300"], capture_output=True, text=True, timeout=600, env=env)
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert "cases 300" in r.stdout
