@@ -9,11 +9,13 @@
 // memory traffic: it only updates (x, z).  At the leaf, the outcome of psi
 // is the outcome of s with its index xor-ed by x.
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <array>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <unordered_map>
@@ -1065,6 +1067,14 @@ static void pack_meta(const tqs_plan *p, const tqs_noise *nz, const HostMeta &hm
     put(Ly.off_sched, sched.data(), sched.size() * 4);
 }
 
+// A roctx range open for the lifetime of the object (every return path).
+struct MarkerRange {
+    explicit MarkerRange(const char *name) { roctxRangePush(name); }
+    ~MarkerRange() { roctxRangePop(); }
+    MarkerRange(const MarkerRange &) = delete;
+    MarkerRange &operator=(const MarkerRange &) = delete;
+};
+
 template <typename R>
 static tqs_status run_t(tqs_plan *p, const tqs_noise *nz, unsigned char *ws, uint64_t ws_bytes,
                         hipStream_t s, uint64_t first, uint64_t last, uint64_t *outcomes,
@@ -1123,6 +1133,10 @@ static tqs_status run_t(tqs_plan *p, const tqs_noise *nz, unsigned char *ws, uin
     for (const Task &t : tasks) {
         const tqs::Level &lv = p->levels[t.level];
         merged += t.count - t.ccount;
+        // a marker range per chunk task, for timelines (no cost without a tool)
+        char mark[64];
+        std::snprintf(mark, sizeof mark, "tqs level %u: %u nodes, %u computed", t.level, t.count, t.ccount);
+        const MarkerRange range(mark);
         hipEvent_t ea = nullptr, eb = nullptr, ec = nullptr;
         if (stats) {
             ea = pool_event(p, ev_i++);
