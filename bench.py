@@ -425,8 +425,8 @@ def main():
                     help="skip the 20-qubit brick-wall forms (reported beside the QFT ones)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the level-0 subtrees would shard across GPUs; see the design notes)",
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
+              "(level-0 subtree ranges would be split across GPUs with tqs_run_range)",
               file=sys.stderr)
         sys.exit(2)
 

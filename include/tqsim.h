@@ -70,7 +70,7 @@ typedef enum {
     TQS_E_WORKSPACE = -3,   /* workspace too small or misaligned */
     TQS_E_HIP = -4,         /* HIP runtime error (message carries its text) */
     TQS_E_OOM = -5,         /* host allocation failed */
-    TQS_E_UNSUPPORTED = -6  /* valid request outside what this build supports */
+    TQS_E_UNSUPPORTED = -6  /* valid request outside what the library supports */
 } tqs_status;
 
 typedef enum { TQS_C64 = 0, TQS_C128 = 1 } tqs_precision;
