@@ -67,7 +67,7 @@ __device__ __forceinline__ uint64_t uni(uint64_t x) {
 // phases in the accumulator width A.
 template <typename A>
 struct TermU {
-    uint32_t nq, role1, phys0, phys1;
+    uint32_t nq, role1, phys0, phys1, k;
     A th[4];
 };
 template <typename A>
@@ -80,6 +80,7 @@ __device__ __forceinline__ TermU<A> load_term(kptr<DiagTerm> p) {
     t.role1 = (w0 >> 16) & 0xFFu;
     t.phys0 = (w1 >> 8) & 0xFFu;
     t.phys1 = (w1 >> 16) & 0xFFu;
+    t.k = (w1 >> 24) & 0xFFu;
 #pragma unroll
     for (int r = 0; r < 4; r++) {
         if constexpr (sizeof(A) == 4) t.th[r] = uni(w[2 + 2 * r]);
@@ -554,6 +555,143 @@ __device__ __forceinline__ void op_diag_one(cplx<R> (&v)[1 << RB], const DiagGat
     });
 }
 
+// The run's phase factors applied with one multiply per amplitude (plus one
+// per register-dependent coefficient): e^{2 pi i (C + sum_i lam_i x_i)}.
+template <typename R, int RB>
+__device__ __forceinline__ void apply_run_phase(cplx<R> (&v)[1 << RB], typename Turns<R>::T C,
+                                                const typename Turns<R>::T (&lam)[RB], uint32_t lm) {
+    constexpr int NJ = 1 << RB;
+    constexpr int LO = RB < 3 ? RB : 3;
+    constexpr int HI = RB - LO;
+    if (__builtin_popcount(lm) == 1) {
+        // one register-dependent factor: e^{2 pi i C} on the registers with
+        // the bit clear, e^{2 pi i (C + lam_i)} on the others
+        with_reg<RB>((uint32_t)__builtin_ctz(lm), [&](auto Ic) __attribute__((always_inline)) {
+            constexpr int I = decltype(Ic)::value;
+            const cplx<R> w0 = expi_turns(C);
+            const cplx<R> w1 = cmul(w0, expi_turns(lam[I]));
+            sfor<NJ>([&](auto Jc) __attribute__((always_inline)) {
+                constexpr int j = decltype(Jc)::value;
+                v[j] = cmul(((j >> I) & 1) ? w1 : w0, v[j]);
+            });
+        });
+    } else if (__builtin_popcount(lm) <= 2) {
+        // few register-dependent factors: e^{2 pi i C}, then e^{2 pi i lam_i}
+        // on the registers with bit i set
+        const cplx<R> w0 = expi_turns(C);
+        sfor<NJ>([&](auto Jc) __attribute__((always_inline)) {
+            constexpr int j = decltype(Jc)::value;
+            v[j] = cmul(w0, v[j]);
+        });
+        sfor<RB>([&](auto Ic) __attribute__((always_inline)) {
+            constexpr int i = decltype(Ic)::value;
+            if ((lm >> i) & 1u) {
+                const cplx<R> e = expi_turns(lam[i]);
+                sfor<NJ>([&](auto Jc) __attribute__((always_inline)) {
+                    constexpr int j = decltype(Jc)::value;
+                    if constexpr (((j >> i) & 1) != 0) v[j] = cmul(e, v[j]);
+                });
+            }
+        });
+    } else {
+        // subset products over the low and high register bits
+        cplx<R> wlo[1 << LO], whi[1 << HI];
+        wlo[0] = expi_turns(C);
+        sfor<LO>([&](auto Ic) __attribute__((always_inline)) {
+            constexpr int i = decltype(Ic)::value;
+            const cplx<R> e = expi_turns(lam[i]);
+            sfor<(1 << i)>([&](auto Sc) __attribute__((always_inline)) {
+                constexpr int s2 = decltype(Sc)::value;
+                wlo[s2 | (1 << i)] = cmul(wlo[s2], e);
+            });
+        });
+        whi[0] = cplx<R>{R(1), R(0)};
+        sfor<HI>([&](auto Ic) __attribute__((always_inline)) {
+            constexpr int i = decltype(Ic)::value;
+            const cplx<R> e = expi_turns(lam[LO + i]);
+            sfor<(1 << i)>([&](auto Sc) __attribute__((always_inline)) {
+                constexpr int s2 = decltype(Sc)::value;
+                whi[s2 | (1 << i)] = cmul(whi[s2], e);
+            });
+        });
+        sfor<NJ>([&](auto Jc) __attribute__((always_inline)) {
+            constexpr int j = decltype(Jc)::value;
+            const cplx<R> w = HI ? cmul(wlo[j & ((1 << LO) - 1)], whi[j >> LO]) : wlo[j & ((1 << LO) - 1)];
+            v[j] = cmul(w, v[j]);
+        });
+    }
+}
+
+// A phase run split by one noise event: its gates before gate `ks` see the
+// frame fxa, the others fxb (only the X part matters for diagonal gates).
+// Same phase polynomial as op_diag_run, with each term evaluated in its own
+// gate's frame and the register-bit frame folded in per term; the gates on
+// register qubits only are applied one by one by the caller.
+template <typename R, int RB>
+__device__ __forceinline__ void op_diag_run_split(cplx<R> (&v)[1 << RB], const OpDesc &o, kptr<DiagTerm> tm,
+                                                  uint32_t fxa, uint32_t fxb, uint32_t ks, uint32_t L,
+                                                  uint32_t base, const uint32_t (&rq)[RB]) {
+    using A = typename Turns<R>::T;
+    A C = 0;
+    A lam[RB];
+#pragma unroll
+    for (int i = 0; i < RB; i++) lam[i] = 0;
+    kptr<DiagTerm> p = tm;
+    for (uint32_t k = 0; k < o.n_fix; k++) {
+        const TermU<A> t = load_term<A>(p + k);
+        const uint32_t yfix = base ^ (t.k < ks ? fxa : fxb);
+        const uint32_t y0 = (yfix >> t.phys0) & 1u;
+        const uint32_t y1 = t.nq == 2 ? (yfix >> t.phys1) & 1u : 0u;
+        const A lo = y0 ? t.th[1] : t.th[0], hi = y0 ? t.th[3] : t.th[2];
+        C += y1 ? hi : lo;
+    }
+    p += o.n_fix;
+    sfor<RB>([&](auto Ic) __attribute__((always_inline)) {
+        constexpr int i = decltype(Ic)::value;
+        const uint32_t cnt = o.n_fixreg[i];
+        for (uint32_t k = 0; k < cnt; k++) {
+            const TermU<A> t = load_term<A>(p + k);
+            const uint32_t f = t.k < ks ? fxa : fxb;
+            const uint32_t y = ((base ^ f) >> t.phys0) & 1u;
+            const A a0 = y ? t.th[1] : t.th[0], a1 = y ? t.th[3] : t.th[2];
+            // register value x_i ^ f_i: a0 + (a1 - a0) (x_i ^ f_i)
+            const bool fi = ((f >> rq[i]) & 1u) != 0;
+            C += fi ? a1 : a0;
+            lam[i] += fi ? (A)(a0 - a1) : (A)(a1 - a0);
+        }
+        p += cnt;
+    });
+    for (uint32_t k = 0; k < o.n_lane; k++) {
+        const TermU<A> t = load_term<A>(p + k);
+        const uint32_t f = t.k < ks ? fxa : fxb;
+        const uint32_t ylane = L ^ f, yfix = base ^ f;
+        const uint32_t y0 = (ylane >> t.phys0) & 1u;
+        if (t.nq == 1) {
+            C += y0 ? t.th[1] : t.th[0];
+        } else {
+            const uint32_t y1 = t.role1 == ROLE_LANE ? (ylane >> t.phys1) & 1u : (yfix >> t.phys1) & 1u;
+            const A lo = y0 ? t.th[1] : t.th[0], hi = y0 ? t.th[3] : t.th[2];
+            C += y1 ? hi : lo;
+        }
+    }
+    p += o.n_lane;
+    sfor<RB>([&](auto Ic) __attribute__((always_inline)) {
+        constexpr int i = decltype(Ic)::value;
+        const uint32_t cnt = o.n_lanereg[i];
+        for (uint32_t k = 0; k < cnt; k++) {
+            const TermU<A> t = load_term<A>(p + k);
+            const uint32_t f = t.k < ks ? fxa : fxb;
+            const uint32_t y = ((L ^ f) >> t.phys0) & 1u;
+            const A a0 = y ? t.th[1] : t.th[0], a1 = y ? t.th[3] : t.th[2];
+            const bool fi = ((f >> rq[i]) & 1u) != 0;
+            C += fi ? a1 : a0;
+            lam[i] += fi ? (A)(a0 - a1) : (A)(a1 - a0);
+        }
+        p += cnt;
+    });
+    apply_run_phase<R, RB>(v, C, lam, o.lam_mask);
+}
+
 // A run of diagonal gates as one phase polynomial (all its gates commute).
 // With y = index ^ frame-x, the run's phase (in turns) is
 //   C(lane, fixed bits) + sum_i lam_i(lane, fixed bits) y_reg_i + P(y_reg).
@@ -566,8 +704,6 @@ __device__ __forceinline__ void op_diag_run(cplx<R> (&v)[1 << RB], const OpDesc 
                                             const uint32_t (&rq)[RB], uint32_t nr) {
     using A = typename Turns<R>::T;
     constexpr int NJ = 1 << RB;
-    constexpr int LO = RB < 3 ? RB : 3;
-    constexpr int HI = RB - LO;
     const uint32_t yfix = base ^ fx;  // frame-adjusted fixed bits (uniform)
     const uint32_t ylane = L ^ fx;    // frame-adjusted lane bits (lane qubits are physical 0..5)
     // wave-uniform part
@@ -648,64 +784,7 @@ __device__ __forceinline__ void op_diag_run(cplx<R> (&v)[1 << RB], const OpDesc 
             }
         }
     });
-    const uint32_t lm = o.lam_mask;
-    if (__builtin_popcount(lm) == 1) {
-        // one register-dependent factor: e^{2 pi i C} on the registers with
-        // the bit clear, e^{2 pi i (C + lam_i)} on the others
-        with_reg<RB>((uint32_t)__builtin_ctz(lm), [&](auto Ic) __attribute__((always_inline)) {
-            constexpr int I = decltype(Ic)::value;
-            const cplx<R> w0 = expi_turns(C);
-            const cplx<R> w1 = cmul(w0, expi_turns(lam[I]));
-            sfor<NJ>([&](auto Jc) __attribute__((always_inline)) {
-                constexpr int j = decltype(Jc)::value;
-                v[j] = cmul(((j >> I) & 1) ? w1 : w0, v[j]);
-            });
-        });
-    } else if (__builtin_popcount(lm) <= 2) {
-        // few register-dependent factors: e^{2 pi i C}, then e^{2 pi i lam_i}
-        // on the registers with bit i set
-        const cplx<R> w0 = expi_turns(C);
-        sfor<NJ>([&](auto Jc) __attribute__((always_inline)) {
-            constexpr int j = decltype(Jc)::value;
-            v[j] = cmul(w0, v[j]);
-        });
-        sfor<RB>([&](auto Ic) __attribute__((always_inline)) {
-            constexpr int i = decltype(Ic)::value;
-            if ((lm >> i) & 1u) {
-                const cplx<R> e = expi_turns(lam[i]);
-                sfor<NJ>([&](auto Jc) __attribute__((always_inline)) {
-                    constexpr int j = decltype(Jc)::value;
-                    if constexpr (((j >> i) & 1) != 0) v[j] = cmul(e, v[j]);
-                });
-            }
-        });
-    } else {
-        // subset products over the low and high register bits
-        cplx<R> wlo[1 << LO], whi[1 << HI];
-        wlo[0] = expi_turns(C);
-        sfor<LO>([&](auto Ic) __attribute__((always_inline)) {
-            constexpr int i = decltype(Ic)::value;
-            const cplx<R> e = expi_turns(lam[i]);
-            sfor<(1 << i)>([&](auto Sc) __attribute__((always_inline)) {
-                constexpr int s = decltype(Sc)::value;
-                wlo[s | (1 << i)] = cmul(wlo[s], e);
-            });
-        });
-        whi[0] = cplx<R>{R(1), R(0)};
-        sfor<HI>([&](auto Ic) __attribute__((always_inline)) {
-            constexpr int i = decltype(Ic)::value;
-            const cplx<R> e = expi_turns(lam[LO + i]);
-            sfor<(1 << i)>([&](auto Sc) __attribute__((always_inline)) {
-                constexpr int s = decltype(Sc)::value;
-                whi[s | (1 << i)] = cmul(whi[s], e);
-            });
-        });
-        sfor<NJ>([&](auto Jc) __attribute__((always_inline)) {
-            constexpr int j = decltype(Jc)::value;
-            const cplx<R> w = HI ? cmul(wlo[j & ((1 << LO) - 1)], whi[j >> LO]) : wlo[j & ((1 << LO) - 1)];
-            v[j] = cmul(w, v[j]);
-        });
-    }
+    apply_run_phase<R, RB>(v, C, lam, o.lam_mask);
     if (o.has_t) {
         // register-only gates: one wave-uniform factor per register index
         const uint32_t msk = (1u << nr) - 1u;
@@ -886,8 +965,24 @@ __global__ __launch_bounds__(64, (PassWaves<R, RB>::value)) void pass_kernel(Pas
             const bool inside = e < e1 && ev_pos[e] < (a.pass_key | o.slot1);
             if (!inside) {
                 op_diag_run<R, RB>(v, o, mats + o.mat, kconst(a.terms) + o.terms, fx, L, base, rq, nr);
+            } else if (o.ngates < 255u && !(e + 1 < e1 && ev_pos[e + 1] < (a.pass_key | o.slot1))) {
+                // one event inside the run: the run in two frames, the gates
+                // on register qubits only one by one
+                const uint32_t ks = (ev_pos[e] & 0xFFFFu) - o.slot0;
+                const uint32_t fxb = fx ^ ev_dx[e];
+                op_diag_run_split<R, RB>(v, o, kconst(a.terms) + o.terms, fx, fxb, ks, L, base, rq);
+                if (o.has_t) {
+                    for (uint32_t k = 0; k < o.ngates; k++) {
+                        const DiagGate dg = kload(kconst(a.dgates) + o.gates + k);
+                        const bool regonly = dg.role[0] == ROLE_REG && (dg.nq == 1 || dg.role[1] == ROLE_REG);
+                        if (regonly) op_diag_one<R, RB>(v, dg, mats + dg.d, k < ks ? fx : fxb, L, base);
+                    }
+                }
+                fx = fxb;
+                fz ^= ev_dz[e];
+                e++;
             } else {
-                // an event inside the run: gate by gate with frame updates
+                // several events inside the run: gate by gate with frame updates
                 for (uint32_t k = 0; k < o.ngates; k++) {
                     while (e < e1 && ev_pos[e] <= (a.pass_key | (o.slot0 + k))) {
                         fx ^= ev_dx[e];

@@ -312,6 +312,8 @@ extern "C" tqs_status tqs_plan_create(const tqs_circuit *c, const tqs_tree *tree
                         if (g.a == 2 && q0 == 1) rg = ((r & 1u) << 1) | (r >> 1);
                         tm.th[r] = phase_fixed(g.m[rg * nd + rg]);
                     }
+                    // the gate's index in the run (events inside a run split it)
+                    tm.k = (uint8_t)std::min<size_t>(k - i, 255);
                     const bool reg1 = g.a == 2 && tm.role[1] == ROLE_REG;
                     if (nlane == 0) {
                         if (reg1) g_fixreg[tm.pos[1]].push_back(tm);

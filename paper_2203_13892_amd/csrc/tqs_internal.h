@@ -76,7 +76,7 @@ struct OpDesc {
     uint8_t phys[2];   // physical qubit per gate qubit (frame bits)
     uint8_t tq;        // OP_DENSE1 with nq == 2: gate qubit that is the target
     uint8_t real;      // DENSE1/DENSE2: every matrix entry is real
-    uint8_t has_t;     // DIAGRUN: the register-qubit table is not all ones
+    uint8_t has_t;     // DIAGRUN: some gates act on register qubits only (the table)
     uint8_t lam_mask;  // DIAGRUN: register bits that fixed+register or lane+register terms touch
     uint16_t slot0, slot1;  // gate slots [slot0, slot1) of the pass covered by the op
     uint32_t mat;      // DENSE1/DENSE2: matrix offset; DIAGRUN: table offset (2^nr entries)
@@ -100,7 +100,7 @@ struct DiagTerm {
     uint8_t role[2];
     uint8_t pos[2];
     uint8_t phys[2];
-    uint8_t pad;
+    uint8_t k;  // index of its gate in the run (255: 255 or later)
     uint64_t th[4];
 };
 
