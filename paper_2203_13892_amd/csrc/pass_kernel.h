@@ -622,15 +622,25 @@ __device__ __forceinline__ void apply_run_phase(cplx<R> (&v)[1 << RB], typename 
     }
 }
 
-// A phase run split by one noise event: its gates before gate `ks` see the
-// frame fxa, the others fxb (only the X part matters for diagonal gates).
-// Same phase polynomial as op_diag_run, with each term evaluated in its own
-// gate's frame and the register-bit frame folded in per term; the gates on
-// register qubits only are applied one by one by the caller.
+// The X part of the frame along a phase run with up to three noise events
+// inside it: gates [0, k0) see f0, [k0, k1) f1, [k1, k2) f2, the rest f3
+// (only the X part matters for diagonal gates).
+struct RunFrames {
+    uint32_t k0, k1, k2;
+    uint32_t f0, f1, f2, f3;
+    __device__ __forceinline__ uint32_t at(uint32_t k) const {
+        return k < k0 ? f0 : (k < k1 ? f1 : (k < k2 ? f2 : f3));
+    }
+};
+
+// A phase run split by noise events: the same phase polynomial as
+// op_diag_run, with each term evaluated in its own gate's frame and the
+// register-bit frame folded in per term; the gates on register qubits only
+// are applied one by one by the caller.
 template <typename R, int RB>
 __device__ __forceinline__ void op_diag_run_split(cplx<R> (&v)[1 << RB], const OpDesc &o, kptr<DiagTerm> tm,
-                                                  uint32_t fxa, uint32_t fxb, uint32_t ks, uint32_t L,
-                                                  uint32_t base, const uint32_t (&rq)[RB]) {
+                                                  const RunFrames &rf, uint32_t L, uint32_t base,
+                                                  const uint32_t (&rq)[RB]) {
     using A = typename Turns<R>::T;
     A C = 0;
     A lam[RB];
@@ -639,7 +649,7 @@ __device__ __forceinline__ void op_diag_run_split(cplx<R> (&v)[1 << RB], const O
     kptr<DiagTerm> p = tm;
     for (uint32_t k = 0; k < o.n_fix; k++) {
         const TermU<A> t = load_term<A>(p + k);
-        const uint32_t yfix = base ^ (t.k < ks ? fxa : fxb);
+        const uint32_t yfix = base ^ rf.at(t.k);
         const uint32_t y0 = (yfix >> t.phys0) & 1u;
         const uint32_t y1 = t.nq == 2 ? (yfix >> t.phys1) & 1u : 0u;
         const A lo = y0 ? t.th[1] : t.th[0], hi = y0 ? t.th[3] : t.th[2];
@@ -651,7 +661,7 @@ __device__ __forceinline__ void op_diag_run_split(cplx<R> (&v)[1 << RB], const O
         const uint32_t cnt = o.n_fixreg[i];
         for (uint32_t k = 0; k < cnt; k++) {
             const TermU<A> t = load_term<A>(p + k);
-            const uint32_t f = t.k < ks ? fxa : fxb;
+            const uint32_t f = rf.at(t.k);
             const uint32_t y = ((base ^ f) >> t.phys0) & 1u;
             const A a0 = y ? t.th[1] : t.th[0], a1 = y ? t.th[3] : t.th[2];
             // register value x_i ^ f_i: a0 + (a1 - a0) (x_i ^ f_i)
@@ -663,7 +673,7 @@ __device__ __forceinline__ void op_diag_run_split(cplx<R> (&v)[1 << RB], const O
     });
     for (uint32_t k = 0; k < o.n_lane; k++) {
         const TermU<A> t = load_term<A>(p + k);
-        const uint32_t f = t.k < ks ? fxa : fxb;
+        const uint32_t f = rf.at(t.k);
         const uint32_t ylane = L ^ f, yfix = base ^ f;
         const uint32_t y0 = (ylane >> t.phys0) & 1u;
         if (t.nq == 1) {
@@ -680,7 +690,7 @@ __device__ __forceinline__ void op_diag_run_split(cplx<R> (&v)[1 << RB], const O
         const uint32_t cnt = o.n_lanereg[i];
         for (uint32_t k = 0; k < cnt; k++) {
             const TermU<A> t = load_term<A>(p + k);
-            const uint32_t f = t.k < ks ? fxa : fxb;
+            const uint32_t f = rf.at(t.k);
             const uint32_t y = ((L ^ f) >> t.phys0) & 1u;
             const A a0 = y ? t.th[1] : t.th[0], a1 = y ? t.th[3] : t.th[2];
             const bool fi = ((f >> rq[i]) & 1u) != 0;
@@ -965,24 +975,38 @@ __global__ __launch_bounds__(64, (PassWaves<R, RB>::value)) void pass_kernel(Pas
             const bool inside = e < e1 && ev_pos[e] < (a.pass_key | o.slot1);
             if (!inside) {
                 op_diag_run<R, RB>(v, o, mats + o.mat, kconst(a.terms) + o.terms, fx, L, base, rq, nr);
-            } else if (o.ngates < 255u && !(e + 1 < e1 && ev_pos[e + 1] < (a.pass_key | o.slot1))) {
-                // one event inside the run: the run in two frames, the gates
-                // on register qubits only one by one
-                const uint32_t ks = (ev_pos[e] & 0xFFFFu) - o.slot0;
-                const uint32_t fxb = fx ^ ev_dx[e];
-                op_diag_run_split<R, RB>(v, o, kconst(a.terms) + o.terms, fx, fxb, ks, L, base, rq);
+                continue;
+            }
+            // events inside the run (counted up to four)
+            const uint32_t end = a.pass_key | o.slot1;
+            uint32_t ne = 1;
+            while (ne < 4u && e + ne < e1 && ev_pos[e + ne] < end) ne++;
+            if (o.ngates < 255u && ne <= 3u) {
+                // up to three: the run in up to four frames, the gates on
+                // register qubits only one by one (event indexes stay in
+                // [e, e1))
+                const uint32_t eb = ne > 1u ? e + 1 : e, ec = ne > 2u ? e + 2 : eb;
+                RunFrames rf;
+                rf.f0 = fx;
+                rf.k0 = (ev_pos[e] & 0xFFFFu) - o.slot0;
+                rf.f1 = fx ^ ev_dx[e];
+                rf.k1 = ne > 1u ? (ev_pos[eb] & 0xFFFFu) - o.slot0 : 255u;
+                rf.f2 = ne > 1u ? rf.f1 ^ ev_dx[eb] : rf.f1;
+                rf.k2 = ne > 2u ? (ev_pos[ec] & 0xFFFFu) - o.slot0 : 255u;
+                rf.f3 = ne > 2u ? rf.f2 ^ ev_dx[ec] : rf.f2;
+                op_diag_run_split<R, RB>(v, o, kconst(a.terms) + o.terms, rf, L, base, rq);
                 if (o.has_t) {
                     for (uint32_t k = 0; k < o.ngates; k++) {
                         const DiagGate dg = kload(kconst(a.dgates) + o.gates + k);
                         const bool regonly = dg.role[0] == ROLE_REG && (dg.nq == 1 || dg.role[1] == ROLE_REG);
-                        if (regonly) op_diag_one<R, RB>(v, dg, mats + dg.d, k < ks ? fx : fxb, L, base);
+                        if (regonly) op_diag_one<R, RB>(v, dg, mats + dg.d, rf.at(k), L, base);
                     }
                 }
-                fx = fxb;
-                fz ^= ev_dz[e];
-                e++;
+                fx = rf.f3;
+                fz ^= ev_dz[e] ^ (ne > 1u ? ev_dz[eb] : 0u) ^ (ne > 2u ? ev_dz[ec] : 0u);
+                e += ne;
             } else {
-                // several events inside the run: gate by gate with frame updates
+                // more events inside the run: gate by gate with frame updates
                 for (uint32_t k = 0; k < o.ngates; k++) {
                     while (e < e1 && ev_pos[e] <= (a.pass_key | (o.slot0 + k))) {
                         fx ^= ev_dx[e];
