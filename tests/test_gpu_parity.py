@@ -116,6 +116,58 @@ def test_every_op_class_with_forced_noise(T, prec, n):
     check_outcomes(out, oout, ost, arr[3], DELTA[prec])
 
 
+def longest_phase_run(plan):
+    """Gates of the plan's longest run of diagonal gates whose noise events
+    act inside the run (all but its last gate), from the plan's text form:
+    'pass p' lines, 'diag slot0 slot1' ops, 'gate g pass slot-after' lines."""
+    runs, where, p = [], {}, -1
+    for line in plan.describe().splitlines():
+        f = line.split()
+        if f[0] == "pass":
+            p = int(f[1])
+        elif f[0] == "diag":
+            runs.append((int(f[2]) - int(f[1]), p, int(f[1]), int(f[2])))
+        elif f[0] == "gate":
+            where[int(f[1])] = (int(f[2]), int(f[3]))
+    _, p, s0, s1 = max(runs)
+    return sorted(g for g, (gp, gs) in where.items() if gp == p and s0 < gs < s1)
+
+
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+def test_phase_run_with_up_to_five_events_inside(T, prec):
+    # one long run of diagonal gates on lane, register and fixed qubits;
+    # leaf i carries counts[i] events inside it, so the run is applied
+    # whole, in two to four frames, and gate by gate
+    rng = np.random.default_rng(11)
+    n = 13
+    wc = W.Circuit(n)
+    for q in range(n):
+        wc.add((q,), W.haar_unitary(2, rng))
+    for i in range(48):
+        if i % 4 == 3:
+            wc.add((int(rng.integers(n)),), W.phase(float(rng.uniform(0, 6))))
+        else:
+            a, b = [int(x) for x in rng.choice(n, 2, replace=False)]
+            wc.add((a, b), W.cphase(float(rng.uniform(0, 6))) if i % 4 < 2 else W.rzz(float(rng.uniform(0, 6))))
+    for q in range(n):
+        wc.add((q,), W.haar_unitary(2, rng))
+    tree = ([8], [0, len(wc)])
+    run = longest_phase_run(T.Plan(T.Circuit.from_workload(wc), tree, prec))
+    assert len(run) >= 30
+    assert all(np.allclose(np.diag(np.diag(wc.gates[g][1])), wc.gates[g][1]) for g in run)
+    counts = [0, 1, 2, 3, 4, 5, 1, 3]
+    node_off, eg, ec = [0], [], []
+    for k in counts:
+        for g in sorted(rng.choice(run, k, replace=False)):
+            eg.append(int(g))
+            ec.append(int(rng.integers(1, 4 ** len(wc.gates[g][0]))))
+        node_off.append(len(eg))
+    arr = (np.array(node_off, np.uint64), np.array(eg, np.uint32), np.array(ec, np.uint8), rng.random(8))
+    out, amps, oout, ost, _ = run_both(T, wc, tree, 0, prec, np.arange(8), noise_arrays=arr)
+    assert np.max(np.abs(amps - ost)) < TOL[prec]
+    check_outcomes(out, oout, ost, arr[3], DELTA[prec])
+
+
 @pytest.mark.parametrize("prec", ["c64", "c128"])
 def test_tree_levels_ragged_chunks(T, prec):
     rng = np.random.default_rng(7)
