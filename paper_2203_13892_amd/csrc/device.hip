@@ -655,6 +655,41 @@ struct HostMeta;
 static bool same_history(const HostMeta &hm, uint32_t a, uint32_t b);
 static uint64_t history_hash(const HostMeta &hm, uint32_t a);
 
+// History keys of a chunk's computed states: open addressing with linear
+// probing, at most half full (a chunk computes at most `chunk` states).
+// Equal keys may belong to different histories, so a lookup visits every
+// entry with its key.
+struct SeenTable {
+    std::vector<uint64_t> key;
+    std::vector<uint32_t> val;  // computed index; kEmpty marks a free entry
+    uint64_t mask = 0;
+    static constexpr uint32_t kEmpty = 0xFFFFFFFFu;
+    void reset(uint64_t n) {
+        uint64_t cap = 16;
+        while (cap < 2 * n) cap <<= 1;
+        if (key.size() != cap) {
+            key.assign(cap, 0);
+            val.assign(cap, kEmpty);
+        } else {
+            std::fill(val.begin(), val.end(), kEmpty);
+        }
+        mask = cap - 1;
+    }
+    uint64_t home(uint64_t k) const { return (k ^ (k >> 29)) & mask; }
+    template <typename F>
+    int64_t find(uint64_t k, F &&match) const {
+        for (uint64_t i = home(k); val[i] != kEmpty; i = (i + 1) & mask)
+            if (key[i] == k && match(val[i])) return val[i];
+        return -1;
+    }
+    void insert(uint64_t k, uint32_t v) {
+        uint64_t i = home(k);
+        while (val[i] != kEmpty) i = (i + 1) & mask;
+        key[i] = k;
+        val[i] = v;
+    }
+};
+
 // Depth-first chunk walk of the subtrees [first0, last0).  hm == NULL
 // computes every node.
 static void build_schedule(const tqs_plan *p, uint64_t first0, uint64_t last0, std::vector<Task> *tasks,
@@ -670,7 +705,7 @@ static void build_schedule(const tqs_plan *p, uint64_t first0, uint64_t last0, s
     std::vector<Frame_> st;
     st.push_back({0, first0, last0, first0, {}});
     std::vector<uint32_t> slot, rep, cnode, csrc;
-    std::unordered_multimap<uint64_t, uint32_t> seen;  // history key -> computed index
+    SeenTable seen;  // history key -> computed index
     while (!st.empty()) {
         Frame_ &f = st.back();
         const uint32_t l = f.level;
@@ -687,7 +722,7 @@ static void build_schedule(const tqs_plan *p, uint64_t first0, uint64_t last0, s
         rep.clear();
         cnode.clear();
         csrc.clear();
-        seen.clear();
+        if (hm) seen.reset(p->chunk[l]);
         uint64_t c = c0;
         for (; c < c_end; c++) {
             const uint32_t node = (uint32_t)(p->level_offset[l] + c);
@@ -696,18 +731,14 @@ static void build_schedule(const tqs_plan *p, uint64_t first0, uint64_t last0, s
             uint64_t key = 0;
             if (hm) {
                 key = history_hash(*hm, node) * 0x9E3779B97F4A7C15ull + from;
-                auto range = seen.equal_range(key);
-                for (auto it = range.first; it != range.second && hit < 0; ++it) {
-                    const uint32_t j = it->second;
-                    if (csrc[j] == from && same_history(*hm, cnode[j], node)) hit = j;
-                }
+                hit = seen.find(key, [&](uint32_t j) { return csrc[j] == from && same_history(*hm, cnode[j], node); });
             }
             if (hit < 0) {
                 if (cnode.size() == p->chunk[l]) break;
                 hit = (int64_t)cnode.size();
                 cnode.push_back(node);
                 csrc.push_back(from);
-                if (hm) seen.emplace(key, (uint32_t)hit);
+                if (hm) seen.insert(key, (uint32_t)hit);
             }
             rep.push_back((uint32_t)hit);
             slot.push_back(slot_base[l] + (uint32_t)hit);
@@ -815,10 +846,21 @@ static void build_meta(const tqs_plan *p, const tqs_noise *nz, HostMeta *hm) {
                 const uint32_t g = nz->ev_gate[e];
                 ord.push_back({(p->gate_pass[g] << 16) | p->gate_pos[g], e});
             }
-            std::stable_sort(ord.begin(), ord.end(),
-                             [](const std::pair<uint32_t, uint64_t> &a, const std::pair<uint32_t, uint64_t> &b) {
-                                 return a.first < b.first;
-                             });
+            if (ord.size() <= 32) {
+                // a node carries a handful of events: a stable insertion sort
+                // (no scratch allocation per node)
+                for (size_t i = 1; i < ord.size(); i++) {
+                    const std::pair<uint32_t, uint64_t> x = ord[i];
+                    size_t j = i;
+                    for (; j > 0 && ord[j - 1].first > x.first; j--) ord[j] = ord[j - 1];
+                    ord[j] = x;
+                }
+            } else {
+                std::stable_sort(ord.begin(), ord.end(),
+                                 [](const std::pair<uint32_t, uint64_t> &a, const std::pair<uint32_t, uint64_t> &b) {
+                                     return a.first < b.first;
+                                 });
+            }
             for (uint64_t i = 0; i < ord.size(); i++) {
                 const uint64_t e = ord[i].second, o = e0 + i;
                 const uint32_t g = nz->ev_gate[e];
