@@ -470,3 +470,29 @@ def test_host_code_under_address_and_undefined_behaviour_sanitizers(tmp_path):
     r = subprocess.run([exe, "300"], capture_output=True, text=True, timeout=600, env=env)
     assert r.returncode == 0, r.stderr[-2000:]
     assert "cases 300" in r.stdout
+def test_executor_host_steps_under_address_and_undefined_behaviour_sanitizers(tmp_path):
+    # the executor's host side (frames and events per node, the chunk
+    # schedule with shared states and its key table, layout and metadata
+    # packing) on random circuits, trees, tunings and noise, with the
+    # schedule's invariants checked; built by hipcc with the sanitizers on
+    # the host code only (the kernels are compiled but never launched)
+    import subprocess
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    if not os.path.exists(hipcc):
+        pytest.skip("hipcc not available")
+    exe = str(tmp_path / "executor_sanitize")
+    csrc = os.path.join(ROOT, "paper_2203_13892_amd", "csrc")
+    cmd = [hipcc, "--offload-arch=gfx950", "-std=c++17", "-O1", "-g", "-Xarch_device", "-O3", "-Xarch_device", "-g0",
+           "-Xarch_host", "-fsanitize=address,undefined", "-Xarch_host", "-fno-sanitize-recover=undefined",
+           "-fno-omit-frame-pointer", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           "-mllvm", "-simplifycfg-sink-common=false", "-Wno-unused-command-line-argument",
+           "-I", os.path.join(ROOT, "include"), "-I", csrc,
+           os.path.join(ROOT, "tests", "executor_sanitize.hip"), os.path.join(csrc, "plan.cpp"),
+           os.path.join(csrc, "host.cpp"), "-lrocprofiler-sdk-roctx", "-o", exe]
+    subprocess.run(cmd, check=True, capture_output=True, timeout=900)
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=1:verify_asan_link_order=0")
+    r = subprocess.run([exe, "2000"], capture_output=True, text=True, timeout=600, env=env)
+    assert r.returncode == 0, r.stdout[-1000:] + r.stderr[-2000:]
+    assert "cases 2000 runs 4000 fails 0" in r.stdout, r.stdout
+
+
