@@ -1,8 +1,9 @@
 // The executor's host-side steps (per-node frames and events, the chunk
 // schedule with shared states, the workspace layout and the metadata
 // packing) driven on random circuits, trees, tunings and noise under
-// AddressSanitizer and UndefinedBehaviorSanitizer.  Built host-only with
-// hipcc by tests/test_host.py; no HIP call is made and no kernel launched.
+// AddressSanitizer and UndefinedBehaviorSanitizer.  Built with hipcc by
+// tests/test_host.py, the sanitizers on the host code only; no HIP call is
+// made and no kernel launched.
 #include "device.hip"
 
 #include <cstdlib>
