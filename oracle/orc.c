@@ -192,16 +192,17 @@ int orc_readout_fill(uint64_t seed, int levels, const uint64_t *A, const uint64_
  * assignment of the other qubits, gather the 2^a amplitudes, multiply by the
  * matrix, scatter. */
 
-void orc_apply_gate(int n, double *psi_d, int a, const int *q, const double *mat_d) {
+/* The gate on the index range [x0, x1) of the other qubits' assignments. */
+static void apply_gate_range(double *psi_d, int a, const int *q, const double *mat_d,
+                             uint64_t x0, uint64_t x1) {
     cplx *psi = (cplx *)psi_d;
     const cplx *M = (const cplx *)mat_d;
-    uint64_t dim = 1ULL << n;
     int k = 1 << a;
     uint64_t mask = 0;
     for (int j = 0; j < a; j++) mask |= 1ULL << q[j];
     cplx in[4], out[4];
     uint64_t idx[4];
-    for (uint64_t x = 0; x < dim; x++) {
+    for (uint64_t x = x0; x < x1; x++) {
         if (x & mask) continue; /* x enumerates the other qubits */
         for (int l = 0; l < k; l++) {
             uint64_t y = x;
@@ -224,6 +225,53 @@ void orc_apply_gate(int n, double *psi_d, int a, const int *q, const double *mat
     }
 }
 
+void orc_apply_gate(int n, double *psi_d, int a, const int *q, const double *mat_d) {
+    apply_gate_range(psi_d, a, q, mat_d, 0, 1ULL << n);
+}
+
+/* The same gate with the index loop split into `parts` contiguous ranges
+ * run by threads.  Every group of amplitudes is still read, multiplied and
+ * written by the same expression, exactly once, so the result is identical
+ * to orc_apply_gate's; this only lets spare threads help a leaf when there
+ * are fewer leaves than threads. */
+typedef struct {
+    double *psi;
+    int a;
+    const int *q;
+    const double *mat;
+    uint64_t x0, x1;
+} range_t;
+
+static void *range_worker(void *arg) {
+    const range_t *R = (const range_t *)arg;
+    apply_gate_range(R->psi, R->a, R->q, R->mat, R->x0, R->x1);
+    return NULL;
+}
+
+static void apply_gate_split(int n, double *psi, int a, const int *q, const double *mat, int parts) {
+    uint64_t dim = 1ULL << n;
+    if (parts <= 1 || dim < 4096) {
+        apply_gate_range(psi, a, q, mat, 0, dim);
+        return;
+    }
+    if (parts > 64) parts = 64;
+    range_t R[64];
+    pthread_t th[64];
+    int started[64];
+    for (int t = 0; t < parts; t++) {
+        R[t].psi = psi; R[t].a = a; R[t].q = q; R[t].mat = mat;
+        R[t].x0 = dim * (uint64_t)t / (uint64_t)parts;
+        R[t].x1 = dim * (uint64_t)(t + 1) / (uint64_t)parts;
+        started[t] = t > 0 && pthread_create(&th[t], NULL, range_worker, &R[t]) == 0;
+    }
+    /* this thread takes range 0, and any range whose thread did not start */
+    range_worker(&R[0]);
+    for (int t = 1; t < parts; t++)
+        if (!started[t]) range_worker(&R[t]);
+    for (int t = 1; t < parts; t++)
+        if (started[t]) pthread_join(th[t], NULL);
+}
+
 /* The one-qubit Pauli matrices I, X, Y, Z. */
 static const double PAULI[4][8] = {
     {1, 0, 0, 0, 0, 0, 1, 0},
@@ -234,11 +282,15 @@ static const double PAULI[4][8] = {
 
 /* A Pauli noise operator on the gate's qubits, applied as its one-qubit
  * factors (plain matrix products). */
-void orc_apply_pauli(int n, double *psi, int a, const int *q, int code) {
+static void apply_pauli_split(int n, double *psi, int a, const int *q, int code, int parts) {
     for (int j = 0; j < a; j++) {
         int c = (code >> (2 * j)) & 3;
-        if (c) orc_apply_gate(n, psi, 1, &q[j], PAULI[c]);
+        if (c) apply_gate_split(n, psi, 1, &q[j], PAULI[c], parts);
     }
+}
+
+void orc_apply_pauli(int n, double *psi, int a, const int *q, int code) {
+    apply_pauli_split(n, psi, a, q, code, 1);
 }
 
 /* Sec. 2.2: an outcome is sampled from the final state.  Inverse CDF in
@@ -275,6 +327,7 @@ typedef struct {
     uint64_t *outcomes;
     double *states;
     int nthreads, tid;
+    int parts; /* threads per gate application (1 unless leaves < threads) */
 } job_t;
 
 /* One leaf = one full trajectory, computed from scratch (no reuse): the
@@ -290,9 +343,9 @@ static void run_leaf(const job_t *J, uint64_t lam, double *psi) {
         uint64_t e = J->node_off[nu], e1 = J->node_off[nu + 1];
         for (uint64_t g = J->cut[l]; g < J->cut[l + 1]; g++) {
             const int *q = J->qubits + 2 * g;
-            orc_apply_gate(J->n, psi, J->arity[g], q, J->mats + J->mat_off[g]);
+            apply_gate_split(J->n, psi, J->arity[g], q, J->mats + J->mat_off[g], J->parts);
             while (e < e1 && J->ev_gate[e] == g) {
-                orc_apply_pauli(J->n, psi, J->arity[g], q, J->ev_code[e]);
+                apply_pauli_split(J->n, psi, J->arity[g], q, J->ev_code[e], J->parts);
                 e++;
             }
         }
@@ -314,14 +367,19 @@ static void *worker(void *arg) {
     return NULL;
 }
 
-/* Simulate the listed leaves independently (threads over leaves). */
+/* Simulate the listed leaves independently (threads over leaves; with
+ * fewer leaves than threads, the spare threads split each gate's loop). */
 int orc_run_leaves(int n, const int *arity, const int *qubits, const double *mats,
                    const int64_t *mat_off, int levels, const uint64_t *A,
                    const uint64_t *cut, const uint64_t *node_off, const uint32_t *ev_gate,
                    const uint8_t *ev_code, const double *leaf_u, const uint64_t *leaves,
                    uint64_t n_leaves, uint64_t *outcomes, double *states, int nthreads) {
     if (nthreads < 1) nthreads = 1;
-    if ((uint64_t)nthreads > n_leaves) nthreads = n_leaves ? (int)n_leaves : 1;
+    int parts = 1;
+    if ((uint64_t)nthreads > n_leaves) {
+        parts = n_leaves ? nthreads / (int)n_leaves : 1;
+        nthreads = n_leaves ? (int)n_leaves : 1;
+    }
     job_t *jobs = (job_t *)calloc((size_t)nthreads, sizeof(job_t));
     pthread_t *th = (pthread_t *)calloc((size_t)nthreads, sizeof(pthread_t));
     if (!jobs || !th) return -1;
@@ -333,6 +391,7 @@ int orc_run_leaves(int n, const int *arity, const int *qubits, const double *mat
         J->node_off = node_off; J->ev_gate = ev_gate; J->ev_code = ev_code;
         J->leaf_u = leaf_u; J->leaves = leaves; J->n_leaves = n_leaves;
         J->outcomes = outcomes; J->states = states; J->nthreads = nthreads; J->tid = t;
+        J->parts = parts;
         if (pthread_create(&th[t], NULL, worker, J)) {
             rc = -1;
             break;

@@ -366,6 +366,12 @@ tqs_status tqs_noise_import(const tqs_circuit *c, const tqs_tree *tree, const ui
         const uint64_t I = level_nodes(A, l);
         for (uint64_t m = 0; m < I; m++, nu++) {
             if (node_off[nu + 1] < node_off[nu]) return fail(TQS_E_ARG, "node_off not monotone");
+            // before any event of this node is read: its range must lie
+            // inside the list's declared length node_off[nodes]
+            if (node_off[nu + 1] > ne)
+                return fail(TQS_E_ARG, "node_off[%llu] = %llu beyond node_off[%llu] = %llu",
+                            (unsigned long long)(nu + 1), (unsigned long long)node_off[nu + 1],
+                            (unsigned long long)nodes, (unsigned long long)ne);
             int64_t prev = -1;
             for (uint64_t e = node_off[nu]; e < node_off[nu + 1]; e++) {
                 const uint32_t g = ev_gate[e];

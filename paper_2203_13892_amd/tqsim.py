@@ -221,6 +221,21 @@ class Noise:
         eg = np.ascontiguousarray(np.asarray(ev_gate, np.uint32))
         ec = np.ascontiguousarray(np.asarray(ev_code, np.uint8))
         lu = np.ascontiguousarray(np.asarray(leaf_u, np.float64))
+        # the library reads node_off[nodes + 1], node_off[-1] events and one
+        # uniform per leaf: check the lengths before handing pointers over
+        A = [int(a) for a in tree[0]]
+        nodes, leaves, width = 0, 1, 1
+        for a in A:
+            width *= a
+            nodes += width
+        leaves = width
+        if no.ndim != 1 or no.size != nodes + 1:
+            raise ValueError("node_off needs %d entries (nodes + 1), got %d" % (nodes + 1, no.size))
+        ne = int(no[-1])
+        if eg.size < ne or ec.size < ne:
+            raise ValueError("node_off[-1] = %d events, ev_gate has %d and ev_code %d" % (ne, eg.size, ec.size))
+        if lu.size != leaves:
+            raise ValueError("leaf_u needs %d entries (one per leaf), got %d" % (leaves, lu.size))
         if eg.size == 0:
             eg, ec = np.zeros(1, np.uint32), np.zeros(1, np.uint8)
         h = vp()

@@ -119,6 +119,20 @@ int main(int argc, char **argv) {
                     if (tqs_noise_import(c, &tree, off, eg, bad.data(), lu, &nz3) == TQS_OK) return 4;
                     refused++;
                 }
+                if (nn > 1) {
+                    // an offset that overshoots the list's length
+                    // node_off[nodes] while the event arrays hold exactly
+                    // that many: refused before any event is read
+                    std::vector<uint64_t> off2(off, off + nn + 1);
+                    const uint64_t k = 1 + g() % (nn - 1);
+                    off2[k] = off[nn] + 1 + g() % 7;
+                    std::vector<uint32_t> eg2(eg, eg + off[nn]);
+                    std::vector<uint8_t> ec2(ec, ec + off[nn]);
+                    tqs_noise *nz4 = nullptr;
+                    if (tqs_noise_import(c, &tree, off2.data(), eg2.data(), ec2.data(), lu, &nz4) == TQS_OK)
+                        return 5;
+                    refused++;
+                }
                 std::vector<uint32_t> fl(nl, 1u);
                 tqs_noise_set_flips(nz2, fl.data());
                 const uint32_t *fv = nullptr;
