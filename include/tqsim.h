@@ -268,6 +268,17 @@ tqs_status tqs_run_capture(tqs_plan *p, const tqs_noise *nz, void *d_workspace,
                            uint64_t ws_bytes, void *stream, uint64_t *outcomes,
                            const uint64_t *leaves, uint64_t n, double *host_amps);
 
+/* As tqs_run, for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * no workspace argument and no allocation.  The run uses a static device
+ * array of the library, 64 MiB, one per GPU, held until the process ends;
+ * a run that needs more (tqs_workspace_bytes) returns TQS_E_WORKSPACE.  The
+ * stream (or NULL, the null stream) must belong to the current device.  All
+ * calls on one GPU share its array and it keeps the last call's contents:
+ * calls that overlap on one GPU (other threads, other streams) race, so
+ * the caller orders them.  Outcomes as tqs_run; no statistics. */
+tqs_status tqs_run_noalloc(tqs_plan *p, const tqs_noise *nz, void *stream, uint64_t *outcomes);
+
 /* --------------------------------------------------------------- batches
  * Several runs (each a plan with its insertion list; different circuits,
  * qubit counts and trees) advanced together: the k-th launch of every run

@@ -17,6 +17,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <unordered_map>
 #include <vector>
@@ -1485,6 +1486,36 @@ tqs_plan::~tqs_plan() {
     for (void *e : events) hipEventDestroy((hipEvent_t)e);
 }
 
+// ----------------------------------------------- run without allocation --
+// For callers that cannot allocate device memory: the run's workspace is a
+// file-scope device array of kStaticScratchBytes, one copy per GPU, held
+// until the process ends.  Host code never passes the array's name to a
+// kernel or a copy (on the host it is not a device address): each device's
+// address comes from hipGetSymbolAddress, taken once per device on its
+// first call with that device current.
+constexpr uint64_t kStaticScratchBytes = 64ull << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace tqs {
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices] = {nullptr};
+
+// The address of this device's scratch array (set up on first use).
+static tqs_status scratch_address(int dev, void **out) {
+    if (dev < 0 || dev >= kMaxDevices) return fail(TQS_E_ARG, "device %d outside 0..%d", dev, kMaxDevices - 1);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+        if (!ptr || (((uintptr_t)ptr) & 255)) return fail(TQS_E_HIP, "scratch array address not 256-byte aligned");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return TQS_OK;
+}
+}  // namespace tqs
+
 #define TQS_GUARD_BEGIN try {
 #define TQS_GUARD_END                                         \
     }                                                         \
@@ -1577,6 +1608,32 @@ tqs_status tqs_probe_copy(void *d_workspace, uint64_t bytes, uint32_t reps, void
     hipEventDestroy(b);
     *gbps = 2.0 * (double)bytes * reps / (ms * 1e-3) / 1e9;
     return TQS_OK;
+    TQS_GUARD_END
+}
+
+tqs_status tqs_run_noalloc(tqs_plan *p, const tqs_noise *nz, void *stream, uint64_t *outcomes) {
+    TQS_GUARD_BEGIN
+    if (!p) return fail(TQS_E_ARG, "plan is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    int cur = -1;
+    HIP_TRY(hipGetDevice(&cur), "hipGetDevice");
+    if (s) {
+        int sdev = -1;
+        HIP_TRY(hipStreamGetDevice(s, &sdev), "hipStreamGetDevice");
+        if (sdev != cur) return fail(TQS_E_ARG, "the stream's device %d is not the current device %d", sdev, cur);
+    }
+    uint64_t need = 0;
+    tqs_status st = tqs_workspace_bytes(p, nz, &need);
+    if (st) return st;
+    if (need > kStaticScratchBytes)
+        return fail(TQS_E_WORKSPACE,
+                    "the run needs %llu bytes of device memory, more than the library's static scratch "
+                    "of %llu bytes (use tqs_run with a workspace)",
+                    (unsigned long long)need, (unsigned long long)kStaticScratchBytes);
+    void *ws = nullptr;
+    st = scratch_address(cur, &ws);
+    if (st) return st;
+    return run_any(p, nz, ws, kStaticScratchBytes, stream, 0, p->arity[0], outcomes, nullptr, Capture());
     TQS_GUARD_END
 }
 

@@ -64,6 +64,7 @@ SIGNATURES = {
     "tqs_run": (i32, [vp, vp, vp, u64, vp, P(u64), P(TqsRunStats)]),
     "tqs_run_range": (i32, [vp, vp, vp, u64, vp, u64, u64, P(u64), P(TqsRunStats)]),
     "tqs_run_capture": (i32, [vp, vp, vp, u64, vp, P(u64), P(u64), u64, P(dbl)]),
+    "tqs_run_noalloc": (i32, [vp, vp, vp, P(u64)]),
     "tqs_histogram": (i32, [P(u64), u64, P(u64), P(u64), P(u64)]),
     "tqs_probe_copy": (i32, [vp, u64, u32, vp, P(dbl)]),
     "tqs_plan_describe": (i32, [vp, C.c_char_p, u64, P(u64)]),
@@ -365,6 +366,14 @@ def run(plan: Plan, noise: Noise, workspace: Workspace = None, stream=None, stat
                                  first, last, _ptr(out, u64),
                                  C.byref(st) if st is not None else None))
     return (out, st.as_dict()) if stats else out
+
+
+def run_noalloc(plan: Plan, noise: Noise, stream=None):
+    """As ``run``, in the library's static device scratch (64 MiB per GPU):
+    no workspace is allocated (tqs_run_noalloc)."""
+    out = np.zeros(plan.n_leaves, np.uint64)
+    _check(lib.tqs_run_noalloc(plan.h, noise.h, _stream(stream), _ptr(out, u64)))
+    return out
 
 
 def run_capture(plan: Plan, noise: Noise, leaves, workspace: Workspace = None, stream=None):
