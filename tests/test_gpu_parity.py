@@ -24,6 +24,15 @@ pytestmark = pytest.mark.gpu
 
 TOL = {"c64": 1e-5, "c128": 1e-12}
 DELTA = {"c64": 1e-6, "c128": 1e-12}
+U = {"c64": 2.0 ** -24, "c128": 2.0 ** -53}
+
+
+def rel_bound(prec, gates):
+    """Relative 2-norm bound on a trajectory after `gates` unitary steps:
+    rounding errors of unit roundoff u add up like a random walk, about
+    u sqrt(G) in the 2-norm (measured: 0.45-1.25 u sqrt(G) at 20-26 qubits
+    in both precisions); three times that is the bound."""
+    return 3.0 * U[prec] * math.sqrt(gates)
 
 
 @pytest.fixture(scope="module")
@@ -178,7 +187,7 @@ def test_c1_qft10_per_shot_c128_all_leaves(T):
     leaves = np.arange(1000)
     out, amps, oout, ost, onz = run_both(T, wc, tree, 0, "c128", leaves)
     assert np.max(np.abs(amps - ost)) < 1e-12
-    assert rel_l2(amps, ost) < 1e-12
+    assert rel_l2(amps, ost) < rel_bound("c128", len(wc))
     nb = check_outcomes(out, oout, ost, onz.leaf_u, DELTA["c128"])
     assert nb <= 2
 
@@ -244,8 +253,9 @@ def _c2_case(family):
 # every leaf of level-0 subtree 0 (its 1024 leaves: 32 sibling groups whose
 # ancestors are shared, spanning state chunks) in four parts, then 64 random
 # leaves of the other subtrees.  Each leaf's amplitudes agree to 1e-5
-# max-abs and 1e-6 in relative 2-norm; outcomes are identical except at
-# valid boundary picks, at most 2 + 1% of the leaves.
+# max-abs and to 3 u sqrt(G) in relative 2-norm (2.7e-6 for the 220-gate
+# QFT, 2.5e-6 for the 190-gate brick-wall); outcomes are identical except
+# at valid boundary picks, at most 2 + 1% of the leaves.
 C2_PARTS = [("sub0", k) for k in range(4)] + [("random", 0)]
 
 
@@ -263,7 +273,7 @@ def test_c2_20q_tree_leaves(T, family, part):
     nb = check_outcomes(out[leaves], oout, ost, onz.leaf_u[leaves], DELTA["c64"])
     print(family, part, "max-abs %.3g rel-l2 %.3g boundary leaves %d" % (err, rel, nb))
     assert err < 1e-5
-    assert rel < 1e-6
+    assert rel < rel_bound("c64", len(wc))
 
 
 def test_range_runs_equal_full_run(T):
@@ -471,7 +481,7 @@ def test_c4_precision_brickwall_26q(T, c4_26q, prec):
     nb = check_outcomes(out[li], oout, ost, onz.leaf_u[li], DELTA[prec])
     print(prec, "26q max-abs %.3g rel-l2 %.3g boundary leaves %d" % (err, rel, nb))
     assert err < TOL[prec]
-    assert rel < {"c64": 1e-5, "c128": 1e-12}[prec]
+    assert rel < rel_bound(prec, len(wc))
 
 
 def test_perceptron_kernels_against_oracle(T):
@@ -798,7 +808,7 @@ def test_c2_20q_tree_sampled_leaves_c128(T):
     leaves = np.array([0, 1, 5000, 16383])
     out, amps, oout, ost, onz = run_both(T, wc, tree, 0, "c128", leaves)
     assert np.max(np.abs(amps - ost)) < 1e-12
-    assert rel_l2(amps, ost) < 1e-12
+    assert rel_l2(amps, ost) < rel_bound("c128", len(wc))
     check_outcomes(out[leaves], oout, ost, onz.leaf_u[leaves], DELTA["c128"])
 
 
