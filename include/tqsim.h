@@ -105,6 +105,11 @@ typedef struct {
     uint32_t separate_sampling; /* 1: sampling reads the final states in kernels of its own.
                                   Default 0: the last pass of the leaf level also writes
                                   the FP64 sampling partial sums when its tile allows */
+    uint32_t jit;              /* pass kernels specialised to the plan (its ops fixed at compile
+                                  time, compiled with hipRTC on the plan's first run and kept
+                                  with the plan): 1 on, 2 off.  Default 0: on for states of
+                                  2^16 amplitudes or more.  Same results either way; nodes a
+                                  specialised kernel does not take run in the generic one */
 } tqs_tuning;
 
 /* Timing and traffic of one run. */
@@ -121,6 +126,8 @@ typedef struct {
     uint64_t bytes_sample;     /* algorithmic HBM bytes of sampling */
     uint64_t events;           /* noise events in the insertion list */
     uint64_t nodes_merged;     /* nodes whose state is an identical earlier node's */
+    uint64_t jit_launches;     /* pass launches of plan-specialised kernels */
+    uint64_t jit_states;       /* states those launches processed */
 } tqs_run_stats;
 
 /* ---------------------------------------------------------------- circuit */
@@ -240,6 +247,17 @@ tqs_status tqs_workspace_bytes(const tqs_plan *p, const tqs_noise *nz, uint64_t 
  * slot ranges end at s and begin at s.  A dense op with no circuit gate in
  * its slot is a lane exchange (a swap of two positions). */
 tqs_status tqs_plan_describe(const tqs_plan *p, char *buf, uint64_t cap, uint64_t *len);
+
+/* Compile the plan's specialised pass kernels now (tuning.jit; a no-op when
+ * they are off).  Runs otherwise compile them on the plan's first run.  No
+ * device is needed; the code is kept with the plan (and shared by identical
+ * plans in the process).  TQS_E_HIP with the compiler's log on failure. */
+tqs_status tqs_plan_compile(tqs_plan *p);
+
+/* The HIP source of the plan's specialised pass kernels (for tests and
+ * inspection): *len gets the size with the terminating NUL; buf may be
+ * NULL; output is truncated to cap. */
+tqs_status tqs_plan_jit_source(const tqs_plan *p, char *buf, uint64_t cap, uint64_t *len);
 
 void tqs_plan_destroy(tqs_plan *p);
 

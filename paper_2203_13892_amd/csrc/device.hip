@@ -23,70 +23,6 @@
 #include <vector>
 
 #include "tqs_internal.h"
-
-namespace tqs {
-
-constexpr uint32_t kInit = 0xFFFFFFFFu;  // src slot: start from |0..0>
-
-template <typename R>
-struct alignas(2 * sizeof(R)) cplx {
-    R re, im;
-};
-
-template <typename R>
-__device__ __forceinline__ cplx<R> cmul(cplx<R> a, cplx<R> b) {
-    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
-}
-
-// acc + a b as four fused multiply-adds (each product term accumulates
-// directly; no separate product and add)
-template <typename R>
-__device__ __forceinline__ cplx<R> cmac(cplx<R> acc, cplx<R> a, cplx<R> b) {
-    acc.re = acc.re + a.re * b.re;
-    acc.re = acc.re - a.im * b.im;
-    acc.im = acc.im + a.re * b.im;
-    acc.im = acc.im + a.im * b.re;
-    return acc;
-}
-
-template <typename R>
-__device__ __forceinline__ cplx<R> cneg_if(cplx<R> a, uint32_t neg) {
-    // sign flip as an integer xor, so uniform values stay in scalar registers
-    if constexpr (sizeof(R) == 4) {
-        const uint32_t m = neg ? 0x80000000u : 0u;
-        return {__uint_as_float(__float_as_uint(a.re) ^ m), __uint_as_float(__float_as_uint(a.im) ^ m)};
-    } else {
-        const unsigned long long m = neg ? 0x8000000000000000ull : 0ull;
-        return {__longlong_as_double((long long)((unsigned long long)__double_as_longlong(a.re) ^ m)),
-                __longlong_as_double((long long)((unsigned long long)__double_as_longlong(a.im) ^ m))};
-    }
-}
-
-// Negates the real and/or imaginary part (integer sign flips).
-template <typename R>
-__device__ __forceinline__ cplx<R> cneg_parts(cplx<R> a, uint32_t neg_re, uint32_t neg_im) {
-    if constexpr (sizeof(R) == 4) {
-        return {__uint_as_float(__float_as_uint(a.re) ^ (neg_re << 31)),
-                __uint_as_float(__float_as_uint(a.im) ^ (neg_im << 31))};
-    } else {
-        return {__longlong_as_double((long long)((unsigned long long)__double_as_longlong(a.re) ^
-                                                 ((unsigned long long)neg_re << 63))),
-                __longlong_as_double((long long)((unsigned long long)__double_as_longlong(a.im) ^
-                                                 ((unsigned long long)neg_im << 63)))};
-    }
-}
-
-// Per-node noise metadata in device memory.
-struct NodeMeta {
-    const uint32_t *frame0;  // [2 * node]: x, z at node start
-    const uint32_t *ev_off;  // [node + 1]
-    const uint32_t *ev_pos;  // (pass << 16) | position of the first op that sees it
-    const uint32_t *ev_dx;
-    const uint32_t *ev_dz;
-};
-
-}  // namespace tqs
-
 #include "pass_kernel.h"
 
 namespace tqs {
@@ -904,6 +840,7 @@ static PassArgs<R> pass_args(const tqs_plan *p, const Layout &Ly, unsigned char 
     a.node_ids = sched + t.cnode();
     a.src_slot = sched + (first ? t.csrc() : t.cdst());
     a.dst_slot = sched + t.cdst();
+    a.perm = nullptr;
     a.count = t.ccount;
     a.work = t.ccount * (1u << pd.nfree);
     a.pass_key = pass_idx << 16;
@@ -953,6 +890,100 @@ static void launch_pass_kernel(uint32_t reg_bits, bool d2, const PassLaunch<R> &
         }
     }
 #undef TQS_LAUNCH
+}
+
+// Which kernel takes each computed state of a chunk task's pass: the
+// plan-specialised kernel (when the plan has one for the pass) takes the
+// states it supports, the generic kernel the rest.  perm: offset in the
+// schedule of the task's computed-state indices, specialised ones first
+// (kNoPerm: all states go to one kernel, in order).
+struct Route {
+    static constexpr uint64_t kNoPerm = ~0ull;
+    uint64_t perm = kNoPerm;
+    uint32_t n_jit = 0;  // states for the specialised kernel
+};
+
+// Routes of every (task, pass of its level), appending index lists to sched.
+static void route_passes(const tqs_plan *p, const HostMeta &hm, const std::vector<Task> &tasks,
+                         std::vector<uint32_t> *sched, std::vector<std::vector<Route>> *routes) {
+    routes->assign(tasks.size(), {});
+    if (p->tune.jit != 1) return;
+    std::vector<std::vector<JitRun>> runs;
+    jit_runs(p, &runs);
+    std::vector<uint32_t> yes, no;
+    for (size_t ti = 0; ti < tasks.size(); ti++) {
+        const Task &t = tasks[ti];
+        const tqs::Level &lv = p->levels[t.level];
+        (*routes)[ti].assign(lv.pass_count, Route());
+        for (uint32_t k = 0; k < lv.pass_count; k++) {
+            const uint32_t pi = lv.pass_begin + k;
+            Route &r = (*routes)[ti][k];
+            if (!jit_pass_supported(p, pi)) continue;
+            yes.clear();
+            no.clear();
+            for (uint32_t c = 0; c < t.ccount; c++) {
+                const uint32_t node = (*sched)[t.cnode() + c];
+                const uint32_t e0 = hm.ev_off[node], e1 = hm.ev_off[node + 1];
+                if (jit_eligible(runs[pi], pi, hm.ev_pos.data() + e0, hm.ev_dx.data() + e0, e1 - e0)) yes.push_back(c);
+                else no.push_back(c);
+            }
+            r.n_jit = (uint32_t)yes.size();
+            if (no.empty() || yes.empty()) continue;
+            r.perm = sched->size();
+            sched->insert(sched->end(), yes.begin(), yes.end());
+            sched->insert(sched->end(), no.begin(), no.end());
+        }
+    }
+}
+
+// Schedule entries route_passes may append at most.
+static uint64_t route_bound(const tqs_plan *p) {
+    uint64_t b = 0;
+    if (p->tune.jit == 1)
+        for (size_t l = 0; l < p->levels.size(); l++) b += p->level_nodes[l] * (uint64_t)p->levels[l].pass_count;
+    return b;
+}
+
+template <typename R>
+static hipError_t launch_jit(const tqs_plan *p, uint32_t pass_idx, PassLaunch<R> &pl, hipStream_t s) {
+    const uint32_t grid = (pl.total + 7u) & ~7u;
+    void *args[] = {&pl};
+    return hipModuleLaunchKernel((hipFunction_t)p->jit_fn[pass_idx], grid, 1, 1, 64, 1, 1, 0, s, args, nullptr);
+}
+
+// One pass over a task's computed states, split between the kernels as
+// routed.  Returns the states the specialised kernel took.
+template <typename R>
+static uint32_t launch_routed(const tqs_plan *p, const Layout &Ly, unsigned char *ws, hipStream_t s,
+                              const Task &t, uint32_t pass_idx, bool first, const Route &r,
+                              uint32_t *launches, hipError_t *err) {
+    const bool have_jit = p->tune.jit == 1 && pass_idx < p->jit_fn.size() && p->jit_fn[pass_idx];
+    const uint32_t n_jit = have_jit ? r.n_jit : 0u;
+    PassLaunch<R> pl;
+    std::memset(&pl, 0, sizeof pl);
+    pl.one = pass_args<R>(p, Ly, ws, t, pass_idx, first);
+    pl.nseg = 0;
+    const uint32_t tiles = 1u << p->passes[pass_idx].nfree;
+    const uint32_t *sched = reinterpret_cast<const uint32_t *>(ws + Ly.off_sched);
+    *launches = 0;
+    if (n_jit) {
+        PassLaunch<R> pj = pl;
+        if (r.perm != Route::kNoPerm) pj.one.perm = sched + r.perm;
+        pj.one.count = n_jit;
+        pj.one.work = n_jit * tiles;
+        pj.total = pj.one.work;
+        *err = launch_jit<R>(p, pass_idx, pj, s);
+        (*launches)++;
+    }
+    if (n_jit < t.ccount) {
+        if (n_jit) pl.one.perm = sched + r.perm + n_jit;
+        pl.one.count = t.ccount - n_jit;
+        pl.one.work = pl.one.count * tiles;
+        pl.total = pl.one.work;
+        launch_pass_kernel<R>(p->reg_bits, p->passes[pass_idx].has_d2 != 0, pl, s);
+        (*launches)++;
+    }
+    return n_jit;
 }
 
 template <typename R>
@@ -1143,6 +1174,13 @@ static tqs_status run_t(tqs_plan *p, const tqs_noise *nz, unsigned char *ws, uin
     std::vector<uint32_t> sched;
     Layout Ly0 = make_layout(p, nz->ev_gate.size(), n_out, 0);
     build_schedule(p, first, last, &tasks, &sched, Ly0.slot_base, p->tune.no_merge ? nullptr : &hm);
+    if (p->tune.jit == 1) {
+        // the plan's specialised kernels, compiled on its first run
+        const tqs_status js = jit_prepare(p);
+        if (js) return js;
+    }
+    std::vector<std::vector<Route>> routes;
+    route_passes(p, hm, tasks, &sched, &routes);
     Layout Ly = make_layout(p, nz->ev_gate.size(), n_out, sched.size());
     if (ws_bytes < Ly.total)
         return fail(TQS_E_WORKSPACE, "workspace has %llu bytes, the run needs %llu",
@@ -1170,6 +1208,7 @@ static tqs_status run_t(tqs_plan *p, const tqs_noise *nz, unsigned char *ws, uin
     }
 
     uint64_t launches = 0, pass_launches = 0, pass_states = 0, bytes_passes = 0, bytes_sample = 0, merged = 0;
+    uint64_t jit_launches = 0, jit_states = 0;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pass_ev, samp_ev;
     const uint64_t state_bytes = Ly.state_bytes;
     const uint32_t b = p->sample_b;
@@ -1188,9 +1227,17 @@ static tqs_status run_t(tqs_plan *p, const tqs_noise *nz, unsigned char *ws, uin
             HIP_TRY(hipEventRecord(ea, s), "hipEventRecord");
         }
         for (uint32_t k = 0; k < lv.pass_count; k++) {
-            launch_pass<R>(p, Ly, ws, s, t, lv.pass_begin + k, k == 0);
-            launches++;
-            pass_launches++;
+            uint32_t nl = 0;
+            hipError_t le = hipSuccess;
+            const uint32_t nj = launch_routed<R>(p, Ly, ws, s, t, lv.pass_begin + k, k == 0,
+                                                 routes[&t - tasks.data()][k], &nl, &le);
+            HIP_TRY(le, "specialised pass kernel launch");
+            launches += nl;
+            pass_launches += nl;
+            if (nj) {
+                jit_launches++;
+                jit_states += nj;
+            }
             pass_states += t.ccount;
             const bool init = (k == 0 && t.level == 0);
             bytes_passes += (uint64_t)t.ccount * state_bytes * (init ? 1 : 2);
@@ -1272,6 +1319,8 @@ static tqs_status run_t(tqs_plan *p, const tqs_noise *nz, unsigned char *ws, uin
         stats->bytes_sample = bytes_sample;
         stats->events = nz->ev_gate.size();
         stats->nodes_merged = merged;
+        stats->jit_launches = jit_launches;
+        stats->jit_states = jit_states;
         stats->ms_wall =
             std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }
@@ -1484,6 +1533,7 @@ using namespace tqs;
 
 tqs_plan::~tqs_plan() {
     for (void *e : events) hipEventDestroy((hipEvent_t)e);
+    jit_release(this);
 }
 
 // ----------------------------------------------- run without allocation --
@@ -1541,12 +1591,14 @@ tqs_status tqs_workspace_bytes(const tqs_plan *p, const tqs_noise *nz, uint64_t 
         std::vector<uint32_t> sched;
         Layout Ly0 = make_layout(p, nz->ev_gate.size(), p->n_leaves, 0);
         build_schedule(p, 0, p->arity[0], &tasks, &sched, Ly0.slot_base, p->tune.no_merge ? nullptr : &hm);
+        std::vector<std::vector<Route>> routes;
+        route_passes(p, hm, tasks, &sched, &routes);
         *bytes = make_layout(p, nz->ev_gate.size(), p->n_leaves, sched.size()).total;
         return TQS_OK;
     }
     uint64_t ev = 0;
     for (size_t l = 0; l < p->arity.size(); l++) ev += p->level_nodes[l] * (uint64_t)(p->cut[l + 1] - p->cut[l]);
-    Layout Ly = make_layout(p, ev, p->n_leaves, 6 * p->n_nodes);
+    Layout Ly = make_layout(p, ev, p->n_leaves, 6 * p->n_nodes + route_bound(p));
     *bytes = Ly.total;
     return TQS_OK;
     TQS_GUARD_END

@@ -1,0 +1,348 @@
+// Building blocks of plan-specialised pass kernels, compiled at run time
+// (hipRTC) from source the planner writes for each pass of a plan.
+//
+// The tile is the one of pass_kernel.h: one wave per workgroup, one tile of
+// one trajectory, lane L holding the amplitudes whose low physical qubits
+// spell L and register index j spelling the register qubits.  Here every
+// op's kind, qubit roles and positions, and every phase term's qubits and
+// phases are compile-time constants, so a pass is straight-line code: no
+// per-op descriptor reads or dispatch, and the tile stays in the same
+// registers from op to op.  Only the trajectory's Pauli frame and noise
+// events are read at run time (wave-uniform, scalar unit).
+//
+// Phase runs: each term's phases are re-indexed by its frame bits and
+// split into the multilinear coefficients of its two index bits,
+//   th(y_u, y_w) = a + b x_u + g x_w + d x_u x_w   (x: stored index bits),
+// accumulated per run on the scalar unit into a constant, per-lane-bit and
+// lane-pair coefficients, and per-register-bit coefficients; each lane then
+// evaluates its phase from its own bits.  Gates on register qubits only
+// form the run's table T (host side), read at index j ^ (frame's register
+// bits) when they all see one frame; nodes whose frame changes between
+// them take the generic pass kernel instead (the executor routes them).
+#pragma once
+
+#include "tile_common.h"
+
+namespace tqs {
+namespace jit {
+
+constexpr int kNone = 3;  // no control qubit (one-qubit gate)
+
+// Wave state: tile origin, the trajectory's Pauli frame and the cursor over
+// its node's noise events (keys (pass << 16) | gate slot).
+struct Wave {
+    uint32_t L, base;
+    uint32_t fx, fz;
+    uint32_t e, e1, nxt;
+    kptr<uint32_t> pos, dx, dz;
+};
+
+// Apply the events up to key (those acting before the op at this slot).
+__device__ __forceinline__ void advance(Wave &w, uint32_t key) {
+    while (w.nxt <= key) {
+        w.fx ^= uni(w.dx[w.e]);
+        w.fz ^= uni(w.dz[w.e]);
+        w.e++;
+        w.nxt = w.e < w.e1 ? uni(w.pos[w.e]) : 0xFFFFFFFFu;
+    }
+}
+
+// Frame bits of one or two qubits as a local index (bit 0: first qubit).
+__device__ __forceinline__ uint32_t local2(uint32_t f, uint32_t p0, uint32_t p1, uint32_t nq) {
+    uint32_t x = (f >> p0) & 1u;
+    if (nq == 2) x |= ((f >> p1) & 1u) << 1;
+    return x;
+}
+
+// Value of the lane whose index differs in the bits of M: quad permutes
+// for masks below 4, the 32-lane swizzle below 32, a permute otherwise.
+template <int M>
+__device__ __forceinline__ int lane_xor_i(int i) {
+    static_assert(M > 0 && M < 64, "lane mask");
+    // (quad permutes read a valid lane everywhere: bound_ctrl, no old value)
+    if constexpr (M == 1) return __builtin_amdgcn_mov_dpp(i, 0xB1, 0xF, 0xF, true);
+    else if constexpr (M == 2) return __builtin_amdgcn_mov_dpp(i, 0x4E, 0xF, 0xF, true);
+    else if constexpr (M == 3) return __builtin_amdgcn_mov_dpp(i, 0x1B, 0xF, 0xF, true);
+    else if constexpr (M < 32) return __builtin_amdgcn_ds_swizzle(i, (M << 10) | 0x1F);
+    else return __builtin_amdgcn_ds_bpermute((int)(((uint32_t)__lane_id() ^ (uint32_t)M) << 2), i);
+}
+template <int M>
+__device__ __forceinline__ float lane_xor(float x) {
+    return __int_as_float(lane_xor_i<M>(__float_as_int(x)));
+}
+template <int M>
+__device__ __forceinline__ double lane_xor(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = lane_xor_i<M>((int)(b & 0xFFFFFFFFll)), hi = lane_xor_i<M>((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (long long)(uint32_t)lo);
+}
+template <int M, typename R>
+__device__ __forceinline__ cplx<R> lane_xor_c(cplx<R> v) {
+    return {lane_xor<M>(v.re), lane_xor<M>(v.im)};
+}
+
+// Keeps an updated amplitude's arithmetic where it is written: without it
+// the multiply-adds can sink past later cross-lane reads, which then all
+// hold their results at once (register spills).  No instruction is emitted.
+template <typename R>
+__device__ __forceinline__ void pin(cplx<R> &v) {
+    asm volatile("" : "+v"(v.re), "+v"(v.im));
+}
+
+// ------------------------------------------------------------ dense 2x2 --
+// A 2x2 gate on qubit TPOS (lane bit or register bit), or a two-qubit gate
+// block-diagonal in its control qubit (role CROLE at CPOS; kNone for a
+// one-qubit gate).  TQ: which of the gate's two qubits is the target.
+template <typename R, int RB, bool REAL, int TROLE, int TPOS, int CROLE, int CPOS, int NQ, int TQ>
+__device__ __forceinline__ void d1(cplx<R> (&v)[1 << RB], kptr<cplx<R>> G, uint32_t xl, uint32_t zl,
+                                   const Wave &w) {
+    constexpr int NJ = 1 << RB;
+    constexpr uint32_t K = 1u << NQ, CQ = 1u - (uint32_t)TQ;
+    cplx<R> B[2][4];
+#pragma unroll
+    for (uint32_t cb = 0; cb < 2; cb++)
+#pragma unroll
+        for (uint32_t rr = 0; rr < 2; rr++)
+#pragma unroll
+            for (uint32_t cc = 0; cc < 2; cc++) {
+                uint32_t r = rr << TQ, c = cc << TQ;
+                if constexpr (NQ == 2) {
+                    r |= cb << CQ;
+                    c |= cb << CQ;
+                }
+                B[cb][rr * 2 + cc] = conj_entry(G, K, r, c, xl, zl);
+            }
+    if constexpr (TROLE == ROLE_REG) {
+        if constexpr (CROLE == ROLE_REG) {
+            sfor<NJ>([&](auto Jc) __attribute__((always_inline)) {
+                constexpr int j = decltype(Jc)::value;
+                if constexpr (!(j & (1 << TPOS))) {
+                    constexpr int cb = (j >> CPOS) & 1;
+                    const cplx<R> x0 = v[j], x1 = v[j | (1 << TPOS)];
+                    v[j] = mmac<REAL>(mmul<REAL>(B[cb][0], x0), B[cb][1], x1);
+                    v[j | (1 << TPOS)] = mmac<REAL>(mmul<REAL>(B[cb][2], x0), B[cb][3], x1);
+                }
+            });
+        } else {
+            cplx<R> M[4];
+            if constexpr (CROLE == ROLE_LANE) {
+                const bool cb = ((w.L >> CPOS) & 1u) != 0;
+#pragma unroll
+                for (int e = 0; e < 4; e++) M[e] = csel(cb, B[1][e], B[0][e]);
+            } else if constexpr (CROLE == ROLE_FIXED) {
+                const bool cb = ((w.base >> CPOS) & 1u) != 0;
+#pragma unroll
+                for (int e = 0; e < 4; e++) M[e] = csel(cb, B[1][e], B[0][e]);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; e++) M[e] = B[0][e];
+            }
+            sfor<NJ>([&](auto Jc) __attribute__((always_inline)) {
+                constexpr int j = decltype(Jc)::value;
+                if constexpr (!(j & (1 << TPOS))) {
+                    const cplx<R> x0 = v[j], x1 = v[j | (1 << TPOS)];
+                    v[j] = mmac<REAL>(mmul<REAL>(M[0], x0), M[1], x1);
+                    v[j | (1 << TPOS)] = mmac<REAL>(mmul<REAL>(M[2], x0), M[3], x1);
+                }
+            });
+        }
+    } else {
+        // lane target: own row b, partner (lane ^ 2^TPOS) in column 1 - b
+        const bool b = ((w.L >> TPOS) & 1u) != 0;
+        if constexpr (CROLE == ROLE_REG) {
+            const cplx<R> a0 = csel(b, B[0][3], B[0][0]), c0 = csel(b, B[0][2], B[0][1]);
+            const cplx<R> a1 = csel(b, B[1][3], B[1][0]), c1 = csel(b, B[1][2], B[1][1]);
+            sfor<NJ>([&](auto Jc) __attribute__((always_inline)) {
+                constexpr int j = decltype(Jc)::value;
+                constexpr int cb = (j >> CPOS) & 1;
+                const cplx<R> p = lane_xor_c<1 << TPOS>(v[j]);
+                v[j] = mmac<REAL>(mmul<REAL>(cb ? a1 : a0, v[j]), cb ? c1 : c0, p);
+                pin(v[j]);
+                shuffle_fence<j>();
+            });
+        } else {
+            bool cb = false;
+            if constexpr (CROLE == ROLE_LANE) cb = ((w.L >> CPOS) & 1u) != 0;
+            else if constexpr (CROLE == ROLE_FIXED) cb = ((w.base >> CPOS) & 1u) != 0;
+            const cplx<R> a = csel(b, csel(cb, B[1][3], B[0][3]), csel(cb, B[1][0], B[0][0]));
+            const cplx<R> c = csel(b, csel(cb, B[1][2], B[0][2]), csel(cb, B[1][1], B[0][1]));
+            sfor<NJ>([&](auto Jc) __attribute__((always_inline)) {
+                constexpr int j = decltype(Jc)::value;
+                const cplx<R> p = lane_xor_c<1 << TPOS>(v[j]);
+                v[j] = mmac<REAL>(mmul<REAL>(a, v[j]), c, p);
+                pin(v[j]);
+                shuffle_fence<j>();
+            });
+        }
+    }
+}
+
+// ------------------------------------------------------------ dense 4x4 --
+// A two-qubit gate on qubits (P0, P1) in normalised order: the first is a
+// register qubit whenever one of them is, and register pairs have P0 < P1.
+// SW: the gate's own qubit order is the reverse of the normalised one.
+template <typename R, int RB, bool SW, bool REG0, bool REG1, int P0, int P1>
+__device__ __forceinline__ void d2(cplx<R> (&v)[1 << RB], kptr<cplx<R>> G, uint32_t xl, uint32_t zl,
+                                   const Wave &w) {
+    constexpr int NJ = 1 << RB;
+    cplx<R> M[16];
+#pragma unroll
+    for (uint32_t r = 0; r < 4; r++)
+#pragma unroll
+        for (uint32_t c = 0; c < 4; c++) {
+            const uint32_t rs = SW ? ((r >> 1) | ((r & 1u) << 1)) : r;
+            const uint32_t cs = SW ? ((c >> 1) | ((c & 1u) << 1)) : c;
+            M[r * 4 + c] = conj_entry(G, 4, rs, cs, xl, zl);
+        }
+    if constexpr (REG0 && REG1) {
+        static_assert(P0 < P1, "normalised register pair");
+        sfor<NJ>([&](auto Jc) __attribute__((always_inline)) {
+            constexpr int j = decltype(Jc)::value;
+            if constexpr (!(j & ((1 << P0) | (1 << P1)))) {
+                constexpr int i0 = j, i1 = j | (1 << P0), i2 = j | (1 << P1), i3 = j | (1 << P0) | (1 << P1);
+                const cplx<R> x0 = v[i0], x1 = v[i1], x2 = v[i2], x3 = v[i3];
+                v[i0] = cmac(cmac(cmac(cmul(M[0], x0), M[1], x1), M[2], x2), M[3], x3);
+                v[i1] = cmac(cmac(cmac(cmul(M[4], x0), M[5], x1), M[6], x2), M[7], x3);
+                v[i2] = cmac(cmac(cmac(cmul(M[8], x0), M[9], x1), M[10], x2), M[11], x3);
+                v[i3] = cmac(cmac(cmac(cmul(M[12], x0), M[13], x1), M[14], x2), M[15], x3);
+            }
+            shuffle_fence<j>();
+        });
+    } else if constexpr (REG0) {
+        // register bit P0, lane bit P1: own rows 2b, 2b+1; partner columns
+        const bool b = ((w.L >> P1) & 1u) != 0;
+        cplx<R> k0[4], k1[4];
+#pragma unroll
+        for (uint32_t cc = 0; cc < 4; cc++) {
+            // (own a0, own a1, partner q0, partner q1) are columns cc for
+            // b = 0 and cc ^ 2 for b = 1
+            k0[cc] = csel(b, M[2 * 4 + (cc ^ 2u)], M[0 * 4 + cc]);
+            k1[cc] = csel(b, M[3 * 4 + (cc ^ 2u)], M[1 * 4 + cc]);
+        }
+        sfor<NJ>([&](auto Jc) __attribute__((always_inline)) {
+            constexpr int j = decltype(Jc)::value;
+            if constexpr (!(j & (1 << P0))) {
+                const cplx<R> a0 = v[j], a1 = v[j | (1 << P0)];
+                const cplx<R> q0 = lane_xor_c<1 << P1>(a0), q1 = lane_xor_c<1 << P1>(a1);
+                v[j] = cmac(cmac(cmac(cmul(k0[0], a0), k0[1], a1), k0[2], q0), k0[3], q1);
+                v[j | (1 << P0)] = cmac(cmac(cmac(cmul(k1[0], a0), k1[1], a1), k1[2], q0), k1[3], q1);
+                pin(v[j]);
+                pin(v[j | (1 << P0)]);
+            }
+            shuffle_fence<j>();
+        });
+    } else {
+        // both on lanes: own index r = b0 + 2 b1, partners r ^ 1, r ^ 2, r ^ 3
+        const uint32_t r = ((w.L >> P0) & 1u) | (((w.L >> P1) & 1u) << 1);
+        cplx<R> k[4];
+#pragma unroll
+        for (uint32_t d = 0; d < 4; d++) {
+            const cplx<R> e0 = M[0 * 4 + (0 ^ d)], e1 = M[1 * 4 + (1 ^ d)];
+            const cplx<R> e2 = M[2 * 4 + (2 ^ d)], e3 = M[3 * 4 + (3 ^ d)];
+            k[d] = csel(r == 3, e3, csel(r == 2, e2, csel(r == 1, e1, e0)));
+        }
+        sfor<NJ>([&](auto Jc) __attribute__((always_inline)) {
+            constexpr int j = decltype(Jc)::value;
+            const cplx<R> q1 = lane_xor_c<1 << P0>(v[j]);
+            const cplx<R> q2 = lane_xor_c<1 << P1>(v[j]);
+            const cplx<R> q3 = lane_xor_c<(1 << P0) | (1 << P1)>(v[j]);
+            v[j] = cmac(cmac(cmac(cmul(k[0], v[j]), k[1], q1), k[2], q2), k[3], q3);
+            pin(v[j]);
+            shuffle_fence<j>();
+        });
+    }
+}
+
+// ------------------------------------------------------------ phase runs --
+// Events strictly inside a run (at most three; the executor routes nodes
+// with more to the generic kernel): the frame a gate of the run sees, by
+// its index k in the run.  Consumes the events and leaves the frame at the
+// run's end.
+__device__ __forceinline__ RunFrames run_frames(Wave &w, uint32_t key0, uint32_t key1) {
+    RunFrames rf;
+    rf.f0 = rf.f1 = rf.f2 = rf.f3 = w.fx;
+    rf.k0 = rf.k1 = rf.k2 = 0xFFFFu;
+    if (w.nxt < key1) {
+        rf.k0 = (w.nxt & 0xFFFFu) - (key0 & 0xFFFFu);
+        rf.f1 = rf.f0 ^ uni(w.dx[w.e]);
+        w.fz ^= uni(w.dz[w.e]);
+        w.e++;
+        w.nxt = w.e < w.e1 ? uni(w.pos[w.e]) : 0xFFFFFFFFu;
+        rf.f2 = rf.f3 = rf.f1;
+        if (w.nxt < key1) {
+            rf.k1 = (w.nxt & 0xFFFFu) - (key0 & 0xFFFFu);
+            rf.f2 = rf.f1 ^ uni(w.dx[w.e]);
+            w.fz ^= uni(w.dz[w.e]);
+            w.e++;
+            w.nxt = w.e < w.e1 ? uni(w.pos[w.e]) : 0xFFFFFFFFu;
+            rf.f3 = rf.f2;
+            if (w.nxt < key1) {
+                rf.k2 = (w.nxt & 0xFFFFu) - (key0 & 0xFFFFu);
+                rf.f3 = rf.f2 ^ uni(w.dx[w.e]);
+                w.fz ^= uni(w.dz[w.e]);
+                w.e++;
+                w.nxt = w.e < w.e1 ? uni(w.pos[w.e]) : 0xFFFFFFFFu;
+            }
+        }
+    }
+    w.fx = rf.f3;
+    return rf;
+}
+
+// One term's four phases re-indexed by its frame bits (fu, fw) and split
+// into multilinear coefficients of the stored index bits (x_u, x_w):
+// th(x_u ^ fu, x_w ^ fw) = a + b x_u + g x_w + d x_u x_w  (mod one turn).
+template <typename A>
+struct Ml {
+    A a, b, g, d;
+};
+template <typename A>
+__device__ __forceinline__ Ml<A> multilinear(A t0, A t1, A t2, A t3, uint32_t fu, uint32_t fw) {
+    // permute by the frame: index (x_u ^ fu) + 2 (x_w ^ fw)
+    const A u0 = fu ? t1 : t0, u1 = fu ? t0 : t1, u2 = fu ? t3 : t2, u3 = fu ? t2 : t3;
+    const A p0 = fw ? u2 : u0, p1 = fw ? u3 : u1, p2 = fw ? u0 : u2, p3 = fw ? u1 : u3;
+    Ml<A> m;
+    m.a = p0;
+    m.b = (A)(p1 - p0);
+    m.g = (A)(p2 - p0);
+    m.d = (A)(p3 - p2 - p1 + p0);
+    return m;
+}
+
+// Per-lane masks of the lane bits: all ones where bit a of L is set.
+struct LaneBits {
+    uint32_t m[6];
+};
+__device__ __forceinline__ LaneBits lane_bits(uint32_t L) {
+    LaneBits lb;
+#pragma unroll
+    for (int a = 0; a < 6; a++) lb.m[a] = 0u - ((L >> a) & 1u);
+    return lb;
+}
+// c where the mask is set (per lane), in the accumulator width
+__device__ __forceinline__ uint32_t masked(uint32_t c, uint32_t m) { return c & m; }
+__device__ __forceinline__ uint64_t masked(uint64_t c, uint32_t m) { return c & (uint64_t)(int64_t)(int32_t)m; }
+
+// The run's register-only gates: table T (2^NR entries, index y = j ^ fr);
+// entries that are exactly 1 are skipped (TMASK, for NR <= 5).
+template <typename R, int RB, uint32_t TMASK>
+__device__ __forceinline__ void apply_table(cplx<R> (&v)[1 << RB], kptr<cplx<R>> T, uint32_t fr) {
+    sfor<(1 << RB)>([&](auto Jc) __attribute__((always_inline)) {
+        constexpr int j = decltype(Jc)::value;
+        const uint32_t t = (uint32_t)j ^ fr;
+        if (RB > 5 || ((TMASK >> t) & 1u)) v[j] = cmul(T[t], v[j]);
+    });
+}
+
+// Register bits of frame f, in register-index order (RQ: physical qubit of
+// each register bit).
+template <int RB>
+__device__ __forceinline__ uint32_t reg_frame(uint32_t f, const uint8_t (&rq)[8]) {
+    uint32_t r = 0;
+#pragma unroll
+    for (int i = 0; i < RB; i++) r |= ((f >> rq[i]) & 1u) << i;
+    return r;
+}
+
+}  // namespace jit
+}  // namespace tqs

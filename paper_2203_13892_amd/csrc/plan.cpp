@@ -146,6 +146,8 @@ extern "C" tqs_status tqs_plan_create(const tqs_circuit *c, const tqs_tree *tree
     }
     if (!tu.sample_block_log) tu.sample_block_log = 12;
     if (!tu.pass_cost) tu.pass_cost = 480;
+    if (tu.jit > 2) return fail(TQS_E_ARG, "jit must be 0 (default), 1 (on) or 2 (off)");
+    if (!tu.jit) tu.jit = c->n >= 16 ? 1u : 2u;
     const uint32_t tmax = prec == TQS_C64 ? 12 : 11;
     if (tu.tile_qubits < 10 || tu.tile_qubits > tmax)
         return fail(TQS_E_ARG, "tile_qubits must be in 10..%u at this precision", tmax);

@@ -30,13 +30,14 @@ class TqsTree(C.Structure):
 class TqsTuning(C.Structure):
     _fields_ = [("tile_qubits", u32), ("max_ops_per_pass", u32), ("chunk_states", u32),
                 ("sample_block_log", u32), ("pass_cost", u32), ("no_merge", u32),
-                ("separate_sampling", u32)]
+                ("separate_sampling", u32), ("jit", u32)]
 
 
 class TqsRunStats(C.Structure):
     _fields_ = [("ms_wall", dbl), ("ms_device", dbl), ("ms_passes", dbl), ("ms_sample", dbl),
                 ("launches", u64), ("pass_launches", u64), ("pass_states", u64), ("bytes_passes", u64),
-                ("bytes_sample", u64), ("events", u64), ("nodes_merged", u64)]
+                ("bytes_sample", u64), ("events", u64), ("nodes_merged", u64), ("jit_launches", u64),
+                ("jit_states", u64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -68,6 +69,8 @@ SIGNATURES = {
     "tqs_histogram": (i32, [P(u64), u64, P(u64), P(u64), P(u64)]),
     "tqs_probe_copy": (i32, [vp, u64, u32, vp, P(dbl)]),
     "tqs_plan_describe": (i32, [vp, C.c_char_p, u64, P(u64)]),
+    "tqs_plan_compile": (i32, [vp]),
+    "tqs_plan_jit_source": (i32, [vp, C.c_char_p, u64, P(u64)]),
     "tqs_batch_create": (i32, [P(vp), P(vp), u32, P(vp)]),
     "tqs_batch_info": (i32, [vp, P(u64), P(u64), P(u32)]),
     "tqs_batch_use_graph": (i32, [vp, u32]),
@@ -310,6 +313,18 @@ class Plan:
         _check(lib.tqs_plan_describe(self.h, None, 0, C.byref(n)))
         buf = C.create_string_buffer(n.value)
         _check(lib.tqs_plan_describe(self.h, buf, n.value, C.byref(n)))
+        return buf.value.decode()
+
+    def compile(self):
+        """Compile the plan's specialised pass kernels now (tqs_plan_compile)."""
+        _check(lib.tqs_plan_compile(self.h))
+
+    def jit_source(self) -> str:
+        """HIP source of the plan's specialised pass kernels."""
+        n = u64()
+        _check(lib.tqs_plan_jit_source(self.h, None, 0, C.byref(n)))
+        buf = C.create_string_buffer(n.value)
+        _check(lib.tqs_plan_jit_source(self.h, buf, n.value, C.byref(n)))
         return buf.value.decode()
 
     def workspace_bytes(self, noise: Noise = None) -> int:

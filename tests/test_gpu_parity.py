@@ -99,16 +99,18 @@ def mixed_gates(n, count, rng):
     return c
 
 
+@pytest.mark.parametrize("jit", [1, 2])
 @pytest.mark.parametrize("prec", ["c64", "c128"])
 @pytest.mark.parametrize("n", [1, 2, 5, 9, 14])
-def test_every_op_class_with_forced_noise(T, prec, n):
+def test_every_op_class_with_forced_noise(T, prec, n, jit):
     rng = np.random.default_rng(100 + n)
     wc = mixed_gates(n, 60, rng) if n > 1 else W.Circuit(1, [((0,), W.haar_unitary(2, rng), None)] * 3)
     if n == 1:
         wc.add((0,), W.phase(0.3))
     tree = ([6], [0, len(wc)])
     arr = event_arrays(wc, tree, rng)
-    out, amps, oout, ost, _ = run_both(T, wc, tree, 0, prec, np.arange(6), noise_arrays=arr)
+    out, amps, oout, ost, _ = run_both(T, wc, tree, 0, prec, np.arange(6), noise_arrays=arr,
+                                       tuning={"jit": jit})
     assert np.max(np.abs(amps - ost)) < TOL[prec]
     check_outcomes(out, oout, ost, arr[3], DELTA[prec])
 
@@ -130,8 +132,9 @@ def longest_phase_run(plan):
     return sorted(g for g, (gp, gs) in where.items() if gp == p and s0 < gs < s1)
 
 
+@pytest.mark.parametrize("jit", [1, 2])
 @pytest.mark.parametrize("prec", ["c64", "c128"])
-def test_phase_run_with_up_to_five_events_inside(T, prec):
+def test_phase_run_with_up_to_five_events_inside(T, prec, jit):
     # one long run of diagonal gates on lane, register and fixed qubits;
     # leaf i carries counts[i] events inside it, so the run is applied
     # whole, in two to four frames, and gate by gate
@@ -160,13 +163,15 @@ def test_phase_run_with_up_to_five_events_inside(T, prec):
             ec.append(int(rng.integers(1, 4 ** len(wc.gates[g][0]))))
         node_off.append(len(eg))
     arr = (np.array(node_off, np.uint64), np.array(eg, np.uint32), np.array(ec, np.uint8), rng.random(8))
-    out, amps, oout, ost, _ = run_both(T, wc, tree, 0, prec, np.arange(8), noise_arrays=arr)
+    out, amps, oout, ost, _ = run_both(T, wc, tree, 0, prec, np.arange(8), noise_arrays=arr,
+                                       tuning={"jit": jit})
     assert np.max(np.abs(amps - ost)) < TOL[prec]
     check_outcomes(out, oout, ost, arr[3], DELTA[prec])
 
 
+@pytest.mark.parametrize("jit", [1, 2])
 @pytest.mark.parametrize("prec", ["c64", "c128"])
-def test_tree_levels_ragged_chunks(T, prec):
+def test_tree_levels_ragged_chunks(T, prec, jit):
     rng = np.random.default_rng(7)
     n = 13
     wc = mixed_gates(n, 45, rng)
@@ -174,7 +179,7 @@ def test_tree_levels_ragged_chunks(T, prec):
     arr = event_arrays(wc, tree, rng, rate=0.15)
     leaves = np.arange(60)
     out, amps, oout, ost, _ = run_both(T, wc, tree, 0, prec, leaves,
-                                       tuning={"chunk_states": 7, "max_ops_per_pass": 5},
+                                       tuning={"chunk_states": 7, "max_ops_per_pass": 5, "jit": jit},
                                        noise_arrays=arr)
     assert np.max(np.abs(amps - ost)) < TOL[prec]
     check_outcomes(out, oout, ost, arr[3], DELTA[prec])
@@ -380,10 +385,11 @@ def test_phase_run_term_groups(T, prec):
         wc = _diag_case(12, gates, rng)
         c = T.Circuit.from_workload(wc)
         tree = ([1], [0, len(wc)])
-        plan = T.Plan(c, tree, prec, {"tile_qubits": 10, "pass_cost": 100000})
-        _, amps = T.run_capture(plan, T.Noise.sample(c, tree, 0), [0])
-        _, ref = oracle.run_events(12, wc.gates)
-        assert np.max(np.abs(amps[0] - ref)) < TOL[prec], k
+        for jit in (1, 2):
+            plan = T.Plan(c, tree, prec, {"tile_qubits": 10, "pass_cost": 100000, "jit": jit})
+            _, amps = T.run_capture(plan, T.Noise.sample(c, tree, 0), [0])
+            _, ref = oracle.run_events(12, wc.gates)
+            assert np.max(np.abs(amps[0] - ref)) < TOL[prec], (k, jit)
 
 
 def test_tree_fidelity_loss_is_small(T):
@@ -612,8 +618,9 @@ def _distinct_histories(tree, arr):
     return merged
 
 
+@pytest.mark.parametrize("jit", [1, 2])
 @pytest.mark.parametrize("prec", ["c64", "c128"])
-def test_merged_states_equal_separate_states(T, prec):
+def test_merged_states_equal_separate_states(T, prec, jit):
     # nodes with equal parent state, frame and events share one state: the
     # outcomes are bit-identical to computing every node, the captured
     # leaves match the oracle, and at least every repeated history is
@@ -625,8 +632,8 @@ def test_merged_states_equal_separate_states(T, prec):
     arr = _repeating_events(wc, tree, rng)
     c = T.Circuit.from_workload(wc)
     nz = T.Noise.from_arrays(c, tree, *arr)
-    merged_plan = T.Plan(c, tree, prec, {"chunk_states": 512})
-    plain_plan = T.Plan(c, tree, prec, {"chunk_states": 512, "no_merge": 1})
+    merged_plan = T.Plan(c, tree, prec, {"chunk_states": 512, "jit": jit})
+    plain_plan = T.Plan(c, tree, prec, {"chunk_states": 512, "no_merge": 1, "jit": jit})
     out_m, st_m = T.run(merged_plan, nz, stats=True)
     out_p, st_p = T.run(plain_plan, nz, stats=True)
     assert np.array_equal(out_m, out_p)
@@ -636,7 +643,7 @@ def test_merged_states_equal_separate_states(T, prec):
     assert st_m["nodes_merged"] >= want
     assert st_m["pass_states"] < st_p["pass_states"]
     leaves = np.arange(256)
-    out, amps, oout, ost, _ = run_both(T, wc, tree, 0, prec, leaves, noise_arrays=arr)
+    out, amps, oout, ost, _ = run_both(T, wc, tree, 0, prec, leaves, noise_arrays=arr, tuning={"jit": jit})
     assert np.max(np.abs(amps - ost)) < TOL[prec]
     check_outcomes(out, oout, ost, arr[3], DELTA[prec])
 
@@ -775,8 +782,9 @@ def test_largest_sizes(T):
     assert np.all(out == x), out
 
 
+@pytest.mark.parametrize("jit", [1, 2])
 @pytest.mark.parametrize("prec", ["c64", "c128"])
-def test_degenerate_trees(T, prec):
+def test_degenerate_trees(T, prec, jit):
     # arity-1 levels, a level of swap gates only (a pass with no ops), a
     # one-gate level, and a list without events: outcomes and amplitudes
     # match the oracle
@@ -789,12 +797,14 @@ def test_degenerate_trees(T, prec):
     for tree in (([1, 1, 3], [0, 10, 20, G]), ([2, 3, 2], [0, 20, 22, G]), ([1], [0, G])):
         arr = event_arrays(wc, tree, rng, rate=0.3)
         leaves = np.arange(int(np.prod(tree[0])))
-        out, amps, oout, ost, _ = run_both(T, wc, tree, 0, prec, leaves, noise_arrays=arr)
+        out, amps, oout, ost, _ = run_both(T, wc, tree, 0, prec, leaves, noise_arrays=arr,
+                                           tuning={"jit": jit})
         assert np.max(np.abs(amps - ost)) < TOL[prec]
         check_outcomes(out, oout, ost, arr[3], DELTA[prec])
     tree = ([4, 4], [0, 10, G])
     none = (np.zeros(1 + 4 + 16, np.uint64), np.zeros(0, np.uint32), np.zeros(0, np.uint8), rng.random(16))
-    out, amps, oout, ost, _ = run_both(T, wc, tree, 0, prec, np.arange(16), noise_arrays=none)
+    out, amps, oout, ost, _ = run_both(T, wc, tree, 0, prec, np.arange(16), noise_arrays=none,
+                                       tuning={"jit": jit})
     assert np.max(np.abs(amps - ost)) < TOL[prec]
     check_outcomes(out, oout, ost, none[3], DELTA[prec])
 
@@ -830,7 +840,8 @@ def test_random_configurations(T, seed):
     tree = (A, cut)
     tuning = {"chunk_states": int(rng.integers(1, 8)), "tile_qubits": int(rng.choice([10, 11])),
               "sample_block_log": int(rng.integers(8, 13)), "separate_sampling": int(rng.integers(0, 2)),
-              "no_merge": int(rng.integers(0, 2)), "pass_cost": int(rng.choice([120, 480]))}
+              "no_merge": int(rng.integers(0, 2)), "pass_cost": int(rng.choice([120, 480])),
+              "jit": 1 + seed % 2}
     arr = _repeating_events(wc, tree, rng, rate=float(rng.uniform(0.01, 0.1)))
     flips = rng.integers(0, 1 << n, arr[3].size).astype(np.uint32) if seed % 2 else None
     c = T.Circuit.from_workload(wc)
@@ -877,3 +888,39 @@ def test_events_after_the_last_op_share_states(T, prec):
     out2, amps, oout, ost, _ = run_both(T, wc, tree, 0, prec, np.arange(24), noise_arrays=arr)
     assert np.max(np.abs(amps - ost)) < TOL[prec]
     check_outcomes(out2, oout, ost, arr[3], DELTA[prec])
+
+
+@pytest.mark.parametrize("case", ["qft20", "bw20", "mixed14"])
+def test_specialised_kernels_match_generic(T, case):
+    # the plan-specialised pass kernels against the generic kernel on the
+    # same plan and insertion list: every leaf's outcome and sampled leaves'
+    # amplitudes; the run statistics show which kernel took how many states
+    # (nodes with more than three events inside a phase run, or a frame
+    # change between a run's register-only gates, go to the generic kernel)
+    rng = np.random.default_rng(77)
+    if case == "qft20":
+        wc = W.qft(20).with_depolarizing(1e-3, 1e-2)
+        A = [16, 32, 32]
+    elif case == "bw20":
+        wc = W.brickwall(20, 20, seed=1).with_depolarizing(1e-3, 1e-2)
+        A = [8, 16, 16]
+    else:
+        wc = mixed_gates(14, 80, rng).with_depolarizing(2e-2, 8e-2)
+        A = [8, 8, 8]
+    G = len(wc)
+    tree = (A, [round(j * G / len(A)) for j in range(len(A) + 1)])
+    c = T.Circuit.from_workload(wc)
+    nz = T.Noise.sample(c, tree, 9)
+    leaves = np.sort(rng.choice(int(np.prod(A)), 12, replace=False))
+    res = {}
+    for jit in (1, 2):
+        plan = T.Plan(c, tree, "c64", {"jit": jit})
+        out, st = T.run(plan, nz, stats=True)
+        _, amps = T.run_capture(plan, nz, leaves)
+        res[jit] = (out, st, amps)
+    (o1, s1, a1), (o2, s2, a2) = res[1], res[2]
+    print(case, "specialised launches", s1["jit_launches"], "states", s1["jit_states"], "of", s1["pass_states"])
+    assert s2["jit_launches"] == 0
+    assert s1["jit_launches"] > 0 and s1["jit_states"] >= 0.5 * s1["pass_states"]
+    assert np.max(np.abs(a1 - a2)) < 1e-6
+    assert np.mean(o1 == o2) > 0.99
