@@ -84,6 +84,7 @@ def time_form(T, torch, circuit, tree, seed, steps, warmup, tuning=None):
     torch.cuda.synchronize()
     agg = {"ms_passes": 0.0, "ms_sample": 0.0, "bytes_passes": 0, "bytes_sample": 0,
            "pass_launches": 0, "ms_device": 0.0, "launches": 0, "nodes_merged": 0,
+           "ms_jit": 0.0, "bytes_jit": 0, "jit_launches": 0, "jit_states": 0, "pass_states": 0,
            "host_plan_ms": (t1 - t0) * 1e3, "host_noise_ms": (t2 - t1) * 1e3}
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -96,6 +97,8 @@ def time_form(T, torch, circuit, tree, seed, steps, warmup, tuning=None):
         agg["launches"] += st["launches"]
         agg["pass_launches"] += st["pass_launches"]
         agg["nodes_merged"] = st["nodes_merged"]
+        for k in ("ms_jit", "bytes_jit", "jit_launches", "jit_states", "pass_states"):
+            agg[k] += st[k]
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     passes_total = sum(plan.info(l)["passes_level"] * int(__import__("numpy").prod(tree[0][:l + 1]))
@@ -106,14 +109,17 @@ def time_form(T, torch, circuit, tree, seed, steps, warmup, tuning=None):
     return plan.n_leaves * steps / dt, dt * 1000 / steps, agg, out
 
 
-def fidelity_loss(T, W, torch, seeds, n=20, shots=16384):
-    """Normalised fidelity (F_s of a peaked ideal distribution, normalised
-    against the uniform one) of the 20-qubit QFT round trip from a basis state,
-    trees (16, 32, 32) and (8, 8, 16, 16) against per-shot, over noise seeds;
-    differences +- their standard errors."""
+def fidelity_loss(T, W, torch, seeds, n=20, shots=16384, p1=1e-4, p2=1e-3):
+    """Normalised fidelity (Sec. 4.1: F_s of a peaked ideal distribution,
+    normalised against the uniform one) of the 20-qubit QFT round trip from a
+    basis state (440 gates), trees (16, 32, 32) and (8, 8, 16, 16) against
+    per-shot, over noise seeds; the differences +- their standard errors over
+    seeds (each seed's level-0 subtrees are independent, so the per-seed
+    difference carries the tree's clustering).  The noise rates keep the
+    per-shot F inside (0.3, 0.9), where a fidelity loss would show."""
     import numpy as np
     x = 0x5A5A5 & ((1 << n) - 1)
-    wc = W.concat(W.basis_prep(n, x), W.qft(n), W.inverse(W.qft(n))).with_depolarizing(1e-3, 1e-2)
+    wc = W.concat(W.basis_prep(n, x), W.qft(n), W.inverse(W.qft(n))).with_depolarizing(p1, p2)
     G = len(wc)
     c = T.Circuit.from_workload(wc)
     u = 2.0 ** -n
@@ -133,7 +139,8 @@ def fidelity_loss(T, W, torch, seeds, n=20, shots=16384):
         out[name] = np.array(vals)
     d = out["tree"] - out["pershot"]
     d4 = out["tree4b"] - out["pershot"]
-    return {"workload": "qft%d round trip from |x>, depolarizing(1e-3,1e-2), %d shots" % (n, shots),
+    return {"workload": "qft%d round trip from |x>, depolarizing(%g,%g), %d shots" % (n, p1, p2, shots),
+            "bound": 0.016,
             "F_pershot": float(out["pershot"].mean()), "F_tree": float(out["tree"].mean()),
             "delta_F": float(d.mean()), "delta_F_se": float(d.std(ddof=1) / np.sqrt(len(d))),
             "F_tree4b": float(out["tree4b"].mean()), "delta_F_tree4b": float(d4.mean()),
@@ -353,9 +360,21 @@ def parity_sample(T, wc, tree, seed, count=16):
     threads = max(1, min(len(os.sched_getaffinity(0)), int(os.environ.get("OMP_NUM_THREADS", "16"))))
     oout, ost = oracle.run_leaves(wc.n, wc.gates, tree, onz, leaves, states=True, threads=threads)
     err = float(np.max(np.abs(amps - ost)))
-    same = int(np.sum(out[leaves.astype(np.int64)] == oout))
+    got = out[leaves.astype(np.int64)]
+    same = int(np.sum(got == oout))
+    # a differing outcome is a boundary pick when every oracle prefix between
+    # the two outcomes lies within 1e-6 T of u T; anything else is invalid
+    boundary, invalid = 0, 0
+    for i in np.nonzero(got != oout)[0]:
+        pr = np.abs(ost[i]) ** 2
+        tot, pre = pr.sum(), np.cumsum(pr)
+        lo, hi = sorted((int(got[i]), int(oout[i])))
+        ok = hi < pr.size and np.all(np.abs(pre[lo:hi] - onz.leaf_u[int(leaves[i])] * tot) <= 1e-6 * tot)
+        boundary += int(ok)
+        invalid += int(not ok)
     return {"leaves": count, "max_abs_amplitude_error": err, "tolerance": 1e-5,
-            "outcomes_equal": "%d of %d" % (same, count)}
+            "outcomes_equal": "%d of %d" % (same, count), "boundary_leaves": boundary,
+            "invalid_outcomes": invalid}
 
 
 def cpu_baseline(wc, seed, budget_s=15.0):
@@ -411,8 +430,8 @@ def main():
     ap.add_argument("--tile", type=int, default=0, help="tile qubits (0 = library default)")
     ap.add_argument("--pass-cost", type=int, default=0, help="per-pass work bound (0 = default)")
     ap.add_argument("--chunk", type=int, default=0, help="live states per level (0 = default)")
-    ap.add_argument("--fidelity", action="store_true",
-                    help="also report the tree's fidelity loss against per-shot sampling")
+    ap.add_argument("--no-fidelity", action="store_true",
+                    help="skip the tree's fidelity loss against per-shot sampling")
     ap.add_argument("--fid-seeds", type=int, default=10)
     ap.add_argument("--batch", action="store_true",
                     help="also run the 512-circuit mixed workload one run at a time and batched")
@@ -488,12 +507,20 @@ def main():
                          "nodes_merged": agg["nodes_merged"],
                          "host_plan_ms": agg["host_plan_ms"], "host_noise_ms": agg["host_noise_ms"],
                          "bytes_per_launch": agg["bytes_passes"] / max(agg["pass_launches"], 1),
-                         "us_per_launch": agg["ms_passes"] * 1e3 / max(agg["pass_launches"], 1)}
+                         "us_per_launch": agg["ms_passes"] * 1e3 / max(agg["pass_launches"], 1),
+                         "jit_launches": agg["jit_launches"], "ms_jit": agg["ms_jit"],
+                         "bytes_jit": agg["bytes_jit"], "jit_states": agg["jit_states"],
+                         "pass_states": agg["pass_states"]}
         print("# %s: %.1f shots/s, %.2f ms/step, pass %.0f GB/s" %
               (name, sps, ms, results[name]["pass_GBps"]), file=sys.stderr, flush=True)
     head = "tree" if "tree" in results else list(results)[0]
     h = results[head]
-    achieved = h["pass_GBps"]
+    # the dominant kernel: the plan-specialised pass kernel, timed with HIP
+    # events around each of its launches (the generic kernel takes the
+    # nodes it does not: reported beside it)
+    jl = max(h["jit_launches"], 1)
+    achieved = h["bytes_jit"] / (h["ms_jit"] * 1e-3) / 1e9 if h["ms_jit"] > 0 else h["pass_GBps"]
+    prof = profiled_record()
     line = {
         "metric": "noisy shots/s, 20q QFT 16k shots: tree vs per-shot on 1 GPU; % HBM peak",
         "value": h["shots_per_s"],
@@ -513,21 +540,22 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "valu_issue_frac": valu_issue_frac(),
-                     "kernel": "pass_kernel<float>",
-                     "algorithmic_bytes_per_launch": h["bytes_per_launch"],
-                     "us_per_launch": h["us_per_launch"], "launches": h["pass_launches"]},
+                     "kernel": "tqs_jit_p* (plan-specialised pass kernel, float)",
+                     "algorithmic_bytes_per_launch": h["bytes_jit"] / jl,
+                     "us_per_launch": h["ms_jit"] * 1e3 / jl, "launches": h["jit_launches"],
+                     "states_share": h["jit_states"] / max(h["pass_states"], 1),
+                     "all_pass_launches_GBps": h["pass_GBps"]},
         "forms": {k: {kk: v[kk] for kk in ("shots_per_s", "ms_per_step", "pass_GBps", "shape", "nodes_merged",
                                            "host_plan_ms", "host_noise_ms")}
                   for k, v in results.items()},
     }
-    # per-shot without merged states is the baseline the tree is measured
-    # against; the ratios separate tree reuse from state sharing
-    base = results.get("pershot_nomerge", results.get("pershot"))
-    if base is not None and head != "pershot":
-        line["tree_speedup_vs_pershot"] = h["shots_per_s"] / base["shots_per_s"]
+    # like for like: the tree against per-shot with states of equal noise
+    # histories shared in both, and with every node computed in both
+    if "tree" in results and "pershot" in results:
+        line["tree_speedup_vs_pershot"] = results["tree"]["shots_per_s"] / results["pershot"]["shots_per_s"]
     if "tree_nomerge" in results and "pershot_nomerge" in results:
-        line["tree_nomerge_speedup_vs_pershot"] = (results["tree_nomerge"]["shots_per_s"] /
-                                                   results["pershot_nomerge"]["shots_per_s"])
+        line["tree_nomerge_speedup_vs_pershot_nomerge"] = (results["tree_nomerge"]["shots_per_s"] /
+                                                           results["pershot_nomerge"]["shots_per_s"])
     if not args.no_dcp:
         line["copy_cost_gates"] = copy_cost
         line["copy_GBps"] = copy_gbps
@@ -548,8 +576,12 @@ def main():
                 "shots_per_s": sps, "ms_per_step": ms, "shape": tree[0],
                 "pass_GBps": agg["bytes_passes"] / (agg["ms_passes"] * 1e-3) / 1e9}
             print("# brickwall %s: %.1f shots/s, %.2f ms/step" % (name, sps, ms), file=sys.stderr, flush=True)
-    if args.fidelity:
+    if not args.no_fidelity:
         line["fidelity_loss"] = fidelity_loss(T, W, torch, args.fid_seeds)
+        fl = line["fidelity_loss"]
+        print("# fidelity: F_pershot %.4f, dF (16,32,32) %+.4f +- %.4f, dF (8,8,16,16) %+.4f +- %.4f" %
+              (fl["F_pershot"], fl["delta_F"], fl["delta_F_se"], fl["delta_F_tree4b"], fl["delta_F_tree4b_se"]),
+              file=sys.stderr, flush=True)
     if args.precision:
         line["precision_sweep"] = precision_sweep(T, W, torch, args.seed)
     if args.batch:

@@ -128,6 +128,8 @@ typedef struct {
     uint64_t nodes_merged;     /* nodes whose state is an identical earlier node's */
     uint64_t jit_launches;     /* pass launches of plan-specialised kernels */
     uint64_t jit_states;       /* states those launches processed */
+    uint64_t bytes_jit;        /* their algorithmic HBM bytes (as bytes_passes) */
+    double ms_jit;             /* their device time (HIP events around each such launch) */
 } tqs_run_stats;
 
 /* ---------------------------------------------------------------- circuit */

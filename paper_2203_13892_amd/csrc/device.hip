@@ -505,7 +505,8 @@ struct Layout {
     uint32_t scratch_slot;
     uint64_t off_states;  // first state slot
     uint64_t off_meta, off_mats, off_ops, off_passes, off_terms, off_dgates, off_frame0, off_evoff,
-        off_evpos, off_evdx, off_evdz, off_leafu, off_leaffx, off_flip, off_sched, off_sums, off_part, off_out, total;
+        off_evpos, off_evdx, off_evdz, off_leafu, off_leaffx, off_flip, off_sched, off_ctoff, off_ctab, off_sums,
+        off_part, off_out, total;
     uint64_t n_sched;
 };
 
@@ -513,7 +514,7 @@ struct Layout {
 // metadata and sampling regions from `meta_at` (by default right after the
 // states).  `total` is the end of the metadata regions.
 static Layout make_layout(const tqs_plan *p, uint64_t n_events, uint64_t n_leaves_out, uint64_t n_sched,
-                          uint64_t states_at = 0, uint64_t meta_at = ~0ull) {
+                          uint64_t states_at = 0, uint64_t meta_at = ~0ull, uint64_t n_ctab = 0) {
     Layout L;
     L.off_states = states_at;
     L.amp_bytes = p->prec == TQS_C64 ? 8 : 16;
@@ -556,6 +557,10 @@ static Layout make_layout(const tqs_plan *p, uint64_t n_events, uint64_t n_leave
     L.off_sched = o;
     L.n_sched = n_sched;
     o = align256(o + n_sched * 4);
+    L.off_ctoff = o;
+    o = align256(o + p->n_nodes * 4);
+    L.off_ctab = o;
+    o = align256(o + n_ctab * L.amp_bytes);
     L.off_sums = o;
     const uint64_t nblocks = 1ull << (p->n - p->sample_b);
     o = align256(o + (uint64_t)p->chunk.back() * nblocks * 8);
@@ -853,6 +858,9 @@ static PassArgs<R> pass_args(const tqs_plan *p, const Layout &Ly, unsigned char 
     a.meta.ev_pos = reinterpret_cast<const uint32_t *>(ws + Ly.off_evpos);
     a.meta.ev_dx = reinterpret_cast<const uint32_t *>(ws + Ly.off_evdx);
     a.meta.ev_dz = reinterpret_cast<const uint32_t *>(ws + Ly.off_evdz);
+    a.meta.ct_off = reinterpret_cast<const uint32_t *>(ws + Ly.off_ctoff);
+    a.meta.ct_dir = reinterpret_cast<const uint32_t *>(ws + Ly.off_sched);
+    a.meta.ctab = ws + Ly.off_ctab;
     a.terms = reinterpret_cast<const DiagTerm *>(ws + Ly.off_terms);
     a.dgates = reinterpret_cast<const DiagGate *>(ws + Ly.off_dgates);
     // the last pass of the leaf level writes the sampling partials
@@ -903,14 +911,27 @@ struct Route {
     uint32_t n_jit = 0;  // states for the specialised kernel
 };
 
-// Routes of every (task, pass of its level), appending index lists to sched.
+// Frame tables of the computed states that need them, and where each
+// node's directory starts (ct_off; ~0u: none).
+struct FrameTables {
+    std::vector<cd> tab;
+    std::vector<uint32_t> ct_off;
+};
+
+// Routes of every (task, pass of its level), appending index lists and the
+// frame-table directories to sched.
 static void route_passes(const tqs_plan *p, const HostMeta &hm, const std::vector<Task> &tasks,
-                         std::vector<uint32_t> *sched, std::vector<std::vector<Route>> *routes) {
+                         std::vector<uint32_t> *sched, std::vector<std::vector<Route>> *routes, FrameTables *ft) {
     routes->assign(tasks.size(), {});
+    ft->tab.clear();
+    ft->ct_off.assign(p->n_nodes, 0xFFFFFFFFu);
     if (p->tune.jit != 1) return;
     std::vector<std::vector<JitRun>> runs;
     jit_runs(p, &runs);
     std::vector<uint32_t> yes, no;
+    // per node with frame tables: (pass, first entry) pairs
+    std::vector<std::pair<uint32_t, std::vector<std::pair<uint32_t, uint32_t>>>> dirs;
+    std::unordered_map<uint32_t, size_t> dir_of;
     for (size_t ti = 0; ti < tasks.size(); ti++) {
         const Task &t = tasks[ti];
         const tqs::Level &lv = p->levels[t.level];
@@ -924,8 +945,23 @@ static void route_passes(const tqs_plan *p, const HostMeta &hm, const std::vecto
             for (uint32_t c = 0; c < t.ccount; c++) {
                 const uint32_t node = (*sched)[t.cnode() + c];
                 const uint32_t e0 = hm.ev_off[node], e1 = hm.ev_off[node + 1];
-                if (jit_eligible(runs[pi], pi, hm.ev_pos.data() + e0, hm.ev_dx.data() + e0, e1 - e0)) yes.push_back(c);
-                else no.push_back(c);
+                const JitFit fit = jit_fit(runs[pi], pi, hm.ev_pos.data() + e0, hm.ev_dx.data() + e0, e1 - e0);
+                if (fit == JIT_NO) {
+                    no.push_back(c);
+                    continue;
+                }
+                yes.push_back(c);
+                if (fit == JIT_TABLES) {
+                    const uint32_t first = (uint32_t)ft->tab.size();
+                    jit_frame_tables(p, pi, hm.frame0[2 * node], hm.ev_pos.data() + e0, hm.ev_dx.data() + e0,
+                                     e1 - e0, &ft->tab);
+                    auto it = dir_of.find(node);
+                    if (it == dir_of.end()) {
+                        it = dir_of.emplace(node, dirs.size()).first;
+                        dirs.push_back({node, {}});
+                    }
+                    dirs[it->second].second.push_back({pi, first});
+                }
             }
             r.n_jit = (uint32_t)yes.size();
             if (no.empty() || yes.empty()) continue;
@@ -934,13 +970,32 @@ static void route_passes(const tqs_plan *p, const HostMeta &hm, const std::vecto
             sched->insert(sched->end(), no.begin(), no.end());
         }
     }
+    for (const auto &d : dirs) {
+        ft->ct_off[d.first] = (uint32_t)sched->size();
+        sched->push_back((uint32_t)d.second.size());
+        for (const auto &e : d.second) {
+            sched->push_back(e.first);
+            sched->push_back(e.second);
+        }
+    }
+}
+
+// Frame-table entries route_passes may create at most.
+static uint64_t table_bound(const tqs_plan *p) {
+    uint64_t b = 0;
+    if (p->tune.jit == 1)
+        for (size_t l = 0; l < p->levels.size(); l++)
+            for (uint32_t k = 0; k < p->levels[l].pass_count; k++)
+                b += p->level_nodes[l] * (uint64_t)jit_table_entries(p, p->levels[l].pass_begin + k);
+    return b;
 }
 
 // Schedule entries route_passes may append at most.
 static uint64_t route_bound(const tqs_plan *p) {
     uint64_t b = 0;
     if (p->tune.jit == 1)
-        for (size_t l = 0; l < p->levels.size(); l++) b += p->level_nodes[l] * (uint64_t)p->levels[l].pass_count;
+        for (size_t l = 0; l < p->levels.size(); l++)
+            b += p->level_nodes[l] * (uint64_t)(p->levels[l].pass_count + 1 + 2 * p->levels[l].pass_count);
     return b;
 }
 
@@ -956,7 +1011,7 @@ static hipError_t launch_jit(const tqs_plan *p, uint32_t pass_idx, PassLaunch<R>
 template <typename R>
 static uint32_t launch_routed(const tqs_plan *p, const Layout &Ly, unsigned char *ws, hipStream_t s,
                               const Task &t, uint32_t pass_idx, bool first, const Route &r,
-                              uint32_t *launches, hipError_t *err) {
+                              uint32_t *launches, hipError_t *err, hipEvent_t ej0, hipEvent_t ej1) {
     const bool have_jit = p->tune.jit == 1 && pass_idx < p->jit_fn.size() && p->jit_fn[pass_idx];
     const uint32_t n_jit = have_jit ? r.n_jit : 0u;
     PassLaunch<R> pl;
@@ -972,7 +1027,9 @@ static uint32_t launch_routed(const tqs_plan *p, const Layout &Ly, unsigned char
         pj.one.count = n_jit;
         pj.one.work = n_jit * tiles;
         pj.total = pj.one.work;
+        if (ej0) hipEventRecord(ej0, s);
         *err = launch_jit<R>(p, pass_idx, pj, s);
+        if (ej1) hipEventRecord(ej1, s);
         (*launches)++;
     }
     if (n_jit < t.ccount) {
@@ -1117,7 +1174,8 @@ struct Capture {
 // host image of the workspace whose first byte is workspace offset `base`.
 template <typename R>
 static void pack_meta(const tqs_plan *p, const tqs_noise *nz, const HostMeta &hm,
-                      const std::vector<uint32_t> &sched, const Layout &Ly, unsigned char *hb, uint64_t base) {
+                      const std::vector<uint32_t> &sched, const Layout &Ly, unsigned char *hb, uint64_t base,
+                      const FrameTables *ftab = nullptr) {
     auto put = [&](uint64_t off, const void *src, size_t bytes) {
         if (bytes) std::memcpy(hb + (off - base), src, bytes);
     };
@@ -1139,6 +1197,15 @@ static void pack_meta(const tqs_plan *p, const tqs_noise *nz, const HostMeta &hm
     put(Ly.off_leaffx, hm.leaf_fx.data(), hm.leaf_fx.size() * 4);
     put(Ly.off_flip, nz->leaf_flip.data(), nz->leaf_flip.size() * 4);  // zeros when absent
     put(Ly.off_sched, sched.data(), sched.size() * 4);
+    if (ftab) {
+        put(Ly.off_ctoff, ftab->ct_off.data(), ftab->ct_off.size() * 4);
+        std::vector<cplx<R>> t(ftab->tab.size());
+        for (size_t i = 0; i < t.size(); i++) t[i] = {(R)ftab->tab[i].real(), (R)ftab->tab[i].imag()};
+        put(Ly.off_ctab, t.data(), t.size() * sizeof(cplx<R>));
+    } else {
+        std::vector<uint32_t> none(p->n_nodes, 0xFFFFFFFFu);
+        put(Ly.off_ctoff, none.data(), none.size() * 4);
+    }
 }
 
 // A roctx range open for the lifetime of the object (every return path).
@@ -1180,15 +1247,16 @@ static tqs_status run_t(tqs_plan *p, const tqs_noise *nz, unsigned char *ws, uin
         if (js) return js;
     }
     std::vector<std::vector<Route>> routes;
-    route_passes(p, hm, tasks, &sched, &routes);
-    Layout Ly = make_layout(p, nz->ev_gate.size(), n_out, sched.size());
+    FrameTables ftab;
+    route_passes(p, hm, tasks, &sched, &routes, &ftab);
+    Layout Ly = make_layout(p, nz->ev_gate.size(), n_out, sched.size(), 0, ~0ull, ftab.tab.size());
     if (ws_bytes < Ly.total)
         return fail(TQS_E_WORKSPACE, "workspace has %llu bytes, the run needs %llu",
                     (unsigned long long)ws_bytes, (unsigned long long)Ly.total);
 
     // pack the metadata exactly as laid out in the workspace
     std::vector<unsigned char> hb(Ly.off_sums - Ly.off_meta, 0);
-    pack_meta<R>(p, nz, hm, sched, Ly, hb.data(), Ly.off_meta);
+    pack_meta<R>(p, nz, hm, sched, Ly, hb.data(), Ly.off_meta, &ftab);
 
     size_t ev_i = 0;
     hipEvent_t e_begin = nullptr, e_end = nullptr;
@@ -1208,7 +1276,8 @@ static tqs_status run_t(tqs_plan *p, const tqs_noise *nz, unsigned char *ws, uin
     }
 
     uint64_t launches = 0, pass_launches = 0, pass_states = 0, bytes_passes = 0, bytes_sample = 0, merged = 0;
-    uint64_t jit_launches = 0, jit_states = 0;
+    uint64_t jit_launches = 0, jit_states = 0, bytes_jit = 0;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> jit_ev;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pass_ev, samp_ev;
     const uint64_t state_bytes = Ly.state_bytes;
     const uint32_t b = p->sample_b;
@@ -1229,20 +1298,32 @@ static tqs_status run_t(tqs_plan *p, const tqs_noise *nz, unsigned char *ws, uin
         for (uint32_t k = 0; k < lv.pass_count; k++) {
             uint32_t nl = 0;
             hipError_t le = hipSuccess;
+            hipEvent_t ej0 = nullptr, ej1 = nullptr;
+            if (stats) {
+                // the specialised launch of this pass, timed on its own
+                ej0 = pool_event(p, ev_i++);
+                ej1 = pool_event(p, ev_i++);
+                if (!ej0 || !ej1) return fail(TQS_E_HIP, "hipEventCreate failed");
+            }
             const uint32_t nj = launch_routed<R>(p, Ly, ws, s, t, lv.pass_begin + k, k == 0,
-                                                 routes[&t - tasks.data()][k], &nl, &le);
+                                                 routes[&t - tasks.data()][k], &nl, &le, ej0, ej1);
             HIP_TRY(le, "specialised pass kernel launch");
             launches += nl;
             pass_launches += nl;
+            pass_states += t.ccount;
+            const bool init = (k == 0 && t.level == 0);
+            const bool parts = p->samp_tiled && t.level == L - 1 && k + 1 == lv.pass_count;
+            // algorithmic bytes per computed state: one read and one write
+            // (write only for the generated |0..0>), plus its sampling partials
+            const uint64_t per_state =
+                state_bytes * (init ? 1 : 2) + (parts ? (8ull << (p->samp_nfree + p->samp_kv)) : 0ull);
+            bytes_passes += (uint64_t)t.ccount * per_state;
             if (nj) {
                 jit_launches++;
                 jit_states += nj;
+                bytes_jit += (uint64_t)nj * per_state;
+                if (stats) jit_ev.push_back({ej0, ej1});
             }
-            pass_states += t.ccount;
-            const bool init = (k == 0 && t.level == 0);
-            bytes_passes += (uint64_t)t.ccount * state_bytes * (init ? 1 : 2);
-            if (p->samp_tiled && t.level == L - 1 && k + 1 == lv.pass_count)
-                bytes_passes += (uint64_t)t.ccount * (8ull << (p->samp_nfree + p->samp_kv));
         }
         if (stats) {
             HIP_TRY(hipEventRecord(eb, s), "hipEventRecord");
@@ -1321,6 +1402,11 @@ static tqs_status run_t(tqs_plan *p, const tqs_noise *nz, unsigned char *ws, uin
         stats->nodes_merged = merged;
         stats->jit_launches = jit_launches;
         stats->jit_states = jit_states;
+        stats->bytes_jit = bytes_jit;
+        for (auto &pr : jit_ev) {
+            HIP_TRY(hipEventElapsedTime(&ms, pr.first, pr.second), "hipEventElapsedTime");
+            stats->ms_jit += ms;
+        }
         stats->ms_wall =
             std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }
@@ -1592,13 +1678,14 @@ tqs_status tqs_workspace_bytes(const tqs_plan *p, const tqs_noise *nz, uint64_t 
         Layout Ly0 = make_layout(p, nz->ev_gate.size(), p->n_leaves, 0);
         build_schedule(p, 0, p->arity[0], &tasks, &sched, Ly0.slot_base, p->tune.no_merge ? nullptr : &hm);
         std::vector<std::vector<Route>> routes;
-        route_passes(p, hm, tasks, &sched, &routes);
-        *bytes = make_layout(p, nz->ev_gate.size(), p->n_leaves, sched.size()).total;
+        FrameTables ftab;
+        route_passes(p, hm, tasks, &sched, &routes, &ftab);
+        *bytes = make_layout(p, nz->ev_gate.size(), p->n_leaves, sched.size(), 0, ~0ull, ftab.tab.size()).total;
         return TQS_OK;
     }
     uint64_t ev = 0;
     for (size_t l = 0; l < p->arity.size(); l++) ev += p->level_nodes[l] * (uint64_t)(p->cut[l + 1] - p->cut[l]);
-    Layout Ly = make_layout(p, ev, p->n_leaves, 6 * p->n_nodes + route_bound(p));
+    Layout Ly = make_layout(p, ev, p->n_leaves, 6 * p->n_nodes + route_bound(p), 0, ~0ull, table_bound(p));
     *bytes = Ly.total;
     return TQS_OK;
     TQS_GUARD_END

@@ -93,7 +93,8 @@ void ro_span(const tqs_plan *p, const OpDesc &o, uint32_t *first, uint32_t *last
     }
 }
 
-void emit_diag(std::string &s, const tqs_plan *p, const PassDesc &d, const OpDesc &o, bool c64) {
+void emit_diag(std::string &s, const tqs_plan *p, const PassDesc &d, const OpDesc &o, bool c64,
+               uint32_t &table_slot) {
     const uint32_t nterm = [&] {
         uint32_t n = o.n_fix + o.n_lane;
         for (uint32_t b = 0; b < kMaxRegBits; b++) n += o.n_fixreg[b] + o.n_lanereg[b];
@@ -206,7 +207,12 @@ void emit_diag(std::string &s, const tqs_plan *p, const PassDesc &d, const OpDes
         ro_span(p, o, &kf, &kl);
         appendf(s, "    { const uint32_t f = rf.at(%uu); const uint32_t fr = 0", kf);
         for (uint32_t i = 0; i < d.nr; i++) appendf(s, " | (((f >> %u) & 1u) << %u)", d.rq[i], i);
-        appendf(s, ";\n      apply_table<R, RB, 0x%08xu>(v, mats + %u, fr); }\n", o.tmask, o.mat);
+        // the plan's table at index j ^ fr, or the node's own table (frames
+        // applied, every entry used) at index j
+        appendf(s,
+                ";\n      apply_table<R, RB>(v, ft ? ft + %uu : mats + %u, ft ? 0u : fr, ft ? 0xFFFFFFFFu : 0x%08xu); }\n",
+                table_slot << d.nr, o.mat, o.tmask);
+        table_slot++;
     }
     s += "  }\n";
 }
@@ -282,9 +288,23 @@ void emit_pass(std::string &s, const tqs_plan *p, uint32_t pi) {
     s += "  const kptr<cplx<R>> mats = kconst(a.mats);\n"
          "  const LaneBits lb = lane_bits(w.L);\n"
          "  (void)lb;\n";
+    if (jit_table_entries(p, pi)) {
+        // the node's own frame tables for this pass, if it has them
+        appendf(s,
+                "  kptr<cplx<R>> ft = nullptr;\n"
+                "  { const uint32_t co = uni(kconst(a.meta.ct_off)[node]);\n"
+                "    if (co != 0xFFFFFFFFu) {\n"
+                "      const kptr<uint32_t> dir = kconst(a.meta.ct_dir);\n"
+                "      const uint32_t cnt = uni(dir[co]);\n"
+                "      for (uint32_t i = 0; i < cnt; i++)\n"
+                "        if (uni(dir[co + 1 + 2 * i]) == %uu) ft = kconst((const cplx<R> *)a.meta.ctab) + uni(dir[co + 2 + 2 * i]);\n"
+                "    } }\n",
+                pi);
+    }
+    uint32_t table_slot = 0;
     for (uint32_t oi = d.op_begin; oi < d.op_begin + d.op_count; oi++) {
         const OpDesc &o = p->ops[oi];
-        if (o.kind == OP_DIAGRUN) emit_diag(s, p, d, o, c64);
+        if (o.kind == OP_DIAGRUN) emit_diag(s, p, d, o, c64, table_slot);
         else emit_dense(s, o);
     }
     s += "  const gptr<cplx<R>> dst = (gptr<cplx<R>>)(a.states + (uint64_t)dst_s * a.slot_amps + w.base);\n";
@@ -419,16 +439,19 @@ void jit_runs(const tqs_plan *p, std::vector<std::vector<JitRun>> *runs) {
             r.ro_last = 0;
             if (o.has_t) ro_span(p, o, &r.ro_first, &r.ro_last);
             r.regmask = regmask;
+            r.op = oi;
             (*runs)[pi].push_back(r);
         }
     }
 }
 
-// Whether the specialised kernel of pass pi takes a node whose events (sorted
-// keys pos[0..n), X masks dx) are given.
-bool jit_eligible(const std::vector<JitRun> &runs, uint32_t pi, const uint32_t *pos, const uint32_t *dx,
-                  uint32_t n) {
+// How the specialised kernel of pass pi takes a node whose events (sorted
+// keys pos[0..n), X masks dx) are given: not at all (more than three events
+// inside a run), with its own frame tables (an X change on register qubits
+// between a run's register-only gates), or as is.
+JitFit jit_fit(const std::vector<JitRun> &runs, uint32_t pi, const uint32_t *pos, const uint32_t *dx, uint32_t n) {
     const uint32_t key = pi << 16;
+    bool tables = false;
     for (const JitRun &r : runs) {
         uint32_t inside = 0;
         for (uint32_t e = 0; e < n; e++) {
@@ -436,11 +459,48 @@ bool jit_eligible(const std::vector<JitRun> &runs, uint32_t pi, const uint32_t *
             if (k <= (key | r.s0) || k >= (key | r.s1)) continue;
             inside++;
             const uint32_t rel = (k & 0xFFFFu) - r.s0;
-            if (r.ro_first <= r.ro_last && rel > r.ro_first && rel <= r.ro_last && (dx[e] & r.regmask)) return false;
+            if (r.ro_first <= r.ro_last && rel > r.ro_first && rel <= r.ro_last && (dx[e] & r.regmask)) tables = true;
         }
-        if (inside > 3 || (inside && r.ngates >= 255)) return false;
+        if (inside > 3 || (inside && r.ngates >= 255)) return JIT_NO;
     }
-    return true;
+    return tables ? JIT_TABLES : JIT_YES;
+}
+
+uint32_t jit_table_entries(const tqs_plan *p, uint32_t pi) {
+    const PassDesc &d = p->passes[pi];
+    uint32_t n = 0;
+    for (uint32_t oi = d.op_begin; oi < d.op_begin + d.op_count; oi++)
+        if (p->ops[oi].kind == OP_DIAGRUN && p->ops[oi].has_t) n += 1u << d.nr;
+    return n;
+}
+
+void jit_frame_tables(const tqs_plan *p, uint32_t pi, uint32_t fx0, const uint32_t *pos, const uint32_t *dx,
+                      uint32_t n, std::vector<cd> *out) {
+    const PassDesc &d = p->passes[pi];
+    const uint32_t nt = 1u << d.nr;
+    for (uint32_t oi = d.op_begin; oi < d.op_begin + d.op_count; oi++) {
+        const OpDesc &o = p->ops[oi];
+        if (o.kind != OP_DIAGRUN || !o.has_t) continue;
+        const size_t at = out->size();
+        out->resize(at + nt, cd(1.0, 0.0));
+        for (uint32_t k = 0; k < o.ngates; k++) {
+            const DiagGate &g = p->dgates[o.gates + k];
+            const bool ro = g.role[0] == ROLE_REG && (g.nq == 1 || g.role[1] == ROLE_REG);
+            if (!ro) continue;
+            // the X frame this gate sees: every event up to its slot
+            const uint32_t gk = (pi << 16) | (o.slot0 + k);
+            uint32_t f = fx0;
+            for (uint32_t e = 0; e < n && pos[e] <= gk; e++) f ^= dx[e];
+            uint32_t fr = 0;
+            for (uint32_t i = 0; i < d.nr; i++) fr |= ((f >> d.rq[i]) & 1u) << i;
+            for (uint32_t t = 0; t < nt; t++) {
+                const uint32_t y = t ^ fr;
+                uint32_t r = 0;
+                for (uint32_t q = 0; q < g.nq; q++) r |= ((y >> g.pos[q]) & 1u) << q;
+                (*out)[at + t] *= p->mats[g.d + r];
+            }
+        }
+    }
 }
 
 }  // namespace tqs

@@ -323,14 +323,14 @@ __device__ __forceinline__ LaneBits lane_bits(uint32_t L) {
 __device__ __forceinline__ uint32_t masked(uint32_t c, uint32_t m) { return c & m; }
 __device__ __forceinline__ uint64_t masked(uint64_t c, uint32_t m) { return c & (uint64_t)(int64_t)(int32_t)m; }
 
-// The run's register-only gates: table T (2^NR entries, index y = j ^ fr);
-// entries that are exactly 1 are skipped (TMASK, for NR <= 5).
-template <typename R, int RB, uint32_t TMASK>
-__device__ __forceinline__ void apply_table(cplx<R> (&v)[1 << RB], kptr<cplx<R>> T, uint32_t fr) {
+// The run's register-only gates: table T (2^RB entries, index j ^ fr);
+// entries whose bit in tmask is clear are exactly 1 and skipped (RB <= 5).
+template <typename R, int RB>
+__device__ __forceinline__ void apply_table(cplx<R> (&v)[1 << RB], kptr<cplx<R>> T, uint32_t fr, uint32_t tmask) {
     sfor<(1 << RB)>([&](auto Jc) __attribute__((always_inline)) {
         constexpr int j = decltype(Jc)::value;
         const uint32_t t = (uint32_t)j ^ fr;
-        if (RB > 5 || ((TMASK >> t) & 1u)) v[j] = cmul(T[t], v[j]);
+        if (RB > 5 || ((tmask >> t) & 1u)) v[j] = cmul(T[t], v[j]);
     });
 }
 

@@ -66,6 +66,12 @@ struct NodeMeta {
     const uint32_t *ev_pos;  // (pass << 16) | position of the first op that sees it
     const uint32_t *ev_dx;
     const uint32_t *ev_dz;
+    // frame tables (specialised kernels): per node ~0u, or the offset in
+    // ct_dir of [count, (pass, first ctab entry) x count]: for those passes
+    // the node's register-only phase tables with its own frames applied
+    const uint32_t *ct_off;
+    const uint32_t *ct_dir;
+    const void *ctab;  // cplx<R> entries
 };
 
 

@@ -111,15 +111,24 @@ struct JitRun {
     uint32_t s0, s1, ngates;
     uint32_t ro_first, ro_last;  // register-only gates' index span (first > last: none)
     uint32_t regmask;            // physical positions of the pass's register qubits
+    uint32_t op;                 // the run's op index
 };
+// How a pass's specialised kernel takes a node.
+enum JitFit { JIT_NO = 0, JIT_YES = 1, JIT_TABLES = 2 /* with its own frame tables */ };
+// Frame tables of one node for pass pi: every table run of the pass, in
+// order, 2^nr entries each, with the node's frames at each register-only
+// gate applied.  pos/dx/n: the node's events; fx0: its X frame at node start.
+void jit_frame_tables(const tqs_plan *p, uint32_t pi, uint32_t fx0, const uint32_t *pos, const uint32_t *dx,
+                      uint32_t n, std::vector<cd> *out);
+// Table entries of pass pi for one node (0 when the pass has no table run).
+uint32_t jit_table_entries(const tqs_plan *p, uint32_t pi);
 bool jit_pass_supported(const tqs_plan *p, uint32_t pi);
 std::string jit_source(const tqs_plan *p);
 tqs_status jit_compile(tqs_plan *p);
 tqs_status jit_prepare(tqs_plan *p);
 void jit_release(tqs_plan *p);
 void jit_runs(const tqs_plan *p, std::vector<std::vector<JitRun>> *runs);
-bool jit_eligible(const std::vector<JitRun> &runs, uint32_t pi, const uint32_t *pos, const uint32_t *dx,
-                  uint32_t n);
+JitFit jit_fit(const std::vector<JitRun> &runs, uint32_t pi, const uint32_t *pos, const uint32_t *dx, uint32_t n);
 
 // planner helpers shared with the executor
 uint64_t level_nodes(const std::vector<uint64_t> &A, uint32_t l);

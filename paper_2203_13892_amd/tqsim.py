@@ -37,7 +37,7 @@ class TqsRunStats(C.Structure):
     _fields_ = [("ms_wall", dbl), ("ms_device", dbl), ("ms_passes", dbl), ("ms_sample", dbl),
                 ("launches", u64), ("pass_launches", u64), ("pass_states", u64), ("bytes_passes", u64),
                 ("bytes_sample", u64), ("events", u64), ("nodes_merged", u64), ("jit_launches", u64),
-                ("jit_states", u64)]
+                ("jit_states", u64), ("bytes_jit", u64), ("ms_jit", dbl)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
