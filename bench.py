@@ -23,7 +23,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
-TRAFFIC_JSON = os.path.join(ROOT, "profiles", "pass_kernel_qft20_tree16x32x32_traffic.json")
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "tqs_jit_pass_qft20_tree16x32x32_traffic.json")
 
 
 def profiled_record():
@@ -432,7 +432,7 @@ def main():
     ap.add_argument("--chunk", type=int, default=0, help="live states per level (0 = default)")
     ap.add_argument("--no-fidelity", action="store_true",
                     help="skip the tree's fidelity loss against per-shot sampling")
-    ap.add_argument("--fid-seeds", type=int, default=10)
+    ap.add_argument("--fid-seeds", type=int, default=20)
     ap.add_argument("--batch", action="store_true",
                     help="also run the 512-circuit mixed workload one run at a time and batched")
     ap.add_argument("--learned", action="store_true",
