@@ -345,6 +345,41 @@ def batch_bench(T, W, torch, seed, shots=2048, budget_gib=32):
     return rec
 
 
+def mfma_sweep(T, W, torch, steps=3, shots=4096):
+    """Fused 32x32 blocks on the matrix cores against the vector units: a
+    20-qubit circuit of k Haar SU(4) gates on random pairs of qubits 6..10
+    (the tile's register window; seed 5), noiseless, every state computed,
+    one pass; per k the rate with tuning.mfma_min_ops 1000 (off) and 1."""
+    import numpy as np
+    rng = np.random.default_rng(5)
+    out = []
+    for k in (4, 8, 16, 32):
+        wc = W.Circuit(20)
+        for _ in range(k):
+            a, b = rng.choice(np.arange(6, 11), 2, replace=False)
+            wc.add((int(a), int(b)), W.haar_unitary(4, rng))
+        c = T.Circuit.from_workload(wc)
+        tree = ([shots], [0, len(wc)])
+        nz = T.Noise.sample(c, tree, 0)
+        rec = {"su4_gates": k}
+        for name, mm in (("vector", 1000), ("mfma", 1)):
+            plan = T.Plan(c, tree, "c64", {"mfma_min_ops": mm, "pass_cost": 100000, "no_merge": 1})
+            ws = T.Workspace(plan.workspace_bytes(nz))
+            T.run(plan, nz, ws)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                T.run(plan, nz, ws)
+            torch.cuda.synchronize()
+            rec[name + "_shots_per_s"] = shots * steps / (time.perf_counter() - t0)
+            del ws
+        rec["mfma_speedup"] = rec["mfma_shots_per_s"] / rec["vector_shots_per_s"]
+        print("# mfma: %d SU(4): vector %.1fK shots/s, fused block on MFMA %.1fK shots/s" %
+              (k, rec["vector_shots_per_s"] / 1e3, rec["mfma_shots_per_s"] / 1e3), file=sys.stderr, flush=True)
+        out.append(rec)
+    return out
+
+
 def parity_sample(T, wc, tree, seed, count=16):
     """The headline run against the oracle on `count` leaves spread over the
     tree: max-abs amplitude error (complex64 against complex128) and how many
@@ -442,6 +477,9 @@ def main():
                     help="also run the 26-qubit complex64 / complex128 precision sweep")
     ap.add_argument("--no-bw", action="store_true",
                     help="skip the 20-qubit brick-wall forms (reported beside the QFT ones)")
+    ap.add_argument("--mfma-sweep", action="store_true",
+                    help="only compare fused 32x32 blocks on the matrix cores with the vector units "
+                         "on register-local SU(4) circuits, and print that record")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path "
@@ -456,6 +494,9 @@ def main():
     from paper_2203_13892_amd import workloads as W
 
     torch.cuda.set_device(0)
+    if args.mfma_sweep:
+        print(json.dumps({"mfma_sweep": mfma_sweep(T, W, torch, args.steps)}), flush=True)
+        return
     shots = 16384
     wc = W.qft(20).with_depolarizing(1e-3, 1e-2)
     G = len(wc)

@@ -110,6 +110,14 @@ typedef struct {
                                   with the plan): 1 on, 2 off.  Default 0: on for states of
                                   2^16 amplitudes or more.  Same results either way; nodes a
                                   specialised kernel does not take run in the generic one */
+    uint32_t mfma_min_ops;     /* specialised complex64 kernels with full 11-qubit tiles: runs
+                                  of at least this many consecutive dense ops on the five
+                                  register qubits become one 32x32 unitary (FP64 product, cast
+                                  once) applied on the matrix cores (MFMA).  0: the default
+                                  (6: the block costs about as much as five two-qubit gates
+                                  on the vector units); 1000 or more: off.  Nodes with a noise
+                                  event between the ops of such a run go to the generic
+                                  kernel */
 } tqs_tuning;
 
 /* Timing and traffic of one run. */
@@ -242,6 +250,8 @@ tqs_status tqs_workspace_bytes(const tqs_plan *p, const tqs_noise *nz, uint64_t 
  *   pass <p> <op count> regs <register positions...>
  *   dense <arity> <phys q0> <phys q1> <slot0> <slot1> | <row-major matrix, re im ...>
  *   diag <slot0> <slot1> | <arity> <phys q0> <phys q1> <diagonal, re im ...> | ...
+ *   block <pass> <first op> <end op>   (global op indices fused into one 32x32 unitary
+ *        that the specialised kernel applies on the matrix cores; tuning.mfma_min_ops)
  *   sampling <tiled> <pattern bits> <tile bits> <in-block tile bits> <summed bits> | <source
  *        of each block-index bit: 128 + pattern bit, or tile bit>  (tiled = 1: the last
  *        leaf pass writes per-tile partial masses, lane positions first, then registers)

@@ -927,7 +927,8 @@ static void route_passes(const tqs_plan *p, const HostMeta &hm, const std::vecto
     ft->ct_off.assign(p->n_nodes, 0xFFFFFFFFu);
     if (p->tune.jit != 1) return;
     std::vector<std::vector<JitRun>> runs;
-    jit_runs(p, &runs);
+    std::vector<std::vector<JitBlock>> blks;
+    jit_runs(p, &runs, &blks);
     std::vector<uint32_t> yes, no;
     // per node with frame tables: (pass, first entry) pairs
     std::vector<std::pair<uint32_t, std::vector<std::pair<uint32_t, uint32_t>>>> dirs;
@@ -945,7 +946,8 @@ static void route_passes(const tqs_plan *p, const HostMeta &hm, const std::vecto
             for (uint32_t c = 0; c < t.ccount; c++) {
                 const uint32_t node = (*sched)[t.cnode() + c];
                 const uint32_t e0 = hm.ev_off[node], e1 = hm.ev_off[node + 1];
-                const JitFit fit = jit_fit(runs[pi], pi, hm.ev_pos.data() + e0, hm.ev_dx.data() + e0, e1 - e0);
+                const JitFit fit =
+                    jit_fit(runs[pi], blks[pi], pi, hm.ev_pos.data() + e0, hm.ev_dx.data() + e0, e1 - e0);
                 if (fit == JIT_NO) {
                     no.push_back(c);
                     continue;

@@ -302,8 +302,22 @@ void emit_pass(std::string &s, const tqs_plan *p, uint32_t pi) {
                 pi);
     }
     uint32_t table_slot = 0;
+    size_t bi = 0;
+    while (bi < p->blocks.size() && p->blocks[bi].pass < pi) bi++;
     for (uint32_t oi = d.op_begin; oi < d.op_begin + d.op_count; oi++) {
         const OpDesc &o = p->ops[oi];
+        if (bi < p->blocks.size() && p->blocks[bi].pass == pi && p->blocks[bi].op_begin == oi) {
+            // a fused register-only run on the matrix cores; the frame's
+            // register bits conjugate it
+            const FusedBlock &fb = p->blocks[bi++];
+            appendf(s, "  advance(w, KEY | %uu);\n  { const uint32_t xr = 0", (unsigned)o.slot0);
+            for (uint32_t i = 0; i < d.nr; i++) appendf(s, " | (((w.fx >> %u) & 1u) << %u)", d.rq[i], i);
+            s += ", zr = 0";
+            for (uint32_t i = 0; i < d.nr; i++) appendf(s, " | (((w.fz >> %u) & 1u) << %u)", d.rq[i], i);
+            appendf(s, ";\n    mfma32(v, mats + %u, xr, zr, w.L); }\n", fb.mat);
+            oi = fb.op_end - 1;
+            continue;
+        }
         if (o.kind == OP_DIAGRUN) emit_diag(s, p, d, o, c64, table_slot);
         else emit_dense(s, o);
     }
@@ -422,8 +436,16 @@ void jit_release(tqs_plan *p) {
 }
 
 // Per pass, the phase runs' slots and register-only spans (for routing).
-void jit_runs(const tqs_plan *p, std::vector<std::vector<JitRun>> *runs) {
+void jit_runs(const tqs_plan *p, std::vector<std::vector<JitRun>> *runs,
+              std::vector<std::vector<JitBlock>> *blocks) {
     runs->assign(p->passes.size(), {});
+    blocks->assign(p->passes.size(), {});
+    for (const FusedBlock &fb : p->blocks) {
+        JitBlock b;
+        b.first = (fb.pass << 16) | p->ops[fb.op_begin].slot0;
+        b.last = (fb.pass << 16) | p->ops[fb.op_end - 1].slot0;
+        (*blocks)[fb.pass].push_back(b);
+    }
     for (uint32_t pi = 0; pi < (uint32_t)p->passes.size(); pi++) {
         const PassDesc &d = p->passes[pi];
         uint32_t regmask = 0;
@@ -446,12 +468,17 @@ void jit_runs(const tqs_plan *p, std::vector<std::vector<JitRun>> *runs) {
 }
 
 // How the specialised kernel of pass pi takes a node whose events (sorted
-// keys pos[0..n), X masks dx) are given: not at all (more than three events
-// inside a run), with its own frame tables (an X change on register qubits
+// keys pos[0..n), X masks dx) are given: not at all (an event between the
+// ops of a fused block, or more than three inside a run), with its own frame tables (an X change on register qubits
 // between a run's register-only gates), or as is.
-JitFit jit_fit(const std::vector<JitRun> &runs, uint32_t pi, const uint32_t *pos, const uint32_t *dx, uint32_t n) {
+JitFit jit_fit(const std::vector<JitRun> &runs, const std::vector<JitBlock> &blocks, uint32_t pi,
+              const uint32_t *pos, const uint32_t *dx, uint32_t n) {
     const uint32_t key = pi << 16;
     bool tables = false;
+    // an event between the ops of a fused block
+    for (const JitBlock &b : blocks)
+        for (uint32_t e = 0; e < n; e++)
+            if (pos[e] > b.first && pos[e] <= b.last) return JIT_NO;
     for (const JitRun &r : runs) {
         uint32_t inside = 0;
         for (uint32_t e = 0; e < n; e++) {

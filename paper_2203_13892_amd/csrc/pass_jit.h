@@ -253,6 +253,76 @@ __device__ __forceinline__ void d2(cplx<R> (&v)[1 << RB], kptr<cplx<R>> G, uint3
     }
 }
 
+// ------------------------------------------------------ fused 32x32 (MFMA) --
+// A unitary on the tile's five register qubits (complex64), fused from
+// consecutive register-only dense ops, applied on the matrix cores with
+// v_mfma_f32_32x32x2_f32.  Out = U_F V with V the tile as a 32 x 64 matrix
+// (register index x lane) and U_F = F^dagger U F for the frame's register
+// bits (x, z): U_F[r][c] = U[r ^ x][c ^ x] (-1)^{z.r + z.c}.
+//   B operand (K = 2, N = 32): lane l holds B[l / 32][l % 32].  Swapping
+//   the upper lanes of register 2s with the lower lanes of register 2s+1
+//   (v_permlane32_swap) gives the operands of input rows (2s, 2s+1) for
+//   columns 0-31 and 32-63.
+//   A operand (M = 32, K = 2): lane l holds A[l % 32][l / 32], i.e.
+//   U_F[l % 32][2s + l / 32], read from the plan's row-major U.
+//   Result: accumulator r of lane l is row 8 (r / 4) + 4 (l / 32) + r % 4 of
+//   column l % 32; swapping the halves of the two column blocks' registers
+//   puts every lane's own column back in its registers.
+// Complex products as four real ones per step: re += Ur Vr - Ui Vi,
+// im += Ur Vi + Ui Vr.  128 MFMAs, 64 lane swaps and 16 loads per lane.
+typedef float mfma_v16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ void mfma32(cplx<float> (&v)[32], kptr<cplx<float>> U, uint32_t x, uint32_t z,
+                                       uint32_t L) {
+    const uint32_t m = L & 31u, h = L >> 5;
+    const uint32_t row = (m ^ x) * 32u;
+    const uint32_t sr = (uint32_t)__builtin_popcount(z & m) & 1u;
+    // the lane's A entries for the 16 K steps (loads first)
+    cplx<float> a[16];
+#pragma unroll
+    for (uint32_t s = 0; s < 16; s++) a[s] = U[row + ((2u * s + h) ^ x)];
+    // B operands
+    uint32_t br[32], bi[32];
+#pragma unroll
+    for (uint32_t s = 0; s < 16; s++) {
+        const auto pr = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[2 * s].re), __float_as_uint(v[2 * s + 1].re),
+                                                         false, false);
+        const auto pi = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[2 * s].im), __float_as_uint(v[2 * s + 1].im),
+                                                         false, false);
+        br[2 * s] = pr[0];
+        br[2 * s + 1] = pr[1];
+        bi[2 * s] = pi[0];
+        bi[2 * s + 1] = pi[1];
+    }
+    mfma_v16 re0 = {0}, im0 = {0}, re1 = {0}, im1 = {0};
+#pragma unroll
+    for (uint32_t s = 0; s < 16; s++) {
+        // frame signs of entry (m, 2s + h)
+        const uint32_t sg = (sr ^ ((uint32_t)__builtin_popcount(z & (2u * s + h)) & 1u)) << 31;
+        const float ar = __uint_as_float(__float_as_uint(a[s].re) ^ sg);
+        const float ai = __uint_as_float(__float_as_uint(a[s].im) ^ sg);
+        const float an = -ai;
+        const float b0r = __uint_as_float(br[2 * s]), b0i = __uint_as_float(bi[2 * s]);
+        const float b1r = __uint_as_float(br[2 * s + 1]), b1i = __uint_as_float(bi[2 * s + 1]);
+        re0 = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, b0r, re0, 0, 0, 0);
+        re0 = __builtin_amdgcn_mfma_f32_32x32x2f32(an, b0i, re0, 0, 0, 0);
+        im0 = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, b0i, im0, 0, 0, 0);
+        im0 = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, b0r, im0, 0, 0, 0);
+        re1 = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, b1r, re1, 0, 0, 0);
+        re1 = __builtin_amdgcn_mfma_f32_32x32x2f32(an, b1i, re1, 0, 0, 0);
+        im1 = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, b1i, im1, 0, 0, 0);
+        im1 = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, b1r, im1, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 16; r++) {
+        const auto qr = __builtin_amdgcn_permlane32_swap(__float_as_uint(re0[r]), __float_as_uint(re1[r]), false, false);
+        const auto qi = __builtin_amdgcn_permlane32_swap(__float_as_uint(im0[r]), __float_as_uint(im1[r]), false, false);
+        const int lo = 8 * (r / 4) + r % 4;
+        v[lo] = cplx<float>{__uint_as_float(qr[0]), __uint_as_float(qi[0])};
+        v[lo + 4] = cplx<float>{__uint_as_float(qr[1]), __uint_as_float(qi[1])};
+    }
+}
+
 // ------------------------------------------------------------ phase runs --
 // Events strictly inside a run (at most three; the executor routes nodes
 // with more to the generic kernel): the frame a gate of the run sees, by

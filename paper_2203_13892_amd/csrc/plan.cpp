@@ -148,6 +148,7 @@ extern "C" tqs_status tqs_plan_create(const tqs_circuit *c, const tqs_tree *tree
     if (!tu.pass_cost) tu.pass_cost = 480;
     if (tu.jit > 2) return fail(TQS_E_ARG, "jit must be 0 (default), 1 (on) or 2 (off)");
     if (!tu.jit) tu.jit = c->n >= 16 ? 1u : 2u;
+    if (!tu.mfma_min_ops) tu.mfma_min_ops = 6;
     const uint32_t tmax = prec == TQS_C64 ? 12 : 11;
     if (tu.tile_qubits < 10 || tu.tile_qubits > tmax)
         return fail(TQS_E_ARG, "tile_qubits must be in 10..%u at this precision", tmax);
@@ -569,10 +570,76 @@ extern "C" tqs_status tqs_plan_create(const tqs_circuit *c, const tqs_tree *tree
     }
     for (uint32_t l = 0; l < L; l++)
         p->chunk.push_back((uint32_t)std::min<uint64_t>(p->level_nodes[l], tu.chunk_states));
+    if (tu.jit == 1 && prec == TQS_C64 && tu.mfma_min_ops < 1000) fuse_blocks(p, tu.mfma_min_ops);
     *out = p;
     return TQS_OK;
     TQS_GUARD_END
 }
+
+namespace tqs {
+
+// Register-only dense ops of full complex64 tiles with five register qubits,
+// fused in runs of consecutive ops: U = U_last ... U_first, each op's
+// matrix embedded in the 32-dimensional register space (FP64).
+void fuse_blocks(tqs_plan *p, uint32_t min_ops) {
+    for (uint32_t pi = 0; pi < (uint32_t)p->passes.size(); pi++) {
+        const PassDesc &d = p->passes[pi];
+        if (d.nr != 5 || d.nl != kLaneBits) continue;
+        auto fusable = [&](const OpDesc &o) {
+            if (o.kind == OP_DIAGRUN) return false;
+            for (uint32_t q = 0; q < o.nq; q++)
+                if (o.role[q] != ROLE_REG) return false;
+            return true;
+        };
+        uint32_t oi = d.op_begin;
+        const uint32_t oe = d.op_begin + d.op_count;
+        while (oi < oe) {
+            if (!fusable(p->ops[oi])) {
+                oi++;
+                continue;
+            }
+            uint32_t oj = oi;
+            while (oj < oe && fusable(p->ops[oj])) oj++;
+            if (oj - oi >= min_ops) {
+                std::vector<cd> U(32 * 32, cd(0.0, 0.0)), T(32 * 32);
+                for (uint32_t r = 0; r < 32; r++) U[r * 32 + r] = cd(1.0, 0.0);
+                for (uint32_t k = oi; k < oj; k++) {
+                    const OpDesc &o = p->ops[k];
+                    const uint32_t nd = 1u << o.nq;
+                    uint32_t mask = 0;
+                    for (uint32_t q = 0; q < o.nq; q++) mask |= 1u << o.pos[q];
+                    auto loc = [&](uint32_t r) {
+                        uint32_t x = 0;
+                        for (uint32_t q = 0; q < o.nq; q++) x |= ((r >> o.pos[q]) & 1u) << q;
+                        return x;
+                    };
+                    // T = G U, G the op embedded (identity on the other bits)
+                    for (uint32_t r = 0; r < 32; r++)
+                        for (uint32_t c = 0; c < 32; c++) {
+                            cd acc(0.0, 0.0);
+                            for (uint32_t b = 0; b < nd; b++) {
+                                uint32_t m = r & ~mask;
+                                for (uint32_t q = 0; q < o.nq; q++) m |= ((b >> q) & 1u) << o.pos[q];
+                                acc += p->mats[o.mat + loc(r) * nd + b] * U[m * 32 + c];
+                            }
+                            T[r * 32 + c] = acc;
+                        }
+                    U.swap(T);
+                }
+                FusedBlock fb;
+                fb.pass = pi;
+                fb.op_begin = oi;
+                fb.op_end = oj;
+                fb.mat = (uint32_t)p->mats.size();
+                p->mats.insert(p->mats.end(), U.begin(), U.end());
+                p->blocks.push_back(fb);
+            }
+            oi = oj;
+        }
+    }
+}
+
+}  // namespace tqs
 
 extern "C" tqs_status tqs_plan_info(const tqs_plan *p, uint32_t level, uint32_t *passes_level,
                                     uint32_t *passes_total, uint32_t *chunk_states) {
@@ -630,6 +697,7 @@ extern "C" tqs_status tqs_plan_describe(const tqs_plan *p, char *buf, uint64_t c
             s += "\n";
         }
     }
+    for (const FusedBlock &fb : p->blocks) put("block %u %u %u\n", fb.pass, fb.op_begin, fb.op_end);
     put("sampling %u %u %u %u %u |", p->samp_tiled, p->samp_kv, p->samp_nfree, p->samp_tfree, p->samp_psum);
     for (uint32_t q = p->sample_b; q < p->n; q++) put(" %u", (uint32_t)p->samp_bsrc[q - p->sample_b]);
     s += "\n";

@@ -59,6 +59,13 @@ struct Level {
     uint32_t g0 = 0, g1 = 0;
 };
 
+// Consecutive dense ops [op_begin, op_end) of a pass on its five register
+// qubits, fused into one 32x32 unitary (mats[mat..mat+1024), row-major over
+// the register index) that the specialised kernel applies with MFMA.
+struct FusedBlock {
+    uint32_t pass, op_begin, op_end, mat;
+};
+
 }  // namespace tqs
 
 struct tqs_plan {
@@ -99,6 +106,7 @@ struct tqs_plan {
     std::vector<void *> events;  // hipEvent_t pool for run statistics
     // plan-specialised pass kernels (jit.cpp): code object, the module
     // loaded on jit_device, one function per pass (NULL: generic kernel)
+    std::vector<tqs::FusedBlock> blocks;  // sorted by pass, then op
     std::vector<char> jit_code;
     void *jit_module = nullptr;
     int jit_device = -1;
@@ -112,6 +120,10 @@ struct JitRun {
     uint32_t ro_first, ro_last;  // register-only gates' index span (first > last: none)
     uint32_t regmask;            // physical positions of the pass's register qubits
     uint32_t op;                 // the run's op index
+};
+// A fused block's slots: events at keys in (first, last] fall between its ops.
+struct JitBlock {
+    uint32_t first, last;
 };
 // How a pass's specialised kernel takes a node.
 enum JitFit { JIT_NO = 0, JIT_YES = 1, JIT_TABLES = 2 /* with its own frame tables */ };
@@ -127,8 +139,12 @@ std::string jit_source(const tqs_plan *p);
 tqs_status jit_compile(tqs_plan *p);
 tqs_status jit_prepare(tqs_plan *p);
 void jit_release(tqs_plan *p);
-void jit_runs(const tqs_plan *p, std::vector<std::vector<JitRun>> *runs);
-JitFit jit_fit(const std::vector<JitRun> &runs, uint32_t pi, const uint32_t *pos, const uint32_t *dx, uint32_t n);
+void jit_runs(const tqs_plan *p, std::vector<std::vector<JitRun>> *runs,
+              std::vector<std::vector<JitBlock>> *blocks);
+JitFit jit_fit(const std::vector<JitRun> &runs, const std::vector<JitBlock> &blocks, uint32_t pi,
+              const uint32_t *pos, const uint32_t *dx, uint32_t n);
+// Fuse the register-only dense runs of a complex64 plan (plan creation).
+void fuse_blocks(tqs_plan *p, uint32_t min_ops);
 
 // planner helpers shared with the executor
 uint64_t level_nodes(const std::vector<uint64_t> &A, uint32_t l);

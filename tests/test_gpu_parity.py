@@ -841,7 +841,7 @@ def test_random_configurations(T, seed):
     tuning = {"chunk_states": int(rng.integers(1, 8)), "tile_qubits": int(rng.choice([10, 11])),
               "sample_block_log": int(rng.integers(8, 13)), "separate_sampling": int(rng.integers(0, 2)),
               "no_merge": int(rng.integers(0, 2)), "pass_cost": int(rng.choice([120, 480])),
-              "jit": 1 + seed % 2}
+              "jit": 1 + seed % 2, "mfma_min_ops": (1, 2, 1000)[seed % 3]}
     arr = _repeating_events(wc, tree, rng, rate=float(rng.uniform(0.01, 0.1)))
     flips = rng.integers(0, 1 << n, arr[3].size).astype(np.uint32) if seed % 2 else None
     c = T.Circuit.from_workload(wc)
@@ -924,3 +924,39 @@ def test_specialised_kernels_match_generic(T, case):
     assert s1["jit_launches"] > 0 and s1["jit_states"] >= 0.5 * s1["pass_states"]
     assert np.max(np.abs(a1 - a2)) < 1e-6
     assert np.mean(o1 == o2) > 0.99
+
+
+@pytest.mark.parametrize("min_ops", [1, 2])
+@pytest.mark.parametrize("n", [11, 14])
+def test_fused_register_blocks_on_matrix_cores(T, n, min_ops):
+    # runs of dense ops on the five register qubits fused into 32x32
+    # unitaries and applied with MFMA (complex64): amplitudes and outcomes
+    # against the oracle, with events before, after and between the fused
+    # ops (nodes with events between them take the generic kernel), frames
+    # with X and Z parts on register qubits, and a lane exchange in between
+    rng = np.random.default_rng(300 + n + min_ops)
+    wc = W.Circuit(n)
+    for q in range(n):
+        wc.add((q,), W.haar_unitary(2, rng))
+    for layer in range(8):
+        for a in range(layer % 2, n - 1, 2):
+            wc.add((a, a + 1), W.haar_unitary(4, rng))
+        wc.add((int(rng.integers(n)),), W.haar_unitary(2, rng))
+    G = len(wc)
+    tree = ([4, 6], [0, G // 2, G])
+    c = T.Circuit.from_workload(wc)
+    plan = T.Plan(c, tree, "c64", {"jit": 1, "mfma_min_ops": min_ops})
+    blocks = [ln for ln in plan.describe().splitlines() if ln.startswith("block")]
+    assert blocks, "no fused block"
+    arr = event_arrays(wc, tree, rng, rate=0.04)
+    out, amps, oout, ost, _ = run_both(T, wc, tree, 0, "c64", np.arange(24), noise_arrays=arr,
+                                       tuning={"jit": 1, "mfma_min_ops": min_ops})
+    print("fused blocks", len(blocks), "max-abs %.3g" % np.max(np.abs(amps - ost)))
+    assert np.max(np.abs(amps - ost)) < TOL["c64"]
+    check_outcomes(out, oout, ost, arr[3], DELTA["c64"])
+    # the same list through the generic kernel only: equal outcomes
+    nz = T.Noise.from_arrays(c, tree, *arr)
+    base = T.run(T.Plan(c, tree, "c64", {"jit": 2}), nz)
+    fused, st = T.run(plan, nz, stats=True)
+    assert st["jit_launches"] > 0
+    assert np.mean(base == fused) > 0.9
