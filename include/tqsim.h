@@ -280,7 +280,14 @@ void tqs_plan_destroy(tqs_plan *p);
  * is sampled once).  d_workspace: device pointer, 256-byte aligned,
  * ws_bytes >= tqs_workspace_bytes.  stream: hipStream_t or NULL.  outcomes:
  * host array of n_leaves.  Stream-ordered; returns after the outcomes are on
- * the host.  stats may be NULL. */
+ * the host.  stats may be NULL.
+ * Errors: a run that fails after it enqueued device work waits for that work
+ * on the stream before it returns, so the workspace may be freed or reused at
+ * once and the plan stays valid (resume with tqs_run_range).  For tests of
+ * these paths the environment variable TQS_FAULT injects a failure on the
+ * host (no kernel is altered): "alloc" fails the run's host metadata
+ * allocation (TQS_E_OOM, before any device call); "launch:K" fails its K-th
+ * pass from 0 (TQS_E_HIP, after the passes before it were enqueued). */
 tqs_status tqs_run(tqs_plan *p, const tqs_noise *nz, void *d_workspace, uint64_t ws_bytes,
                    void *stream, uint64_t *outcomes, tqs_run_stats *stats);
 

@@ -16,6 +16,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -280,13 +281,38 @@ __global__ __launch_bounds__(kThreads) void block_gather_kernel(SampleLaunch<R> 
 // order xl, psi's block B_L is s's block B_L ^ (xl >> b) and inside it
 // index y is s's (y ^ xl) low bits, read at physical position P(.).  The
 // outcome is min { y : sum_{y' <= y} |psi_y'|^2 > u T } with FP64 sums.
+// Exclusive prefix of part[0..kThreads) into pre[], plus base, in a fixed
+// order (deterministic): an inclusive scan inside each wave by shuffles,
+// then the four wave totals in sequence.  Returns the total (base included)
+// to every thread.  All threads call it; part[] must be written before.
+__device__ __forceinline__ double block_scan(const double *part, double *pre, double base, double *wave_tot) {
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
+    double x = part[tid];
+#pragma unroll
+    for (uint32_t d = 1; d < 64; d <<= 1) {
+        const double y = __shfl_up(x, d);
+        if (lane >= d) x += y;
+    }
+    const double ex = __shfl_up(x, 1);  // exclusive: inclusive of lane - 1
+    if (lane == 63) wave_tot[wv] = x;
+    __syncthreads();
+    double off = base;
+    for (uint32_t w = 0; w < wv; w++) off += wave_tot[w];
+    pre[tid] = lane ? off + ex : off;
+    double tot = base;
+    for (uint32_t w = 0; w < kThreads / 64; w++) tot += wave_tot[w];
+    __syncthreads();
+    return tot;
+}
+
 template <typename R>
 __global__ __launch_bounds__(kThreads) void sample_kernel(SampleLaunch<R> sl) {
     __shared__ double part[kThreads];
     __shared__ uint32_t ptab[3][64];  // P of the in-block index, by 6-bit digit
     __shared__ double pre[kThreads];
+    __shared__ double wave_tot[kThreads / 64];
     __shared__ uint32_t hit;
-    __shared__ double tsh, cum_sh;
+    __shared__ double cum_sh;
     uint32_t k;
     const SampleArgs<R> &sa = sample_seg(sl, 2, blockIdx.x, &k);
     if (k >= sa.count) return;
@@ -323,16 +349,7 @@ __global__ __launch_bounds__(kThreads) void sample_kernel(SampleLaunch<R> sl) {
     part[tid] = s;
     if (tid == 0) hit = 0xFFFFFFFFu;
     __syncthreads();
-    if (tid == 0) {
-        double run = 0.0;
-        for (uint32_t i = 0; i < kThreads; i++) {
-            pre[i] = run;
-            run += part[i];
-        }
-        tsh = u * run;
-    }
-    __syncthreads();
-    const double t = tsh;
+    const double t = u * block_scan(part, pre, 0.0, wave_tot);
     {
         double run = pre[tid];
         for (uint32_t B = b0; B < b1; B++) {
@@ -399,14 +416,7 @@ __global__ __launch_bounds__(kThreads) void sample_kernel(SampleLaunch<R> sl) {
     }
     part[tid] = s;
     __syncthreads();
-    if (tid == 0) {
-        double run = cum_sh;
-        for (uint32_t i = 0; i < kThreads; i++) {
-            pre[i] = run;
-            run += part[i];
-        }
-    }
-    __syncthreads();
+    block_scan(part, pre, cum_sh, wave_tot);
     {
         double run = pre[tid];
         if (keep) {
@@ -1029,10 +1039,12 @@ static uint32_t launch_routed(const tqs_plan *p, const Layout &Ly, unsigned char
         pj.one.count = n_jit;
         pj.one.work = n_jit * tiles;
         pj.total = pj.one.work;
-        if (ej0) hipEventRecord(ej0, s);
-        *err = launch_jit<R>(p, pass_idx, pj, s);
-        if (ej1) hipEventRecord(ej1, s);
+        hipError_t e = ej0 ? hipEventRecord(ej0, s) : hipSuccess;
+        if (e == hipSuccess) e = launch_jit<R>(p, pass_idx, pj, s);
+        if (e == hipSuccess && ej1) e = hipEventRecord(ej1, s);
+        *err = e;
         (*launches)++;
+        if (e != hipSuccess) return n_jit;
     }
     if (n_jit < t.ccount) {
         if (n_jit) pl.one.perm = sched + r.perm + n_jit;
@@ -1218,6 +1230,44 @@ struct MarkerRange {
     MarkerRange &operator=(const MarkerRange &) = delete;
 };
 
+// Failure injection for tests of the error paths, set from the environment
+// and read on each run; host side only, no kernel is altered.
+//   TQS_FAULT=alloc     the host allocation of the run's metadata fails
+//                       (TQS_E_OOM) before any device call;
+//   TQS_FAULT=launch:K  the run's K-th pass (from 0) reports a launch
+//                       failure (TQS_E_HIP) after the passes before it
+//                       were enqueued ("launch" alone: K = 0).
+struct FaultSpec {
+    enum Kind { NONE, ALLOC, LAUNCH } kind = NONE;
+    uint64_t at = 0;
+};
+
+static FaultSpec fault_spec() {
+    FaultSpec f;
+    const char *e = std::getenv("TQS_FAULT");
+    if (!e || !*e) return f;
+    if (!std::strcmp(e, "alloc")) {
+        f.kind = FaultSpec::ALLOC;
+    } else if (!std::strncmp(e, "launch", 6) && (e[6] == 0 || e[6] == ':')) {
+        f.kind = FaultSpec::LAUNCH;
+        if (e[6] == ':') f.at = std::strtoull(e + 7, nullptr, 10);
+    }
+    return f;
+}
+
+// A run that fails after it enqueued device work waits for that work before
+// returning, so the caller may free or reuse the workspace at once.
+struct DrainOnError {
+    hipStream_t s;
+    bool armed = false;
+    explicit DrainOnError(hipStream_t st) : s(st) {}
+    ~DrainOnError() {
+        if (armed) (void)hipStreamSynchronize(s);
+    }
+    DrainOnError(const DrainOnError &) = delete;
+    DrainOnError &operator=(const DrainOnError &) = delete;
+};
+
 template <typename R>
 static tqs_status run_t(tqs_plan *p, const tqs_noise *nz, unsigned char *ws, uint64_t ws_bytes,
                         hipStream_t s, uint64_t first, uint64_t last, uint64_t *outcomes,
@@ -1237,6 +1287,8 @@ static tqs_status run_t(tqs_plan *p, const tqs_noise *nz, unsigned char *ws, uin
     const uint64_t leaf_first = first * per_subtree;
     const uint64_t n_out = (last - first) * per_subtree;
 
+    const FaultSpec fault = fault_spec();
+    if (fault.kind == FaultSpec::ALLOC) throw std::bad_alloc();
     HostMeta hm;
     build_meta(p, nz, &hm);
     std::vector<Task> tasks;
@@ -1260,6 +1312,8 @@ static tqs_status run_t(tqs_plan *p, const tqs_noise *nz, unsigned char *ws, uin
     std::vector<unsigned char> hb(Ly.off_sums - Ly.off_meta, 0);
     pack_meta<R>(p, nz, hm, sched, Ly, hb.data(), Ly.off_meta, &ftab);
 
+    DrainOnError drain(s);
+    drain.armed = true;
     size_t ev_i = 0;
     hipEvent_t e_begin = nullptr, e_end = nullptr;
     if (stats) {
@@ -1278,7 +1332,7 @@ static tqs_status run_t(tqs_plan *p, const tqs_noise *nz, unsigned char *ws, uin
     }
 
     uint64_t launches = 0, pass_launches = 0, pass_states = 0, bytes_passes = 0, bytes_sample = 0, merged = 0;
-    uint64_t jit_launches = 0, jit_states = 0, bytes_jit = 0;
+    uint64_t jit_launches = 0, jit_states = 0, bytes_jit = 0, pass_iter = 0;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> jit_ev;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pass_ev, samp_ev;
     const uint64_t state_bytes = Ly.state_bytes;
@@ -1307,6 +1361,9 @@ static tqs_status run_t(tqs_plan *p, const tqs_noise *nz, unsigned char *ws, uin
                 ej1 = pool_event(p, ev_i++);
                 if (!ej0 || !ej1) return fail(TQS_E_HIP, "hipEventCreate failed");
             }
+            if (fault.kind == FaultSpec::LAUNCH && pass_iter == fault.at)
+                HIP_TRY(hipErrorLaunchFailure, "pass launch (TQS_FAULT)");
+            pass_iter++;
             const uint32_t nj = launch_routed<R>(p, Ly, ws, s, t, lv.pass_begin + k, k == 0,
                                                  routes[&t - tasks.data()][k], &nl, &le, ej0, ej1);
             HIP_TRY(le, "specialised pass kernel launch");
@@ -1382,6 +1439,7 @@ static tqs_status run_t(tqs_plan *p, const tqs_noise *nz, unsigned char *ws, uin
         HIP_TRY(hipEventRecord(e_end, s), "hipEventRecord");
     }
     HIP_TRY(hipStreamSynchronize(s), "stream synchronize");
+    drain.armed = false;
     if (stats) {
         std::memset(stats, 0, sizeof *stats);
         float ms = 0;
@@ -1537,6 +1595,8 @@ static tqs_status batch_run_t(tqs_batch *B, unsigned char *ws, uint64_t ws_bytes
             }
         }
     }
+    DrainOnError drain(s);
+    drain.armed = true;
     HIP_TRY(hipMemcpyAsync(ws + B->table_at, tb.data(), tb.size(), hipMemcpyHostToDevice, s), "table upload");
     // the kernel arguments depend only on the batch and the workspace
     // address, so one recording serves every later run with that workspace
@@ -1601,6 +1661,7 @@ static tqs_status batch_run_t(tqs_batch *B, unsigned char *ws, uint64_t ws_bytes
                 "outcome download");
     if (stats) HIP_TRY(hipEventRecord(e1, s), "hipEventRecord");
     HIP_TRY(hipStreamSynchronize(s), "stream synchronize");
+    drain.armed = false;
     if (stats) {
         std::memset(stats, 0, sizeof *stats);
         float ms = 0;
@@ -1620,7 +1681,7 @@ static tqs_status batch_run_t(tqs_batch *B, unsigned char *ws, uint64_t ws_bytes
 using namespace tqs;
 
 tqs_plan::~tqs_plan() {
-    for (void *e : events) hipEventDestroy((hipEvent_t)e);
+    for (void *e : events) (void)hipEventDestroy((hipEvent_t)e);
     jit_release(this);
 }
 
@@ -1745,8 +1806,8 @@ tqs_status tqs_probe_copy(void *d_workspace, uint64_t bytes, uint32_t reps, void
     HIP_TRY(hipEventSynchronize(b), "hipEventSynchronize");
     float ms = 0;
     HIP_TRY(hipEventElapsedTime(&ms, a, b), "hipEventElapsedTime");
-    hipEventDestroy(a);
-    hipEventDestroy(b);
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
     *gbps = 2.0 * (double)bytes * reps / (ms * 1e-3) / 1e9;
     return TQS_OK;
     TQS_GUARD_END

@@ -417,7 +417,7 @@ tqs_status jit_prepare(tqs_plan *p) {
         std::snprintf(name, sizeof name, "tqs_jit_p%u", pi);
         hipFunction_t fn = nullptr;
         if (hipModuleGetFunction(&fn, mod, name) != hipSuccess) {
-            hipModuleUnload(mod);
+            (void)hipModuleUnload(mod);
             p->jit_fn.clear();
             return fail(TQS_E_HIP, "kernel %s missing from the compiled module", name);
         }
@@ -429,7 +429,7 @@ tqs_status jit_prepare(tqs_plan *p) {
 }
 
 void jit_release(tqs_plan *p) {
-    if (p->jit_module) hipModuleUnload((hipModule_t)p->jit_module);
+    if (p->jit_module) (void)hipModuleUnload((hipModule_t)p->jit_module);
     p->jit_module = nullptr;
     p->jit_fn.clear();
     p->jit_device = -1;

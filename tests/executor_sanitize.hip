@@ -127,10 +127,20 @@ int main(int argc, char **argv) {
         if (g() % 2) tu.chunk_states = 1 + g() % 9;
         if (g() % 2) tu.sample_block_log = 8 + g() % 5;
         tu.separate_sampling = g() % 2;
+        // specialised kernels: routing, frame tables and code generation
+        // (host side; nothing is compiled or loaded)
+        tu.jit = 1 + g() % 2;
+        if (g() % 2) tu.mfma_min_ops = 1 + g() % 8;
         tqs_plan *p = nullptr;
         if (tqs_plan_create(c, &tree, g() % 2 ? TQS_C64 : TQS_C128, &tu, &p) != TQS_OK) {
             tqs_circuit_destroy(c);
             continue;
+        }
+        if (tu.jit == 1) {
+            uint64_t len = 0;
+            CHECK(tqs_plan_jit_source(p, nullptr, 0, &len) == TQS_OK && len > 0);
+            std::vector<char> src(len);
+            CHECK(tqs_plan_jit_source(p, src.data(), len, &len) == TQS_OK && src[len - 1] == 0);
         }
         tqs_noise *nz = nullptr;
         if (tqs_noise_sample(c, &tree, g(), &nz) != TQS_OK) return 3;
@@ -150,10 +160,50 @@ int main(int argc, char **argv) {
             Layout Ly0 = make_layout(p, nz->ev_gate.size(), (last - first) * per, 0);
             build_schedule(p, first, last, &tasks, &sched, Ly0.slot_base, merge ? &hm : nullptr);
             check_schedule(p, merge ? &hm : nullptr, first, last, tasks, sched);
-            Layout Ly = make_layout(p, nz->ev_gate.size(), (last - first) * per, sched.size());
+            const size_t sched0 = sched.size();
+            std::vector<std::vector<Route>> routes;
+            FrameTables ftab;
+            route_passes(p, hm, tasks, &sched, &routes, &ftab);
+            CHECK(routes.size() == tasks.size());
+            CHECK(ftab.tab.size() <= table_bound(p));
+            for (size_t ti = 0; ti < tasks.size(); ti++) {
+                const Task &t = tasks[ti];
+                CHECK(routes[ti].size() == (p->tune.jit == 1 ? p->levels[t.level].pass_count : 0));
+                for (const Route &r : routes[ti]) {
+                    CHECK(r.n_jit <= t.ccount);
+                    if (r.perm == Route::kNoPerm) continue;
+                    // a permutation of the chunk's computed states
+                    CHECK(r.perm >= sched0 && r.perm + t.ccount <= sched.size());
+                    std::vector<char> seen(t.ccount, 0);
+                    for (uint32_t c = 0; c < t.ccount && r.perm + t.ccount <= sched.size(); c++) {
+                        const uint32_t v = sched[r.perm + c];
+                        CHECK(v < t.ccount && !seen[v]);
+                        if (v < t.ccount) seen[v] = 1;
+                    }
+                }
+            }
+            for (uint64_t nu = 0; nu < p->n_nodes; nu++) {
+                const uint32_t o = ftab.ct_off[nu];
+                if (o == 0xFFFFFFFFu) continue;
+                CHECK(o < sched.size());
+                const uint32_t cnt = o < sched.size() ? sched[o] : 0;
+                CHECK(o + 1 + 2ull * cnt <= sched.size());
+                for (uint32_t i = 0; i < cnt && o + 1 + 2ull * cnt <= sched.size(); i++) {
+                    CHECK(sched[o + 1 + 2 * i] < p->passes.size());
+                    CHECK(sched[o + 2 + 2 * i] < ftab.tab.size());
+                }
+            }
+            Layout Ly = make_layout(p, nz->ev_gate.size(), (last - first) * per, sched.size(), 0, ~0ull,
+                                    ftab.tab.size());
+            CHECK(sched.size() - sched0 <= route_bound(p));
+            // within what tqs_workspace_bytes promises: for any list, and for
+            // this list (whole runs share states unless the tuning says not to)
+            uint64_t bound = 0;
+            CHECK(tqs_workspace_bytes(p, nullptr, &bound) == TQS_OK && Ly.total <= bound);
+            if (merge != p->tune.no_merge) CHECK(tqs_workspace_bytes(p, nz, &bound) == TQS_OK && Ly.total <= bound);
             std::vector<unsigned char> hb(Ly.off_sums - Ly.off_meta, 0);
-            if (p->prec == TQS_C64) pack_meta<float>(p, nz, hm, sched, Ly, hb.data(), Ly.off_meta);
-            else pack_meta<double>(p, nz, hm, sched, Ly, hb.data(), Ly.off_meta);
+            if (p->prec == TQS_C64) pack_meta<float>(p, nz, hm, sched, Ly, hb.data(), Ly.off_meta, &ftab);
+            else pack_meta<double>(p, nz, hm, sched, Ly, hb.data(), Ly.off_meta, &ftab);
             runs++;
         }
         tqs_noise_destroy(nz);

@@ -13,6 +13,7 @@ import oracle
 from oracle import tree as otree
 from paper_2203_13892_amd import tqsim as T
 from paper_2203_13892_amd import workloads as W
+from paper_2203_13892_amd import build
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -472,8 +473,9 @@ def test_host_code_under_address_and_undefined_behaviour_sanitizers(tmp_path):
     assert "cases 300" in r.stdout
 def test_executor_host_steps_under_address_and_undefined_behaviour_sanitizers(tmp_path):
     # the executor's host side (frames and events per node, the chunk
-    # schedule with shared states and its key table, layout and metadata
-    # packing) on random circuits, trees, tunings and noise, with the
+    # schedule with shared states and its key table, the routing of states
+    # to the specialised kernels with their frame tables and generated
+    # source, layout and metadata packing) on random circuits, trees, tunings and noise, with the
     # schedule's invariants checked; built by hipcc with the sanitizers on
     # the host code only (the kernels are compiled but never launched)
     import subprocess
@@ -488,7 +490,8 @@ def test_executor_host_steps_under_address_and_undefined_behaviour_sanitizers(tm
            "-mllvm", "-simplifycfg-sink-common=false", "-Wno-unused-command-line-argument",
            "-I", os.path.join(ROOT, "include"), "-I", csrc,
            os.path.join(ROOT, "tests", "executor_sanitize.hip"), os.path.join(csrc, "plan.cpp"),
-           os.path.join(csrc, "host.cpp"), "-lrocprofiler-sdk-roctx", "-o", exe]
+           os.path.join(csrc, "host.cpp"), os.path.join(csrc, "jit.cpp"), "-I", os.path.dirname(build.write_jit_headers()),
+           "-lrocprofiler-sdk-roctx", "-lhiprtc", "-o", exe]
     subprocess.run(cmd, check=True, capture_output=True, timeout=900)
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=1:verify_asan_link_order=0")
     r = subprocess.run([exe, "2000"], capture_output=True, text=True, timeout=600, env=env)
