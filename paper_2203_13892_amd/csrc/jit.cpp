@@ -15,6 +15,7 @@
 #include <hip/hiprtc.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cinttypes>
 #include <cstdarg>
 #include <cstdio>
@@ -188,7 +189,15 @@ void emit_diag(std::string &s, const tqs_plan *p, const PassDesc &d, const OpDes
         for (int a = 0; a < 6; a++)
             for (int b = a + 1; b < 6; b++)
                 if (cll[a][b]) appendf(s, " + masked(cll%d_%d, lb.m[%d] & lb.m[%d])", a, b, a, b);
-        s += ";\n    A lam[RB];\n";
+        s += ";\n";
+        // C is zero in every lane when its scalar coefficients all are
+        s += "    const bool cz = uni((uint32_t)((c0";
+        for (int a = 0; a < 6; a++)
+            if (cl[a]) appendf(s, " | cl%d", a);
+        for (int a = 0; a < 6; a++)
+            for (int b = a + 1; b < 6; b++)
+                if (cll[a][b]) appendf(s, " | cll%d_%d", a, b);
+        s += ") == 0)) != 0u;\n    A lam[RB];\n";
         for (uint32_t i = 0; i < d.nr; i++) {
             if (!cr[i]) {
                 appendf(s, "    lam[%u] = 0;\n", i);
@@ -200,7 +209,7 @@ void emit_diag(std::string &s, const tqs_plan *p, const PassDesc &d, const OpDes
                 if (clr[a][i]) appendf(s, " + masked(clr%d_%u, lb.m[%d])", a, i, a);
             s += ";\n";
         }
-        appendf(s, "    apply_run_phase<R, RB>(v, C, lam, %uu);\n", lm);
+        appendf(s, "    run_phase<R, RB, %uu>(v, C, lam, cz);\n", lm);
     }
     if (o.has_t) {
         uint32_t kf = 0, kl = 0;
@@ -217,11 +226,36 @@ void emit_diag(std::string &s, const tqs_plan *p, const PassDesc &d, const OpDes
     s += "  }\n";
 }
 
-void emit_dense(std::string &s, const OpDesc &o) {
+// A one-qubit gate whose entries are all +-s (real, equal magnitudes): the
+// sign pattern (bit 2r + c set where entry (r, c) is negative) and s; -1
+// for any other op.
+int butterfly(const tqs_plan *p, const OpDesc &o, double *s) {
+    if (o.kind != OP_DENSE1 || o.nq != 1 || !o.real) return -1;
+    const cd *m = p->mats.data() + o.mat;
+    const double a = std::fabs(m[0].real());
+    if (!(a > 0.0)) return -1;
+    int neg = 0;
+    for (int e = 0; e < 4; e++) {
+        if (m[e].imag() != 0.0 || std::fabs(m[e].real()) != a) return -1;
+        if (m[e].real() < 0.0) neg |= 1 << e;
+    }
+    *s = a;
+    return neg;
+}
+
+void emit_dense(std::string &s, const tqs_plan *p, const OpDesc &o, double *scale) {
     appendf(s, "  advance(w, KEY | %uu);\n", (unsigned)o.slot0);
     appendf(s,
             "  { const uint32_t xl = local2(w.fx, %u, %u, %u), zl = local2(w.fz, %u, %u, %u);\n",
             o.phys[0], o.phys[1], o.nq, o.phys[0], o.phys[1], o.nq);
+    double bs = 0.0;
+    const int neg = butterfly(p, o, &bs);
+    if (neg >= 0) {
+        // its common factor joins the pass's scale
+        *scale *= bs;
+        appendf(s, "    bf<R, RB, %s, %u, %d>(v, xl, zl, w); }\n", role_name(o.role[0]), (unsigned)o.pos[0], neg);
+        return;
+    }
     if (o.kind == OP_DENSE1) {
         const uint32_t tq = o.nq == 2 ? o.tq : 0u, cq = 1u - tq;
         const uint32_t crole = o.nq == 2 ? o.role[cq] : 3u;
@@ -302,6 +336,7 @@ void emit_pass(std::string &s, const tqs_plan *p, uint32_t pi) {
                 pi);
     }
     uint32_t table_slot = 0;
+    double scale = 1.0;  // product of the butterflies' common factors
     size_t bi = 0;
     while (bi < p->blocks.size() && p->blocks[bi].pass < pi) bi++;
     for (uint32_t oi = d.op_begin; oi < d.op_begin + d.op_count; oi++) {
@@ -319,8 +354,9 @@ void emit_pass(std::string &s, const tqs_plan *p, uint32_t pi) {
             continue;
         }
         if (o.kind == OP_DIAGRUN) emit_diag(s, p, d, o, c64, table_slot);
-        else emit_dense(s, o);
+        else emit_dense(s, p, o, &scale);
     }
+    if (scale != 1.0) appendf(s, "  scale_tile<R, RB>(v, R(%.17g));\n", scale);
     s += "  const gptr<cplx<R>> dst = (gptr<cplx<R>>)(a.states + (uint64_t)dst_s * a.slot_amps + w.base);\n";
     for (uint32_t j = 0; j < nj; j++) {
         if (full) appendf(s, "  dst[%lluull + w.L] = v[%u];\n", (unsigned long long)reg_off(d, j), j);

@@ -177,6 +177,95 @@ __device__ __forceinline__ void d1(cplx<R> (&v)[1 << RB], kptr<cplx<R>> G, uint3
     }
 }
 
+// ---------------------------------------------------------- butterflies --
+// A one-qubit gate whose four entries are +-s (a Hadamard up to signs), as
+// the butterfly out_r = sum_c sigma_rc x_c without its common factor s: the
+// pass multiplies the tile by the product of these factors once, before it
+// stores it (scale_tile).  NEG: bit 2r + c set where sigma_rc = -1.  The
+// frame on the qubit conjugates the signs as conj_entry does a matrix,
+// sigma'_rc = sigma_{r^x, c^x} (-1)^{z r + z c}.  With no frame on the qubit
+// (the common case) the signs are compile-time: one add or subtract per
+// real output for a register target; for a lane target one multiply-add
+// (own value times a per-lane sign, plus or minus the partner's) where
+// the partner comes from the swizzle or permute unit.
+template <int NEG, int RR, int CC>
+struct Sgn {
+    static constexpr int value = ((NEG >> (2 * RR + CC)) & 1) ? -1 : 1;
+};
+
+template <typename R, int RB, int TROLE, int TPOS, int NEG>
+__device__ __forceinline__ void bf(cplx<R> (&v)[1 << RB], uint32_t xl, uint32_t zl, const Wave &w) {
+    constexpr int NJ = 1 << RB;
+    if ((xl | zl) == 0) {
+        constexpr int s00 = Sgn<NEG, 0, 0>::value, s01 = Sgn<NEG, 0, 1>::value;
+        constexpr int s10 = Sgn<NEG, 1, 0>::value, s11 = Sgn<NEG, 1, 1>::value;
+        if constexpr (TROLE == ROLE_REG) {
+            sfor<NJ>([&](auto Jc) __attribute__((always_inline)) {
+                constexpr int j = decltype(Jc)::value;
+                if constexpr (!(j & (1 << TPOS))) {
+                    const cplx<R> x0 = v[j], x1 = v[j | (1 << TPOS)];
+                    v[j] = {R(s00) * x0.re + R(s01) * x1.re, R(s00) * x0.im + R(s01) * x1.im};
+                    v[j | (1 << TPOS)] = {R(s10) * x0.re + R(s11) * x1.re, R(s10) * x0.im + R(s11) * x1.im};
+                }
+            });
+        } else {
+            // own row b: own value in column b, partner's in column 1 - b
+            const bool b = ((w.L >> TPOS) & 1u) != 0;
+            const R a = b ? R(s11) : R(s00), c = b ? R(s10) : R(s01);
+            sfor<NJ>([&](auto Jc) __attribute__((always_inline)) {
+                constexpr int j = decltype(Jc)::value;
+                const cplx<R> p = lane_xor_c<1 << TPOS>(v[j]);
+                if constexpr (s01 == s10)
+                    v[j] = {a * v[j].re + R(s01) * p.re, a * v[j].im + R(s01) * p.im};
+                else if constexpr (s00 == s11)
+                    v[j] = {R(s00) * v[j].re + c * p.re, R(s00) * v[j].im + c * p.im};
+                else
+                    v[j] = {a * v[j].re + c * p.re, a * v[j].im + c * p.im};
+                pin(v[j]);
+                shuffle_fence<j>();
+            });
+        }
+    } else {
+        R S[4];
+#pragma unroll
+        for (uint32_t r = 0; r < 2; r++)
+#pragma unroll
+            for (uint32_t c = 0; c < 2; c++) {
+                const uint32_t flip = ((NEG >> (2 * (r ^ xl) + (c ^ xl))) & 1u) ^ ((zl & r) ^ (zl & c));
+                S[2 * r + c] = flip ? R(-1) : R(1);
+            }
+        if constexpr (TROLE == ROLE_REG) {
+            sfor<NJ>([&](auto Jc) __attribute__((always_inline)) {
+                constexpr int j = decltype(Jc)::value;
+                if constexpr (!(j & (1 << TPOS))) {
+                    const cplx<R> x0 = v[j], x1 = v[j | (1 << TPOS)];
+                    v[j] = {S[0] * x0.re + S[1] * x1.re, S[0] * x0.im + S[1] * x1.im};
+                    v[j | (1 << TPOS)] = {S[2] * x0.re + S[3] * x1.re, S[2] * x0.im + S[3] * x1.im};
+                }
+            });
+        } else {
+            const bool b = ((w.L >> TPOS) & 1u) != 0;
+            const R a = b ? S[3] : S[0], c = b ? S[2] : S[1];
+            sfor<NJ>([&](auto Jc) __attribute__((always_inline)) {
+                constexpr int j = decltype(Jc)::value;
+                const cplx<R> p = lane_xor_c<1 << TPOS>(v[j]);
+                v[j] = {a * v[j].re + c * p.re, a * v[j].im + c * p.im};
+                pin(v[j]);
+                shuffle_fence<j>();
+            });
+        }
+    }
+}
+
+// The tile times a real factor (the butterflies' common factors).
+template <typename R, int RB>
+__device__ __forceinline__ void scale_tile(cplx<R> (&v)[1 << RB], R s) {
+    sfor<(1 << RB)>([&](auto Jc) __attribute__((always_inline)) {
+        constexpr int j = decltype(Jc)::value;
+        v[j] = {v[j].re * s, v[j].im * s};
+    });
+}
+
 // ------------------------------------------------------------ dense 4x4 --
 // A two-qubit gate on qubits (P0, P1) in normalised order: the first is a
 // register qubit whenever one of them is, and register pairs have P0 < P1.
@@ -392,6 +481,42 @@ __device__ __forceinline__ LaneBits lane_bits(uint32_t L) {
 // c where the mask is set (per lane), in the accumulator width
 __device__ __forceinline__ uint32_t masked(uint32_t c, uint32_t m) { return c & m; }
 __device__ __forceinline__ uint64_t masked(uint64_t c, uint32_t m) { return c & (uint64_t)(int64_t)(int32_t)m; }
+
+// A run's factors e^{2 pi i (C + sum_i lam_i x_i)} (apply_run_phase) with
+// the register bits LM known when the pass is compiled.  CZ (wave-uniform):
+// C is zero in every lane, as it is for a run of controlled phases with no
+// X frame on their qubits; then a run with one register bit multiplies only
+// the registers with that bit set, and a run with none is the identity.
+// (The full product multiplies the others by e^0, exactly 1, so the results
+// are the same.)  The factor e^{2 pi i C} is taken in a branch of its own
+// rather than beside the short form: two forms of the whole product would
+// hold more registers than the tile leaves free.
+template <typename R, int RB, uint32_t LM>
+__device__ __forceinline__ void run_phase(cplx<R> (&v)[1 << RB], typename Turns<R>::T C,
+                                          const typename Turns<R>::T (&lam)[RB], bool cz) {
+    constexpr int NB = __builtin_popcount(LM);
+    if constexpr (NB == 1) {
+        constexpr int I = __builtin_ctz(LM);
+        const cplx<R> e = expi_turns(lam[I]);
+        cplx<R> w1 = e;
+        if (!cz) {
+            const cplx<R> w0 = expi_turns(C);
+            w1 = cmul(w0, e);
+            sfor<(1 << RB)>([&](auto Jc) __attribute__((always_inline)) {
+                constexpr int j = decltype(Jc)::value;
+                if constexpr (((j >> I) & 1) == 0) v[j] = cmul(w0, v[j]);
+            });
+        }
+        sfor<(1 << RB)>([&](auto Jc) __attribute__((always_inline)) {
+            constexpr int j = decltype(Jc)::value;
+            if constexpr (((j >> I) & 1) != 0) v[j] = cmul(w1, v[j]);
+        });
+    } else if constexpr (NB == 0) {
+        if (!cz) apply_run_phase<R, RB>(v, C, lam, LM);
+    } else {
+        apply_run_phase<R, RB>(v, C, lam, LM);
+    }
+}
 
 // The run's register-only gates: table T (2^RB entries, index j ^ fr);
 // entries whose bit in tmask is clear are exactly 1 and skipped (RB <= 5).

@@ -127,11 +127,12 @@ def design_effect(scores: np.ndarray, root: int) -> float:
     return float((means.var(ddof=1) / root) / (v / N))
 
 
-def measure(T, torch, wc, circuit, shape, shots, p_ideal, seed, ws=None):
-    """One timed run of `shape` (equal cuts); returns (seconds per leaf,
-    design effect of the cross-entropy score over all leaves)."""
+def measure(T, torch, wc, circuit, shape, shots, p_ideal, seed, ws=None, cut=None):
+    """One timed run of `shape` (with `cut` as given, else equal cuts);
+    returns (seconds per leaf, design effect of the cross-entropy score over
+    all leaves)."""
     G = len(wc)
-    tree = (list(shape), equal_cuts(G, len(shape)))
+    tree = (list(shape), list(cut) if cut is not None else equal_cuts(G, len(shape)))
     plan = T.Plan(circuit, tree, "c64")
     nz = T.Noise.sample(circuit, tree, seed)
     need = plan.workspace_bytes(nz)
@@ -213,12 +214,14 @@ class ShapeModel:
         return True
 
 
-def choose_shape(T, model, wc, shots, copy_cost=26.0, max_deff=4.0, max_levels=4, deff_margin=0.8):
+def choose_shape(T, model, wc, shots, copy_cost=1.0, max_deff=4.0, max_levels=4, deff_margin=0.8):
     """The learned choice: the candidate with the smallest predicted time per
     shot among those whose predicted log design effect plus deff_margin (about
     twice the model's error on its training runs) stays <= log(max_deff); the
-    DCP shape when the model is missing, the circuit is out of its range or no
-    candidate qualifies.  Returns (tree, source)."""
+    DCP tree (at `copy_cost` gates per branch copy: about one here, where the
+    copy rides in the child's first pass) when the model is missing, the
+    circuit is out of its range or no candidate qualifies.  Returns
+    ((arities, cuts), source)."""
     G = len(wc)
     circuit = T.Circuit.from_workload(wc)
 
@@ -258,12 +261,18 @@ def held_out_circuits(n=24):
 
 
 def evaluate(T, torch, model, circuits, shots=16384, copy_cost=26.0, max_deff=4.0, seed=0, log=print):
-    """Per-shot (the exact reference), the DCP shape and the learned shape on each
-    circuit: measured time, and the normalised linear fidelity
+    """Per-shot (the exact reference), two DCP trees and the learned shape on
+    each circuit: measured time, and the normalised linear fidelity
     F = (mean p_ideal(x) - 2^-n) / (sum p_ideal^2 - 2^-n) (1 for the ideal
     output, 0 for the uniform one; for a single ideal outcome it is the
     normalised fidelity of Sec. 4.1) with its standard error, clustered over
-    level-0 subtrees for trees."""
+    level-0 subtrees for trees.
+
+    The DCP trees are the heuristic's own (arities and cuts, Sec. 3.2) at two
+    copy costs: `copy_cost` gates ("dcp", a state copy as a separate
+    kernel) and one gate ("dcp_fused": this library copies the parent's
+    state inside the child's first pass, so a branch costs about one gate
+    of memory traffic).  The learned gain is stated against both."""
     out = []
     for name, wc in circuits:
         G = len(wc)
@@ -271,12 +280,15 @@ def evaluate(T, torch, model, circuits, shots=16384, copy_cost=26.0, max_deff=4.
         p_ideal = ideal_probs(T, wc)
         u = 2.0 ** -wc.n
         norm = float(np.sum(p_ideal ** 2)) - u
-        (lshape, _), src = choose_shape(T, model, wc, shots, copy_cost, max_deff)
-        dshape = T.dcp(circuit, shots, 1.96, 0.01, copy_cost, 8)[0]
-        rec = {"circuit": name, "qubits": wc.n, "gates": G, "shots": shots, "learned_source": src}
+        ltree, src = choose_shape(T, model, wc, shots, 1.0, max_deff)
+        trees = {"pershot": ([shots], [0, G]),
+                 "dcp": T.dcp(circuit, shots, 1.96, 0.01, copy_cost, 8),
+                 "dcp_fused": T.dcp(circuit, shots, 1.96, 0.01, 1.0, 8),
+                 "learned": (list(ltree[0]), list(ltree[1]))}
+        rec = {"circuit": name, "qubits": wc.n, "gates": G, "shots": shots, "learned_source": src,
+               "copy_cost_gates": copy_cost}
         ws = None
-        for form, shape in (("pershot", [shots]), ("dcp", list(dshape)), ("learned", list(lshape))):
-            tree = (shape, equal_cuts(G, len(shape)))
+        for form, tree in trees.items():
             plan = T.Plan(circuit, tree, "c64")
             nz = T.Noise.sample(circuit, tree, seed)
             need = plan.workspace_bytes(nz)
@@ -286,26 +298,31 @@ def evaluate(T, torch, model, circuits, shots=16384, copy_cost=26.0, max_deff=4.
             torch.cuda.synchronize()
             o, st = T.run(plan, nz, ws, stats=True)
             s = (p_ideal[o.astype(np.int64)] - u) / norm
-            root = int(shape[0])
+            root = int(tree[0][0])
             if root == o.size:
                 se = float(s.std(ddof=1) / math.sqrt(o.size))
             else:
                 m = s.reshape(root, o.size // root).mean(1)
                 se = float(m.std(ddof=1) / math.sqrt(root))
-            rec[form] = {"shape": shape, "s": st["ms_device"] * 1e-3, "leaves": int(o.size),
-                         "F": float(s.mean()), "F_se": se}
+            rec[form] = {"shape": list(tree[0]), "cut": list(tree[1]), "s": st["ms_device"] * 1e-3,
+                         "leaves": int(o.size), "F": float(s.mean()), "F_se": se}
+
+        def per_leaf(f):
+            return rec[f]["s"] / rec[f]["leaves"]
+
         rec["learned_delta_F_vs_pershot"] = rec["learned"]["F"] - rec["pershot"]["F"]
         se = math.hypot(rec["learned"]["F_se"], rec["pershot"]["F_se"])
         rec["learned_delta_F_se"] = se
         # the fidelity bound of the paper (0.016) plus three standard errors
         rec["learned_within_bound"] = bool(abs(rec["learned_delta_F_vs_pershot"]) <= 0.016 + 3 * se)
-        rec["learned_speedup_vs_dcp"] = rec["dcp"]["s"] / rec["learned"]["s"] * \
-            (rec["learned"]["leaves"] / rec["dcp"]["leaves"])
-        rec["learned_speedup_vs_pershot"] = rec["pershot"]["s"] / rec["learned"]["s"] * \
-            (rec["learned"]["leaves"] / rec["pershot"]["leaves"])
-        log("%s: pershot %.2f s, dcp %s %.2f s, learned %s %.2f s (%s); F %.4f+-%.4f / %.4f+-%.4f / %.4f+-%.4f" % (
-            name, rec["pershot"]["s"], rec["dcp"]["shape"], rec["dcp"]["s"], rec["learned"]["shape"],
-            rec["learned"]["s"], src, rec["pershot"]["F"], rec["pershot"]["F_se"], rec["dcp"]["F"],
-            rec["dcp"]["F_se"], rec["learned"]["F"], rec["learned"]["F_se"]))
+        for f in ("dcp", "dcp_fused", "pershot"):
+            rec["learned_speedup_vs_" + f] = per_leaf(f) / per_leaf("learned")
+        log("%s: pershot %.3f s, dcp %s %.3f s, dcp_fused %s %.3f s, learned %s %.3f s (%s); "
+            "F %.4f+-%.4f / %.4f+-%.4f / %.4f+-%.4f / %.4f+-%.4f; learned/dcp_fused %.2fx" % (
+                name, rec["pershot"]["s"], rec["dcp"]["shape"], rec["dcp"]["s"], rec["dcp_fused"]["shape"],
+                rec["dcp_fused"]["s"], rec["learned"]["shape"], rec["learned"]["s"], src,
+                rec["pershot"]["F"], rec["pershot"]["F_se"], rec["dcp"]["F"], rec["dcp"]["F_se"],
+                rec["dcp_fused"]["F"], rec["dcp_fused"]["F_se"], rec["learned"]["F"], rec["learned"]["F_se"],
+                rec["learned_speedup_vs_dcp_fused"]))
         out.append(rec)
     return out

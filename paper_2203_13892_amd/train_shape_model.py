@@ -93,15 +93,19 @@ def main():
     ap.add_argument("--steps", type=int, default=4000)
     ap.add_argument("--out-dir", default=None, help="write the npz files here instead of data/")
     ap.add_argument("--evaluate", action="store_true",
-                    help="only evaluate the stored model on held-out 24-qubit circuits")
+                    help="only evaluate the stored model on held-out 24-26 qubit circuits")
+    ap.add_argument("--model", default=None, help="with --evaluate: the model file (default data/shape_mlp.npz)")
+    ap.add_argument("--copy-cost", type=float, default=26.0,
+                    help="with --evaluate: copy cost in gates of the separate-copy DCP baseline")
     args = ap.parse_args()
     import torch
     from . import tqsim as T
     torch.cuda.set_device(0)
     if args.evaluate:
         import json
-        model = Lm.ShapeModel.load(T)
-        res = Lm.evaluate(T, torch, model, Lm.held_out_circuits(), log=lambda m: print(m, flush=True))
+        model = Lm.ShapeModel.load(T, args.model or Lm.MODEL)
+        res = Lm.evaluate(T, torch, model, Lm.held_out_circuits(), copy_cost=args.copy_cost,
+                          log=lambda m: print(m, flush=True))
         print(json.dumps(res), flush=True)
         return 0
     rows = generate(T, torch, args.minutes, log=lambda m: print(m, flush=True))
