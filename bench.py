@@ -224,6 +224,90 @@ def batch_workload(W, count=512):
     return out
 
 
+def small_runs_leg(T, W, torch, seed, shots=2048, max_qubits=14, reps=3):
+    """The batched mixed workload's circuits of at most 14 qubits (their
+    states fit one workgroup's LDS), per-shot at 2048 shots each: one run
+    after another pass by pass, one run after another with each level's
+    passes in one launch and the states in LDS, and as batches of runs
+    advanced together (plain launches and a replayed graph).  Best of
+    `reps` timings per mode; outcomes must be identical in every mode."""
+    import numpy as np
+    circs = [(name, wc) for name, wc in batch_workload(W) if wc.n <= max_qubits]
+    items = {}
+    for mode, lds in (("pass_by_pass", 2), ("levels_in_lds", 1)):
+        its = []
+        for i, (name, wc) in enumerate(circs):
+            G = len(wc)
+            c = T.Circuit.from_workload(wc)
+            tree = ([shots], [0, G])
+            tun = {"chunk_states": 512, "lds_levels": lds}
+            its.append((T.Plan(c, tree, "c64", tun), T.Noise.sample(c, tree, seed + i)))
+        items[mode] = its
+    ws = T.Workspace(max(p.workspace_bytes(nz) for p, nz in items["pass_by_pass"]))
+    rec = {"workload": "%d circuits of 12-14 qubits from the batched mixed workload, %d shots each, per-shot, "
+                       "depolarizing(1e-3,1e-2)" % (len(circs), shots), "runs": len(circs),
+           "shots_total": shots * len(circs)}
+    outs = {}
+
+    def timed(fn):
+        best = float("inf")
+        out = None
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            out = fn()
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t0)
+        return best, out
+
+    for mode, its in items.items():
+        for p, nz in its[:4]:
+            T.run(p, nz, ws)
+        dt, outs[mode] = timed(lambda: [T.run(p, nz, ws) for p, nz in its])
+        rec[mode + "_s"] = dt
+    # batches: the pass-by-pass plans, runs grouped up to 8 GiB of workspace
+    its = items["pass_by_pass"]
+    groups, cur, cur_b = [], [], 0
+    for k, (p, nz) in enumerate(its):
+        b = p.workspace_bytes(nz)
+        if cur and cur_b + b > (8 << 30):
+            groups.append(cur)
+            cur, cur_b = [], 0
+        cur.append(k)
+        cur_b += b
+    groups.append(cur)
+    batches = [T.Batch([its[k][0] for k in g], [its[k][1] for k in g]) for g in groups]
+    bws = T.Workspace(max(bt.info()["workspace_bytes"] for bt in batches))
+
+    def run_batches():
+        res = [bt.run(bws) for bt in batches]
+        out = [None] * len(its)
+        for gi, g in enumerate(groups):
+            for j, k in enumerate(g):
+                out[k] = res[gi][j]
+        return out
+
+    run_batches()
+    rec["batched_s"], outs["batched"] = timed(run_batches)
+    for bt in batches:
+        bt.use_graph(True)
+    run_batches()
+    rec["batched_graph_s"], outs["batched_graph"] = timed(run_batches)
+    rec["batches"] = len(batches)
+    base = outs["pass_by_pass"]
+    rec["outcomes_identical"] = bool(all(all(np.array_equal(a, b) for a, b in zip(base, o))
+                                         for o in outs.values()))
+    for k in ("pass_by_pass", "levels_in_lds", "batched", "batched_graph"):
+        rec[k + "_shots_per_s"] = rec["shots_total"] / rec[k + "_s"]
+        rec[k + "_speedup"] = rec["pass_by_pass_s"] / rec[k + "_s"]
+    print("# small runs (%d circuits): pass by pass %.3f s, levels in LDS %.3f s (%.2fx), batched %.3f s (%.2fx), "
+          "graph %.3f s (%.2fx), identical %s" % (
+              len(circs), rec["pass_by_pass_s"], rec["levels_in_lds_s"], rec["levels_in_lds_speedup"],
+              rec["batched_s"], rec["batched_speedup"], rec["batched_graph_s"], rec["batched_graph_speedup"],
+              rec["outcomes_identical"]), file=sys.stderr, flush=True)
+    return rec
+
+
 def batch_bench(T, W, torch, seed, shots=2048, budget_gib=32):
     """The mixed workload per-shot at 2048 shots each: one run after another
     (default tuning) against batches (runs grouped in qubit order up to a
@@ -468,6 +552,8 @@ def main():
     ap.add_argument("--no-fidelity", action="store_true",
                     help="skip the tree's fidelity loss against per-shot sampling")
     ap.add_argument("--fid-seeds", type=int, default=20)
+    ap.add_argument("--no-small-runs", action="store_true",
+                    help="skip the leg of the batched mixed workload's 12-14 qubit circuits")
     ap.add_argument("--batch", action="store_true",
                     help="also run the 512-circuit mixed workload one run at a time and batched")
     ap.add_argument("--learned", action="store_true",
@@ -623,6 +709,8 @@ def main():
         print("# fidelity: F_pershot %.4f, dF (16,32,32) %+.4f +- %.4f, dF (8,8,16,16) %+.4f +- %.4f" %
               (fl["F_pershot"], fl["delta_F"], fl["delta_F_se"], fl["delta_F_tree4b"], fl["delta_F_tree4b_se"]),
               file=sys.stderr, flush=True)
+    if not args.no_small_runs:
+        line["small_runs"] = small_runs_leg(T, W, torch, args.seed)
     if args.precision:
         line["precision_sweep"] = precision_sweep(T, W, torch, args.seed)
     if args.batch:

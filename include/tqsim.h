@@ -118,6 +118,12 @@ typedef struct {
                                   on the vector units); 1000 or more: off.  Nodes with a noise
                                   event between the ops of such a run go to the generic
                                   kernel */
+    uint32_t lds_levels;       /* generic complex64 kernels (tiles of at most five register
+                                  qubits), tree levels of two or more passes whose state fits
+                                  one workgroup's LDS (up to 2^14 amplitudes, at most eight
+                                  tiles): all passes of the level in one launch, one workgroup
+                                  per state, the state kept in LDS between passes.  1 on, 2 off;
+                                  default 0: on.  Same results either way */
 } tqs_tuning;
 
 /* Timing and traffic of one run. */

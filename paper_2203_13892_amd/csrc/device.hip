@@ -910,6 +910,59 @@ static void launch_pass_kernel(uint32_t reg_bits, bool d2, const PassLaunch<R> &
 #undef TQS_LAUNCH
 }
 
+// All passes of one level in one launch with the state in LDS (complex64
+// tiles of four or five register qubits: two waves per SIMD leave each
+// lane 256 registers, enough for the tile without spills).
+static void launch_level_kernel(uint32_t reg_bits, bool d2, const LevelLaunch<float> &ll, uint32_t waves,
+                                uint32_t lds_bytes, hipStream_t s) {
+    const uint32_t grid = (ll.a.count + 7u) & ~7u;
+    const dim3 g(grid), b(64 * waves);
+    if (reg_bits == 4) {
+        if (d2) hipLaunchKernelGGL((level_kernel<float, 4, true>), g, b, lds_bytes, s, ll);
+        else hipLaunchKernelGGL((level_kernel<float, 4, false>), g, b, lds_bytes, s, ll);
+    } else {
+        if (d2) hipLaunchKernelGGL((level_kernel<float, 5, true>), g, b, lds_bytes, s, ll);
+        else hipLaunchKernelGGL((level_kernel<float, 5, false>), g, b, lds_bytes, s, ll);
+    }
+}
+
+constexpr int kMaxDevices = 64;
+
+// LDS bytes one workgroup may hold on the current device (cached per device).
+static uint32_t device_lds_limit() {
+    static int cached[kMaxDevices] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return 0;
+    if (!cached[dev]) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
+            v = -1;
+        cached[dev] = v;
+    }
+    return cached[dev] > 0 ? (uint32_t)cached[dev] : 0u;
+}
+
+// Waves per workgroup and LDS bytes of the level kernel for level l of the
+// plan, or {0, 0} when the level runs pass by pass: the generic kernels,
+// complex64 tiles of at most five register qubits, two or more passes, the
+// state within LDS and at most eight tiles.
+struct LevelShape {
+    uint32_t waves = 0, lds = 0;
+};
+static LevelShape level_shape(const tqs_plan *p, uint32_t l) {
+    LevelShape ls;
+    const tqs::Level &lv = p->levels[l];
+    if (p->tune.lds_levels != 1 || p->tune.jit == 1 || lv.pass_count < 2) return ls;
+    if (p->prec != TQS_C64 || p->reg_bits > 5) return ls;
+    const uint64_t bytes = 8ull << p->n;
+    uint32_t nfree = 0;
+    for (uint32_t k = 0; k < lv.pass_count; k++) nfree = std::max<uint32_t>(nfree, p->passes[lv.pass_begin + k].nfree);
+    if (nfree > 3 || bytes > device_lds_limit()) return ls;
+    ls.waves = 1u << nfree;
+    ls.lds = (uint32_t)bytes;
+    return ls;
+}
+
 // Which kernel takes each computed state of a chunk task's pass: the
 // plan-specialised kernel (when the plan has one for the pass) takes the
 // states it supports, the generic kernel the rest.  perm: offset in the
@@ -1351,7 +1404,32 @@ static tqs_status run_t(tqs_plan *p, const tqs_noise *nz, unsigned char *ws, uin
             if (!ea || !eb) return fail(TQS_E_HIP, "hipEventCreate failed");
             HIP_TRY(hipEventRecord(ea, s), "hipEventRecord");
         }
-        for (uint32_t k = 0; k < lv.pass_count; k++) {
+        const LevelShape lsh = level_shape(p, t.level);
+        if constexpr (sizeof(R) == 4) if (lsh.waves && t.ccount) {
+            // the whole level in one launch, the states in LDS between passes
+            if (fault.kind == FaultSpec::LAUNCH && pass_iter <= fault.at && fault.at < pass_iter + lv.pass_count)
+                HIP_TRY(hipErrorLaunchFailure, "pass launch (TQS_FAULT)");
+            pass_iter += lv.pass_count;
+            LevelLaunch<float> ll;
+            std::memset(&ll, 0, sizeof ll);
+            ll.a = pass_args<float>(p, Ly, ws, t, lv.pass_begin, true);
+            ll.npass = lv.pass_count;
+            const PassArgs<float> al = pass_args<float>(p, Ly, ws, t, lv.pass_begin + lv.pass_count - 1, false);
+            ll.part = al.part;
+            ll.psum = al.psum;
+            bool d2 = false;
+            for (uint32_t k = 0; k < lv.pass_count; k++) d2 = d2 || p->passes[lv.pass_begin + k].has_d2;
+            launch_level_kernel(p->reg_bits, d2, ll, lsh.waves, lsh.lds, s);
+            HIP_TRY(hipGetLastError(), "level kernel launch");
+            launches++;
+            pass_launches++;
+            pass_states += t.ccount;
+            const bool init = t.level == 0;
+            const bool parts = p->samp_tiled && t.level == L - 1;
+            bytes_passes += (uint64_t)t.ccount * (state_bytes * (init ? 1 : 2) +
+                                                  (parts ? (8ull << (p->samp_nfree + p->samp_kv)) : 0ull));
+        }
+        for (uint32_t k = 0; k < (lsh.waves ? 0u : lv.pass_count); k++) {
             uint32_t nl = 0;
             hipError_t le = hipSuccess;
             hipEvent_t ej0 = nullptr, ej1 = nullptr;
@@ -1696,7 +1774,6 @@ constexpr uint64_t kStaticScratchBytes = 64ull << 20;
 static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
 
 namespace tqs {
-constexpr int kMaxDevices = 64;
 static std::mutex g_scratch_mu;
 static void *g_scratch_ptr[kMaxDevices] = {nullptr};
 

@@ -273,33 +273,21 @@ void emit_dense(std::string &s, const tqs_plan *p, const OpDesc &o, double *scal
     }
 }
 
-void emit_pass(std::string &s, const tqs_plan *p, uint32_t pi) {
-    const PassDesc &d = p->passes[pi];
-    const bool c64 = p->prec == TQS_C64;
-    const int waves = (c64 && d.nr <= 5) ? 3 : 1;
-    appendf(s, "extern \"C\" __global__ __launch_bounds__(64, %d) void tqs_jit_p%u(tqs::PassLaunch<%s> pl) {\n",
-            waves, pi, c64 ? "float" : "double");
-    appendf(s,
-            "  using namespace tqs;\n  using namespace tqs::jit;\n"
-            "  using R = %s;\n  using A = %s;\n  constexpr int RB = %u;\n  constexpr uint32_t KEY = %uu << 16;\n",
-            c64 ? "float" : "double", c64 ? "uint32_t" : "uint64_t", (unsigned)d.nr, pi);
-    s += "  const uint32_t nwg = gridDim.x, bid = blockIdx.x;\n"
-         "  const uint32_t wall = (bid & 7u) * (nwg >> 3) + (bid >> 3);\n"
-         "  const PassArgs<R> &a = pl.one;\n"
-         "  if (wall >= a.work) return;\n"
-         "  const uint32_t ti = wall % a.count, tile = wall / a.count;\n"
-         "  const uint32_t traj = a.perm ? kconst(a.perm)[ti] : ti;\n"
-         "  Wave w;\n  w.L = threadIdx.x;\n  w.base = 0";
-    for (uint32_t i = 0; i < d.nfree; i++) appendf(s, " | (((tile >> %u) & 1u) << %u)", i, d.fbits[i]);
+// The tile's origin w.base from the tile index expression `tile`.
+void emit_base(std::string &s, const PassDesc &d, const char *tile) {
+    s += "  w.base = 0";
+    for (uint32_t i = 0; i < d.nfree; i++) appendf(s, " | (((%s >> %u) & 1u) << %u)", tile, i, d.fbits[i]);
     s += ";\n";
-    s += "  const uint32_t src_s = kconst(a.src_slot)[traj], dst_s = kconst(a.dst_slot)[traj];\n"
-         "  const bool init = src_s == kInit;\n"
-         "  const gptr<const cplx<R>> src = (gptr<const cplx<R>>)(a.states + (uint64_t)(init ? 0u : src_s) * "
-         "a.slot_amps + w.base);\n"
-         "  cplx<R> v[1 << RB];\n";
+}
+
+// Load the tile into v from the source state in HBM (or make |0..0>).
+void emit_load(std::string &s, const PassDesc &d) {
     const bool full = d.nl == kLaneBits;
     const uint32_t nj = 1u << d.nr;
+    s += "  cplx<R> v[1 << RB];\n";
     if (!full) appendf(s, "  const bool lane_ok = w.L < %uu;\n", 1u << d.nl);
+    s += "  { const gptr<const cplx<R>> src = (gptr<const cplx<R>>)(a.states + (uint64_t)(init ? 0u : src_s) * "
+         "a.slot_amps + w.base);\n";
     s += "  if (init) {\n";
     for (uint32_t j = 0; j < nj; j++)
         appendf(s, "    v[%u] = cplx<R>{%s, R(0)};\n", j, j == 0 ? "(w.base | w.L) == 0 ? R(1) : R(0)" : "R(0)");
@@ -310,18 +298,28 @@ void emit_pass(std::string &s, const tqs_plan *p, uint32_t pi) {
             appendf(s, "    v[%u] = lane_ok ? src[%lluull + w.L] : cplx<R>{R(0), R(0)};\n", j,
                     (unsigned long long)reg_off(d, j));
     }
-    s += "  }\n";
+    s += "  } }\n";
+}
+
+// The wave's frame and event cursor at the start of its node's level.
+void emit_frame_init(std::string &s) {
     s += "  const uint32_t node = kconst(a.node_ids)[traj];\n"
          "  w.fx = uni(kconst(a.meta.frame0)[2 * node]);\n"
          "  w.fz = uni(kconst(a.meta.frame0)[2 * node + 1]);\n"
          "  w.e = uni(kconst(a.meta.ev_off)[node]);\n"
          "  w.e1 = uni(kconst(a.meta.ev_off)[node + 1]);\n"
          "  w.pos = kconst(a.meta.ev_pos);\n  w.dx = kconst(a.meta.ev_dx);\n  w.dz = kconst(a.meta.ev_dz);\n"
-         "  w.nxt = w.e < w.e1 ? uni(w.pos[w.e]) : 0xFFFFFFFFu;\n";
-    if (pi > 0) s += "  advance(w, KEY - 1u);\n";
-    s += "  const kptr<cplx<R>> mats = kconst(a.mats);\n"
+         "  w.nxt = w.e < w.e1 ? uni(w.pos[w.e]) : 0xFFFFFFFFu;\n"
+         "  const kptr<cplx<R>> mats = kconst(a.mats);\n"
          "  const LaneBits lb = lane_bits(w.L);\n"
          "  (void)lb;\n";
+}
+
+// The pass's ops on v (frame tables, fused blocks, phase runs, dense ops),
+// then the butterflies' common factor.
+void emit_ops(std::string &s, const tqs_plan *p, uint32_t pi) {
+    const PassDesc &d = p->passes[pi];
+    const bool c64 = p->prec == TQS_C64;
     if (jit_table_entries(p, pi)) {
         // the node's own frame tables for this pass, if it has them
         appendf(s,
@@ -357,12 +355,52 @@ void emit_pass(std::string &s, const tqs_plan *p, uint32_t pi) {
         else emit_dense(s, p, o, &scale);
     }
     if (scale != 1.0) appendf(s, "  scale_tile<R, RB>(v, R(%.17g));\n", scale);
-    s += "  const gptr<cplx<R>> dst = (gptr<cplx<R>>)(a.states + (uint64_t)dst_s * a.slot_amps + w.base);\n";
+}
+
+// Store v to the node's state in HBM, with the sampling partials when the
+// pass is the leaf level's last.
+void emit_store(std::string &s, const PassDesc &d, const char *tile) {
+    const bool full = d.nl == kLaneBits;
+    const uint32_t nj = 1u << d.nr;
+    s += "  { const gptr<cplx<R>> dst = (gptr<cplx<R>>)(a.states + (uint64_t)dst_s * a.slot_amps + w.base);\n";
     for (uint32_t j = 0; j < nj; j++) {
         if (full) appendf(s, "  dst[%lluull + w.L] = v[%u];\n", (unsigned long long)reg_off(d, j), j);
         else appendf(s, "  if (lane_ok) dst[%lluull + w.L] = v[%u];\n", (unsigned long long)reg_off(d, j), j);
     }
-    if (full) appendf(s, "  if (a.part) tile_partials<R, RB>(v, a, traj, tile, %uu, w.L);\n", (unsigned)d.nfree);
+    s += "  }\n";
+    if (full) appendf(s, "  if (a.part) tile_partials<R, RB>(v, a, traj, %s, %uu, w.L);\n", tile, (unsigned)d.nfree);
+}
+
+void emit_header(std::string &s, const tqs_plan *p) {
+    const bool c64 = p->prec == TQS_C64;
+    appendf(s, "  using namespace tqs;\n  using namespace tqs::jit;\n  using R = %s;\n  using A = %s;\n",
+            c64 ? "float" : "double", c64 ? "uint32_t" : "uint64_t");
+}
+
+// One pass over a chunk of states: one wave per tile of one state.
+void emit_pass(std::string &s, const tqs_plan *p, uint32_t pi) {
+    const PassDesc &d = p->passes[pi];
+    const bool c64 = p->prec == TQS_C64;
+    const int waves = (c64 && d.nr <= 5) ? 3 : 1;
+    appendf(s, "extern \"C\" __global__ __launch_bounds__(64, %d) void tqs_jit_p%u(tqs::PassLaunch<%s> pl) {\n",
+            waves, pi, c64 ? "float" : "double");
+    emit_header(s, p);
+    appendf(s, "  constexpr int RB = %u;\n  constexpr uint32_t KEY = %uu << 16;\n", (unsigned)d.nr, pi);
+    s += "  const uint32_t nwg = gridDim.x, bid = blockIdx.x;\n"
+         "  const uint32_t wall = (bid & 7u) * (nwg >> 3) + (bid >> 3);\n"
+         "  const PassArgs<R> &a = pl.one;\n"
+         "  if (wall >= a.work) return;\n"
+         "  const uint32_t ti = wall % a.count, tile = wall / a.count;\n"
+         "  const uint32_t traj = a.perm ? kconst(a.perm)[ti] : ti;\n"
+         "  Wave w;\n  w.L = threadIdx.x;\n";
+    emit_base(s, d, "tile");
+    s += "  const uint32_t src_s = kconst(a.src_slot)[traj], dst_s = kconst(a.dst_slot)[traj];\n"
+         "  const bool init = src_s == kInit;\n";
+    emit_load(s, d);
+    emit_frame_init(s);
+    if (pi > 0) s += "  advance(w, KEY - 1u);\n";
+    emit_ops(s, p, pi);
+    emit_store(s, d, "tile");
     s += "}\n\n";
 }
 

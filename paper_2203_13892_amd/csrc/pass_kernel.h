@@ -660,4 +660,225 @@ __global__ __launch_bounds__(64, (PassWaves<R, RB>::value)) void pass_kernel(Pas
     if (a.part && full) tile_partials<R, RB>(v, a, traj, tile, nfree, L);
 }
 
+// ------------------------------------------------------- level pass tile --
+// One pass of the level kernel over one tile of one trajectory (traj: index
+// in the launched chunk): the body of pass_kernel, with the tile read from
+// the state in LDS (from_lds; physical amplitude order) instead of HBM, and
+// written back to LDS (to_lds) instead of HBM.  (pass_kernel keeps its own
+// copy: factored into a shared function, its register allocation spills
+// several times more.)
+template <typename R, int RB, bool D2>
+__device__ __forceinline__ void level_pass_tile(const PassArgs<R> &a, uint32_t traj, uint32_t tile, uint32_t L,
+                                          cplx<R> *st, bool from_lds, bool to_lds) {
+    constexpr int NJ = 1 << RB;
+    const kptr<PassDesc> pd = kconst(a.pass);
+    const kptr<OpDesc> ops = kconst(a.ops);
+    const kptr<cplx<R>> mats = kconst(a.mats);
+    const kptr<uint32_t> ev_pos = kconst(a.meta.ev_pos), ev_dx = kconst(a.meta.ev_dx),
+                         ev_dz = kconst(a.meta.ev_dz);
+    static_assert(__builtin_offsetof(PassDesc, nl) == 8 && __builtin_offsetof(PassDesc, rq) == 12 &&
+                      __builtin_offsetof(PassDesc, fbits) == 20,
+                  "pass descriptor layout");
+    const kptr<uint32_t> pw = (kptr<uint32_t>)pd;
+    const uint32_t op_begin = uni(pw[0]), op_count = uni(pw[1]), pw2 = uni(pw[2]);
+    const uint32_t rq03 = uni(pw[3]), rq47 = uni(pw[4]);
+    const uint32_t nl = pw2 & 0xFFu, nr = (pw2 >> 8) & 0xFFu, nfree = (pw2 >> 16) & 0xFFu;
+    if (tile >> nfree) return;  // (a workgroup wider than this pass's tile count)
+
+    // tile loads go out first; the noise metadata is fetched behind them
+    const uint32_t src_s = kconst(a.src_slot)[traj];
+    const uint32_t dst_s = kconst(a.dst_slot)[traj];
+    uint32_t base = 0;
+    for (uint32_t i = 0; i < nfree; i++) base |= ((tile >> i) & 1u) << ((uni(pw[5 + (i >> 2)]) >> (8 * (i & 3u))) & 0xFFu);
+    uint32_t rq[RB];
+#pragma unroll
+    for (int i = 0; i < RB; i++) rq[i] = (uint32_t)i < nr ? (((i < 4 ? rq03 : rq47) >> (8 * (i & 3))) & 0xFFu) : 0u;
+    const bool lane_ok = L < (1u << nl);
+    const uint32_t jmax = 1u << nr;
+    const bool init = src_s == kInit;
+    const cplx<R> *src = a.states + (uint64_t)(init ? 0u : src_s) * a.slot_amps + base;
+
+    // a full tile (64 lanes, RB register qubits) loads without predication:
+    // scalar base of each register index plus the lane offset
+    const bool full = nl == kLaneBits && nr == (uint32_t)RB;
+    // (branches sit outside the unrolled loops so all loads issue back to back)
+    auto reg_off = [&](auto Jc) __attribute__((always_inline)) {
+        constexpr int j = decltype(Jc)::value;
+        uint32_t off = 0;
+        sfor<RB>([&](auto Ic) __attribute__((always_inline)) {
+            constexpr int i = decltype(Ic)::value;
+            if constexpr ((j >> i) & 1) off |= 1u << rq[i];
+        });
+        return off;
+    };
+    cplx<R> v[NJ];
+    if (from_lds) {
+        // the state in LDS (physical order), left there by the previous pass
+        sfor<NJ>([&](auto Jc) __attribute__((always_inline)) {
+            constexpr int j = decltype(Jc)::value;
+            v[j] = cplx<R>{R(0), R(0)};
+            if (full || ((uint32_t)j < jmax && lane_ok)) v[j] = st[base + reg_off(Jc) + L];
+        });
+    } else if (init) {
+        sfor<NJ>([&](auto Jc) __attribute__((always_inline)) {
+            constexpr int j = decltype(Jc)::value;
+            const uint32_t off = reg_off(Jc);
+            v[j] = cplx<R>{(uint32_t)j < jmax && (base + off + L) == 0 ? R(1) : R(0), R(0)};
+        });
+    } else if (full) {
+        sfor<NJ>([&](auto Jc) __attribute__((always_inline)) {
+            constexpr int j = decltype(Jc)::value;
+            v[j] = (src + reg_off(Jc))[L];
+        });
+    } else {
+        sfor<NJ>([&](auto Jc) __attribute__((always_inline)) {
+            constexpr int j = decltype(Jc)::value;
+            v[j] = cplx<R>{R(0), R(0)};
+            if ((uint32_t)j < jmax && lane_ok) v[j] = (src + reg_off(Jc))[L];
+        });
+    }
+
+    // frame at the start of this pass
+    const uint32_t node = kconst(a.node_ids)[traj];
+    uint32_t fx = kconst(a.meta.frame0)[2 * node], fz = kconst(a.meta.frame0)[2 * node + 1];
+    uint32_t e = kconst(a.meta.ev_off)[node];
+    const uint32_t e1 = kconst(a.meta.ev_off)[node + 1];
+    while (e < e1 && ev_pos[e] < a.pass_key) {
+        fx ^= ev_dx[e];
+        fz ^= ev_dz[e];
+        e++;
+    }
+
+    for (uint32_t oi = 0; oi < op_count; oi++) {
+        const OpDesc o = kload(ops + op_begin + oi);
+        while (e < e1 && ev_pos[e] <= (a.pass_key | o.slot0)) {
+            fx ^= ev_dx[e];
+            fz ^= ev_dz[e];
+            e++;
+        }
+        if (o.kind == OP_DIAGRUN) {
+            const bool inside = e < e1 && ev_pos[e] < (a.pass_key | o.slot1);
+            if (!inside) {
+                op_diag_run<R, RB>(v, o, mats + o.mat, kconst(a.terms) + o.terms, fx, L, base, rq, nr);
+                continue;
+            }
+            // events inside the run (counted up to four)
+            const uint32_t end = a.pass_key | o.slot1;
+            uint32_t ne = 1;
+            while (ne < 4u && e + ne < e1 && ev_pos[e + ne] < end) ne++;
+            if (o.ngates < 255u && ne <= 3u) {
+                // up to three: the run in up to four frames, the gates on
+                // register qubits only one by one (event indexes stay in
+                // [e, e1))
+                const uint32_t eb = ne > 1u ? e + 1 : e, ec = ne > 2u ? e + 2 : eb;
+                RunFrames rf;
+                rf.f0 = fx;
+                rf.k0 = (ev_pos[e] & 0xFFFFu) - o.slot0;
+                rf.f1 = fx ^ ev_dx[e];
+                rf.k1 = ne > 1u ? (ev_pos[eb] & 0xFFFFu) - o.slot0 : 255u;
+                rf.f2 = ne > 1u ? rf.f1 ^ ev_dx[eb] : rf.f1;
+                rf.k2 = ne > 2u ? (ev_pos[ec] & 0xFFFFu) - o.slot0 : 255u;
+                rf.f3 = ne > 2u ? rf.f2 ^ ev_dx[ec] : rf.f2;
+                op_diag_run_split<R, RB>(v, o, kconst(a.terms) + o.terms, rf, L, base, rq);
+                if (o.has_t) {
+                    for (uint32_t k = 0; k < o.ngates; k++) {
+                        const DiagGate dg = kload(kconst(a.dgates) + o.gates + k);
+                        const bool regonly = dg.role[0] == ROLE_REG && (dg.nq == 1 || dg.role[1] == ROLE_REG);
+                        if (regonly) op_diag_one<R, RB>(v, dg, mats + dg.d, rf.at(k), L, base);
+                    }
+                }
+                fx = rf.f3;
+                fz ^= ev_dz[e] ^ (ne > 1u ? ev_dz[eb] : 0u) ^ (ne > 2u ? ev_dz[ec] : 0u);
+                e += ne;
+            } else {
+                // more events inside the run: gate by gate with frame updates
+                for (uint32_t k = 0; k < o.ngates; k++) {
+                    while (e < e1 && ev_pos[e] <= (a.pass_key | (o.slot0 + k))) {
+                        fx ^= ev_dx[e];
+                        fz ^= ev_dz[e];
+                        e++;
+                    }
+                    const DiagGate dg = kload(kconst(a.dgates) + o.gates + k);
+                    op_diag_one<R, RB>(v, dg, mats + dg.d, fx, L, base);
+                }
+            }
+            continue;
+        }
+        uint32_t xl = (fx >> o.phys[0]) & 1u, zl = (fz >> o.phys[0]) & 1u;
+        if (o.nq == 2) {
+            xl |= ((fx >> o.phys[1]) & 1u) << 1;
+            zl |= ((fz >> o.phys[1]) & 1u) << 1;
+        }
+        const kptr<cplx<R>> G = mats + o.mat;
+        if constexpr (D2) {
+            if (o.kind == OP_DENSE2) {
+                op_dense2<R, RB>(v, o, G, xl, zl, L);
+                continue;
+            }
+        }
+        op_dense1<R, RB>(v, o, G, xl, zl, L, base);
+    }
+
+    if (to_lds) {
+        sfor<NJ>([&](auto Jc) __attribute__((always_inline)) {
+            constexpr int j = decltype(Jc)::value;
+            if (full || ((uint32_t)j < jmax && lane_ok)) st[base + reg_off(Jc) + L] = v[j];
+        });
+        return;
+    }
+    cplx<R> *dst = a.states + (uint64_t)dst_s * a.slot_amps + base;
+    if (full) {
+        sfor<NJ>([&](auto Jc) __attribute__((always_inline)) {
+            constexpr int j = decltype(Jc)::value;
+            (dst + reg_off(Jc))[L] = v[j];
+        });
+    } else {
+        sfor<NJ>([&](auto Jc) __attribute__((always_inline)) {
+            constexpr int j = decltype(Jc)::value;
+            if ((uint32_t)j < jmax && lane_ok) (dst + reg_off(Jc))[L] = v[j];
+        });
+    }
+    if (a.part && full) tile_partials<R, RB>(v, a, traj, tile, nfree, L);
+}
+
+// ----------------------------------------------------------- level kernel --
+// Every pass of one tree level over a chunk of states small enough for LDS
+// (2^n amplitudes in one workgroup's LDS): one workgroup per state, one wave
+// per tile.  The first pass reads the parent's state from HBM (or makes
+// |0..0>), later passes read what the previous one left in LDS, and only
+// the last writes to HBM (with the sampling partials at the leaf level), so
+// a level costs one launch and one read and write of each state instead of
+// one of each per pass.
+constexpr uint32_t kLevelThreads = 512;  // up to eight tiles per state
+
+template <typename R>
+struct LevelLaunch {
+    PassArgs<R> a;   // the level's first pass, for the chunk's computed states
+    uint32_t npass;  // its passes: descriptors a.pass[0, npass), keys a.pass_key + (k << 16)
+    uint32_t psum;   // partial-sum layout of the last pass
+    double *part;    // sampling partials the last pass writes (or NULL)
+};
+
+template <typename R, int RB, bool D2>
+__global__ __launch_bounds__(kLevelThreads, 2) void level_kernel(LevelLaunch<R> ll) {
+    extern __shared__ unsigned char level_lds[];
+    cplx<R> *st = reinterpret_cast<cplx<R> *>(level_lds);
+    const uint32_t nwg = gridDim.x, bid = blockIdx.x;
+    const uint32_t ti = (bid & 7u) * (nwg >> 3) + (bid >> 3);
+    if (ti >= ll.a.count) return;  // (the whole workgroup)
+    const uint32_t tv = threadIdx.x >> 6, L = threadIdx.x & 63u;
+    PassArgs<R> a = ll.a;
+    for (uint32_t k = 0; k < ll.npass; k++) {
+        if (k) {
+            __syncthreads();
+            a.pass = ll.a.pass + k;
+            a.pass_key = ll.a.pass_key + (k << 16);
+        }
+        const bool last = k + 1 == ll.npass;
+        a.part = last ? ll.part : nullptr;
+        a.psum = last ? ll.psum : 0u;
+        level_pass_tile<R, RB, D2>(a, ti, tv, L, st, k > 0, !last);
+    }
+}
+
 }  // namespace tqs

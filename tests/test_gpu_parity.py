@@ -528,11 +528,15 @@ def test_learned_shape_against_partition_heuristic(T):
     (shape, _), src = Lm.choose_shape(T, model, wc, shots)
     assert src == "learned"
     c = T.Circuit.from_workload(wc)
-    dshape = T.dcp(c, shots, 1.96, 0.01, 26.0, 8)[0]
+    # DCP's own trees (arities and cuts): a separate state copy costing 26
+    # gates, and the copy fused into the child's first pass (about one gate)
+    dshape, dcut = T.dcp(c, shots, 1.96, 0.01, 26.0, 8)
+    fshape, fcut = T.dcp(c, shots, 1.96, 0.01, 1.0, 8)
     p_ideal = Lm.ideal_probs(T, wc)
-    t_d, deff_d, ws = Lm.measure(T, torch, wc, c, dshape, shots, p_ideal, 1)
+    t_d, deff_d, ws = Lm.measure(T, torch, wc, c, dshape, shots, p_ideal, 1, cut=dcut)
+    t_f, deff_f, ws = Lm.measure(T, torch, wc, c, fshape, shots, p_ideal, 1, ws, cut=fcut)
     t_l, deff_l, ws = Lm.measure(T, torch, wc, c, shape, shots, p_ideal, 1, ws)
-    print("learned", shape, t_l, deff_l, "dcp", list(dshape), t_d, deff_d)
+    print("learned", shape, t_l, deff_l, "dcp", dshape, dcut, t_d, deff_d, "dcp_fused", fshape, fcut, t_f, deff_f)
     assert t_l < 0.8 * t_d
     assert deff_l < 12.0
     # far outside the training range: the heuristic decides
@@ -960,3 +964,37 @@ def test_fused_register_blocks_on_matrix_cores(T, n, min_ops):
     fused, st = T.run(plan, nz, stats=True)
     assert st["jit_launches"] > 0
     assert np.mean(base == fused) > 0.9
+
+
+@pytest.mark.parametrize("n,tile", [(7, 11), (10, 11), (11, 11), (12, 11), (14, 11), (13, 10)])
+def test_levels_in_lds(T, n, tile):
+    # generic complex64 kernels with every pass of a level in one launch and
+    # the state in LDS between passes (levels of two or more passes): every
+    # op class, events inside and between passes, shared states, a ragged
+    # last chunk and partial tiles (n < 11), against the oracle and against
+    # the same plan run pass by pass
+    rng = np.random.default_rng(500 + n)
+    wc = mixed_gates(n, 60, rng)
+    tree = ([3, 4, 6], [0, 14, 35, 60])
+    arr = event_arrays(wc, tree, rng, rate=0.08)
+    leaves = np.arange(72)
+    tun = {"chunk_states": 5, "max_ops_per_pass": 6, "tile_qubits": tile, "jit": 2}
+    out, amps, oout, ost, _ = run_both(T, wc, tree, 0, "c64", leaves, tuning=dict(tun, lds_levels=1),
+                                       noise_arrays=arr)
+    c = T.Circuit.from_workload(wc)
+    plan = T.Plan(c, tree, "c64", dict(tun, lds_levels=1))
+    passes = [plan.info(l)["passes_level"] for l in range(3)]
+    assert max(passes) >= 2, passes
+    print("n", n, "passes per level", passes, "max-abs %.3g" % np.max(np.abs(amps - ost)))
+    assert np.max(np.abs(amps - ost)) < TOL["c64"]
+    check_outcomes(out, oout, ost, arr[3], DELTA["c64"])
+    # the same plan pass by pass: the same arithmetic, so the same outcomes
+    nz = T.Noise.from_arrays(c, tree, *arr)
+    base_plan = T.Plan(c, tree, "c64", dict(tun, lds_levels=2))
+    base, st_b = T.run(base_plan, nz, stats=True)
+    lds, st_l = T.run(plan, nz, stats=True)
+    assert np.array_equal(base, lds)
+    _, amps_b = T.run_capture(base_plan, nz, leaves)
+    assert np.max(np.abs(amps_b - amps)) < 1e-6
+    print("launches pass by pass", st_b["pass_launches"], "with levels in LDS", st_l["pass_launches"])
+    assert st_l["pass_launches"] < st_b["pass_launches"]
