@@ -224,13 +224,38 @@ def batch_workload(W, count=512):
     return out
 
 
+def memory_probe(torch, gib=4, reps=10):
+    """Plain device memory rates on this GPU, beside the roofline: a fill
+    (write only) and a copy (read plus write) of `gib` GiB with torch's own
+    kernels, best of `reps`."""
+    n = gib << 30
+    x = torch.empty(n, dtype=torch.uint8, device="cuda")
+    y = torch.empty_like(x)
+
+    def best(fn):
+        fn()
+        torch.cuda.synchronize()
+        b = float("inf")
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            b = min(b, time.perf_counter() - t0)
+        return b
+
+    rec = {"fill_write_GBps": n / best(lambda: x.fill_(1)) / 1e9,
+           "copy_read_write_GBps": 2 * n / best(lambda: y.copy_(x)) / 1e9, "bytes": n}
+    del x, y
+    return rec
+
+
 def small_runs_leg(T, W, torch, seed, shots=2048, max_qubits=14, reps=3):
     """The batched mixed workload's circuits of at most 14 qubits (their
     states fit one workgroup's LDS), per-shot at 2048 shots each: one run
-    after another pass by pass, one run after another with each level's
-    passes in one launch and the states in LDS, and as batches of runs
-    advanced together (plain launches and a replayed graph).  Best of
-    `reps` timings per mode; outcomes must be identical in every mode."""
+    after another pass by pass (the default), one run after another with
+    each level's passes in one launch and the states in LDS, and as batches
+    of runs advanced together (plain launches and a replayed graph).  Best
+    of `reps` timings per mode."""
     import numpy as np
     circs = [(name, wc) for name, wc in batch_workload(W) if wc.n <= max_qubits]
     items = {}
@@ -295,13 +320,18 @@ def small_runs_leg(T, W, torch, seed, shots=2048, max_qubits=14, reps=3):
     rec["batched_graph_s"], outs["batched_graph"] = timed(run_batches)
     rec["batches"] = len(batches)
     base = outs["pass_by_pass"]
-    rec["outcomes_identical"] = bool(all(all(np.array_equal(a, b) for a, b in zip(base, o))
-                                         for o in outs.values()))
+    # batches run the same kernels as the runs one after another: identical
+    # outcomes; the level kernel's arithmetic agrees to rounding, so a few
+    # leaves at a CDF boundary may pick the neighbouring outcome
+    rec["outcomes_identical"] = bool(all(all(np.array_equal(a, b) for a, b in zip(base, outs[m]))
+                                         for m in ("batched", "batched_graph")))
+    rec["levels_in_lds_outcomes_differing"] = int(sum(int(np.sum(a != b))
+                                                      for a, b in zip(base, outs["levels_in_lds"])))
     for k in ("pass_by_pass", "levels_in_lds", "batched", "batched_graph"):
         rec[k + "_shots_per_s"] = rec["shots_total"] / rec[k + "_s"]
         rec[k + "_speedup"] = rec["pass_by_pass_s"] / rec[k + "_s"]
     print("# small runs (%d circuits): pass by pass %.3f s, levels in LDS %.3f s (%.2fx), batched %.3f s (%.2fx), "
-          "graph %.3f s (%.2fx), identical %s" % (
+          "graph %.3f s (%.2fx), batched outcomes identical %s" % (
               len(circs), rec["pass_by_pass_s"], rec["levels_in_lds_s"], rec["levels_in_lds_speedup"],
               rec["batched_s"], rec["batched_speedup"], rec["batched_graph_s"], rec["batched_graph_speedup"],
               rec["outcomes_identical"]), file=sys.stderr, flush=True)
@@ -709,6 +739,7 @@ def main():
         print("# fidelity: F_pershot %.4f, dF (16,32,32) %+.4f +- %.4f, dF (8,8,16,16) %+.4f +- %.4f" %
               (fl["F_pershot"], fl["delta_F"], fl["delta_F_se"], fl["delta_F_tree4b"], fl["delta_F_tree4b_se"]),
               file=sys.stderr, flush=True)
+    line["memory_probe"] = memory_probe(torch)
     if not args.no_small_runs:
         line["small_runs"] = small_runs_leg(T, W, torch, args.seed)
     if args.precision:

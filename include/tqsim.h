@@ -123,7 +123,9 @@ typedef struct {
                                   one workgroup's LDS (up to 2^14 amplitudes, at most eight
                                   tiles): all passes of the level in one launch, one workgroup
                                   per state, the state kept in LDS between passes.  1 on, 2 off;
-                                  default 0: on.  Same results either way */
+                                  default 0: off (such states stay in the device's caches between
+                                  passes anyway, and the LDS cuts occupancy).  Amplitudes agree
+                                  to rounding with the pass-by-pass form */
 } tqs_tuning;
 
 /* Timing and traffic of one run. */

@@ -150,7 +150,7 @@ extern "C" tqs_status tqs_plan_create(const tqs_circuit *c, const tqs_tree *tree
     if (!tu.jit) tu.jit = c->n >= 16 ? 1u : 2u;
     if (!tu.mfma_min_ops) tu.mfma_min_ops = 6;
     if (tu.lds_levels > 2) return fail(TQS_E_ARG, "lds_levels must be 0 (default), 1 (on) or 2 (off)");
-    if (!tu.lds_levels) tu.lds_levels = 1;
+    if (!tu.lds_levels) tu.lds_levels = 2;
     const uint32_t tmax = prec == TQS_C64 ? 12 : 11;
     if (tu.tile_qubits < 10 || tu.tile_qubits > tmax)
         return fail(TQS_E_ARG, "tile_qubits must be in 10..%u at this precision", tmax);
