@@ -77,7 +77,12 @@ def time_form(T, torch, circuit, tree, seed, steps, warmup, tuning=None):
     t1 = time.perf_counter()
     nz = T.Noise.sample(circuit, tree, seed)
     t2 = time.perf_counter()
-    ws = T.Workspace(plan.workspace_bytes(nz))
+    # two workspaces: step k + 1 is started (its host work done and its
+    # launches queued) while step k's device work runs, then step k is
+    # finished (tqs_run_start / tqs_run_finish)
+    need = plan.workspace_bytes(nz)
+    wss = [T.Workspace(need), T.Workspace(need)]
+    ws = wss[0]
     stream = torch.cuda.current_stream()
     for _ in range(warmup):
         T.run(plan, nz, ws, stream)
@@ -87,8 +92,16 @@ def time_form(T, torch, circuit, tree, seed, steps, warmup, tuning=None):
            "ms_jit": 0.0, "bytes_jit": 0, "jit_launches": 0, "jit_states": 0, "pass_states": 0,
            "host_plan_ms": (t1 - t0) * 1e3, "host_noise_ms": (t2 - t1) * 1e3}
     t0 = time.perf_counter()
-    for _ in range(steps):
-        out, st = T.run(plan, nz, ws, stream, stats=True)
+    pending = None
+    done = []
+    for k in range(steps + 1):
+        nxt = T.run_start(plan, nz, wss[k % 2], stream, stats=True) if k < steps else None
+        if pending is not None:
+            done.append(pending.finish())
+        pending = nxt
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    for out, st in done:
         agg["ms_passes"] += st["ms_passes"]
         agg["ms_sample"] += st["ms_sample"]
         agg["bytes_passes"] += st["bytes_passes"]
@@ -99,8 +112,6 @@ def time_form(T, torch, circuit, tree, seed, steps, warmup, tuning=None):
         agg["nodes_merged"] = st["nodes_merged"]
         for k in ("ms_jit", "bytes_jit", "jit_launches", "jit_states", "pass_states"):
             agg[k] += st[k]
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
     passes_total = sum(plan.info(l)["passes_level"] * int(__import__("numpy").prod(tree[0][:l + 1]))
                        for l in range(len(tree[0])))
     agg["pass_launches_per_step"] = sum(

@@ -299,6 +299,22 @@ void tqs_plan_destroy(tqs_plan *p);
 tqs_status tqs_run(tqs_plan *p, const tqs_noise *nz, void *d_workspace, uint64_t ws_bytes,
                    void *stream, uint64_t *outcomes, tqs_run_stats *stats);
 
+/* The same run in two halves, so that the host work of the next run (its
+ * noise metadata, schedule and packing, about 2 ms for a 16384-leaf tree)
+ * overlaps this run's device work.  tqs_run_start does everything up to the
+ * outcome download, enqueued on `stream`, and returns without waiting;
+ * tqs_run_finish waits for it, writes `outcomes` (host, n_leaves, owned by
+ * the caller until then) and, with flags TQS_RUN_STATS, the statistics, and
+ * frees the run.  At most two runs of one plan may be in flight (TQS_E_ARG
+ * beyond), each with a workspace of its own; every started run must be
+ * finished, and before its plan is destroyed.  Errors as tqs_run; a start
+ * that fails leaves nothing to finish (*out NULL). */
+typedef struct tqs_pending tqs_pending;
+#define TQS_RUN_STATS 1u
+tqs_status tqs_run_start(tqs_plan *p, const tqs_noise *nz, void *d_workspace, uint64_t ws_bytes,
+                         void *stream, uint64_t *outcomes, uint32_t flags, tqs_pending **out);
+tqs_status tqs_run_finish(tqs_pending *run, tqs_run_stats *stats);
+
 /* As tqs_run, but only level-0 subtrees [first, last) are simulated; the
  * outcomes of their leaves go to outcomes[0 ..): resuming a failed run or
  * splitting one across devices gives the same outcomes as one whole run. */

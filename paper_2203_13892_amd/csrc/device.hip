@@ -18,6 +18,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <unordered_map>
@@ -1009,8 +1010,13 @@ static void route_passes(const tqs_plan *p, const HostMeta &hm, const std::vecto
             for (uint32_t c = 0; c < t.ccount; c++) {
                 const uint32_t node = (*sched)[t.cnode() + c];
                 const uint32_t e0 = hm.ev_off[node], e1 = hm.ev_off[node + 1];
-                const JitFit fit =
-                    jit_fit(runs[pi], blks[pi], pi, hm.ev_pos.data() + e0, hm.ev_dx.data() + e0, e1 - e0);
+                // only the node's events inside this pass matter for the fit
+                const uint32_t *ps = hm.ev_pos.data();
+                const uint32_t *pa = std::lower_bound(ps + e0, ps + e1, pi << 16);
+                const uint32_t *pb = std::lower_bound(pa, ps + e1, (pi + 1) << 16);
+                const JitFit fit = pa == pb ? JIT_YES
+                                            : jit_fit(runs[pi], blks[pi], pi, pa, hm.ev_dx.data() + (pa - ps),
+                                                      (uint32_t)(pb - pa));
                 if (fit == JIT_NO) {
                     no.push_back(c);
                     continue;
@@ -1222,13 +1228,13 @@ static tqs_status check_noise(const tqs_plan *p, const tqs_noise *nz) {
     return TQS_OK;
 }
 
-static hipEvent_t pool_event(tqs_plan *p, size_t i) {
-    while (p->events.size() <= i) {
+static hipEvent_t pool_event(std::vector<void *> &pool, size_t i) {
+    while (pool.size() <= i) {
         hipEvent_t e = nullptr;
         if (hipEventCreate(&e) != hipSuccess) return nullptr;
-        p->events.push_back((void *)e);
+        pool.push_back((void *)e);
     }
-    return (hipEvent_t)p->events[i];
+    return (hipEvent_t)pool[i];
 }
 
 struct Capture {
@@ -1321,10 +1327,87 @@ struct DrainOnError {
     DrainOnError &operator=(const DrainOnError &) = delete;
 };
 
+}  // namespace tqs
+
+// A run between tqs_run_start and tqs_run_finish: its staging slot, the
+// launch counts and the events its statistics are read from.
+struct tqs_pending {
+    tqs_plan *p = nullptr;
+    int slot = -1;
+    hipStream_t s = nullptr;
+    uint64_t *outcomes = nullptr;
+    uint64_t n_out = 0;
+    bool stats = false;
+    std::chrono::steady_clock::time_point t0;
+    uint64_t launches = 0, pass_launches = 0, pass_states = 0, bytes_passes = 0, bytes_sample = 0, merged = 0;
+    uint64_t jit_launches = 0, jit_states = 0, bytes_jit = 0, events = 0;
+    hipEvent_t e_begin = nullptr, e_end = nullptr;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> jit_ev, pass_ev, samp_ev;
+};
+
+namespace tqs {
+
+// A free staging slot of the plan (*k) with pinned buffers of at least the
+// given sizes, marked busy; TQS_E_ARG when both are in use.
+static tqs_status acquire_slot(tqs_plan *p, uint64_t meta_bytes, uint64_t out_bytes, int *k) {
+    *k = -1;
+    {
+        std::lock_guard<std::mutex> lock(p->slot_mu);
+        for (int i = 0; i < 2 && *k < 0; i++)
+            if (!p->slots[i].busy) {
+                p->slots[i].busy = true;
+                *k = i;
+            }
+    }
+    if (*k < 0) return fail(TQS_E_ARG, "two runs of this plan are already in flight (finish one first)");
+    tqs_plan::RunSlot &sl = p->slots[*k];
+    auto grow = [](void **buf, uint64_t *cap, uint64_t need) {
+        if (*cap >= need) return true;
+        if (*buf) (void)hipHostFree(*buf);
+        *buf = nullptr;
+        *cap = 0;
+        const uint64_t want = std::max<uint64_t>(need, 1ull << 16);
+        if (hipHostMalloc(buf, want, hipHostMallocDefault) != hipSuccess) {
+            *buf = nullptr;
+            return false;
+        }
+        *cap = want;
+        return true;
+    };
+    if (!grow(&sl.meta, &sl.meta_cap, meta_bytes) || !grow(&sl.out, &sl.out_cap, out_bytes)) {
+        std::lock_guard<std::mutex> lock(p->slot_mu);
+        sl.busy = false;
+        *k = -1;
+        return fail(TQS_E_OOM, "pinned host staging allocation failed");
+    }
+    return TQS_OK;
+}
+
+static void release_slot(tqs_plan *p, int k) {
+    if (k < 0) return;
+    std::lock_guard<std::mutex> lock(p->slot_mu);
+    p->slots[k].busy = false;
+}
+
+// Frees a started run's slot unless the run was handed over (done).
+struct SlotGuard {
+    tqs_plan *p;
+    int k = -1;
+    bool done = false;
+    ~SlotGuard() {
+        if (!done) release_slot(p, k);
+    }
+};
+
+// Everything of a run up to its outcome download, enqueued on the stream:
+// the host prologue (noise metadata, schedule, routing, packing into the
+// slot's pinned buffer), the upload, every pass and sampling launch, and
+// the download into the slot's pinned buffer.  Returns without waiting
+// (capture requests aside, which copy leaf states out as they come).
 template <typename R>
-static tqs_status run_t(tqs_plan *p, const tqs_noise *nz, unsigned char *ws, uint64_t ws_bytes,
-                        hipStream_t s, uint64_t first, uint64_t last, uint64_t *outcomes,
-                        tqs_run_stats *stats, const Capture &cap) {
+static tqs_status run_start_t(tqs_plan *p, const tqs_noise *nz, unsigned char *ws, uint64_t ws_bytes,
+                              hipStream_t s, uint64_t first, uint64_t last, uint64_t *outcomes,
+                              bool stats, const Capture &cap, tqs_pending *pd) {
     const auto t0 = std::chrono::steady_clock::now();
     tqs_status st = check_noise(p, nz);
     if (st) return st;
@@ -1361,21 +1444,27 @@ static tqs_status run_t(tqs_plan *p, const tqs_noise *nz, unsigned char *ws, uin
         return fail(TQS_E_WORKSPACE, "workspace has %llu bytes, the run needs %llu",
                     (unsigned long long)ws_bytes, (unsigned long long)Ly.total);
 
-    // pack the metadata exactly as laid out in the workspace
-    std::vector<unsigned char> hb(Ly.off_sums - Ly.off_meta, 0);
-    pack_meta<R>(p, nz, hm, sched, Ly, hb.data(), Ly.off_meta, &ftab);
+    // pack the metadata exactly as laid out in the workspace, into the
+    // slot's pinned buffer
+    const uint64_t meta_bytes = Ly.off_sums - Ly.off_meta;
+    SlotGuard sg{p};
+    st = acquire_slot(p, meta_bytes, n_out * 8, &sg.k);
+    if (st) return st;
+    tqs_plan::RunSlot &slot = p->slots[sg.k];
+    unsigned char *hb = static_cast<unsigned char *>(slot.meta);
+    std::memset(hb, 0, meta_bytes);
+    pack_meta<R>(p, nz, hm, sched, Ly, hb, Ly.off_meta, &ftab);
 
     DrainOnError drain(s);
     drain.armed = true;
     size_t ev_i = 0;
     hipEvent_t e_begin = nullptr, e_end = nullptr;
     if (stats) {
-        e_begin = pool_event(p, ev_i++);
+        e_begin = pool_event(slot.events, ev_i++);
         if (!e_begin) return fail(TQS_E_HIP, "hipEventCreate failed");
         HIP_TRY(hipEventRecord(e_begin, s), "hipEventRecord");
     }
-    HIP_TRY(hipMemcpyAsync(ws + Ly.off_meta, hb.data(), hb.size(), hipMemcpyHostToDevice, s),
-            "metadata upload");
+    HIP_TRY(hipMemcpyAsync(ws + Ly.off_meta, hb, meta_bytes, hipMemcpyHostToDevice, s), "metadata upload");
 
     // capture requests: leaf -> capture indices
     std::vector<std::vector<uint64_t>> cap_of;
@@ -1399,8 +1488,8 @@ static tqs_status run_t(tqs_plan *p, const tqs_noise *nz, unsigned char *ws, uin
         const MarkerRange range(mark);
         hipEvent_t ea = nullptr, eb = nullptr, ec = nullptr;
         if (stats) {
-            ea = pool_event(p, ev_i++);
-            eb = pool_event(p, ev_i++);
+            ea = pool_event(slot.events, ev_i++);
+            eb = pool_event(slot.events, ev_i++);
             if (!ea || !eb) return fail(TQS_E_HIP, "hipEventCreate failed");
             HIP_TRY(hipEventRecord(ea, s), "hipEventRecord");
         }
@@ -1435,8 +1524,8 @@ static tqs_status run_t(tqs_plan *p, const tqs_noise *nz, unsigned char *ws, uin
             hipEvent_t ej0 = nullptr, ej1 = nullptr;
             if (stats) {
                 // the specialised launch of this pass, timed on its own
-                ej0 = pool_event(p, ev_i++);
-                ej1 = pool_event(p, ev_i++);
+                ej0 = pool_event(slot.events, ev_i++);
+                ej1 = pool_event(slot.events, ev_i++);
                 if (!ej0 || !ej1) return fail(TQS_E_HIP, "hipEventCreate failed");
             }
             if (fault.kind == FaultSpec::LAUNCH && pass_iter == fault.at)
@@ -1474,7 +1563,7 @@ static tqs_status run_t(tqs_plan *p, const tqs_noise *nz, unsigned char *ws, uin
             bytes_sample += (uint64_t)t.ccount * (p->samp_tiled ? (8ull << (p->samp_nfree + p->samp_kv)) : state_bytes) +
                             (uint64_t)t.count * (Ly.amp_bytes << b);
             if (stats) {
-                ec = pool_event(p, ev_i++);
+                ec = pool_event(slot.events, ev_i++);
                 if (!ec) return fail(TQS_E_HIP, "hipEventCreate failed");
                 HIP_TRY(hipEventRecord(ec, s), "hipEventRecord");
                 samp_ev.push_back({eb, ec});
@@ -1509,56 +1598,99 @@ static tqs_status run_t(tqs_plan *p, const tqs_noise *nz, unsigned char *ws, uin
         }
         HIP_TRY(hipGetLastError(), "kernel launch");
     }
-    HIP_TRY(hipMemcpyAsync(outcomes, ws + Ly.off_out, n_out * 8, hipMemcpyDeviceToHost, s),
-            "outcome download");
+    HIP_TRY(hipMemcpyAsync(slot.out, ws + Ly.off_out, n_out * 8, hipMemcpyDeviceToHost, s), "outcome download");
     if (stats) {
-        e_end = pool_event(p, ev_i++);
+        e_end = pool_event(slot.events, ev_i++);
         if (!e_end) return fail(TQS_E_HIP, "hipEventCreate failed");
         HIP_TRY(hipEventRecord(e_end, s), "hipEventRecord");
     }
-    HIP_TRY(hipStreamSynchronize(s), "stream synchronize");
+    // the run is enqueued: the pending record owns its slot from here
+    pd->p = p;
+    pd->slot = sg.k;
+    pd->s = s;
+    pd->outcomes = outcomes;
+    pd->n_out = n_out;
+    pd->stats = stats;
+    pd->t0 = t0;
+    pd->launches = launches;
+    pd->pass_launches = pass_launches;
+    pd->pass_states = pass_states;
+    pd->bytes_passes = bytes_passes;
+    pd->bytes_sample = bytes_sample;
+    pd->merged = merged;
+    pd->jit_launches = jit_launches;
+    pd->jit_states = jit_states;
+    pd->bytes_jit = bytes_jit;
+    pd->events = nz->ev_gate.size();
+    pd->e_begin = e_begin;
+    pd->e_end = e_end;
+    pd->jit_ev = std::move(jit_ev);
+    pd->pass_ev = std::move(pass_ev);
+    pd->samp_ev = std::move(samp_ev);
+    sg.done = true;
     drain.armed = false;
+    return TQS_OK;
+}
+
+// Wait for a started run, copy its outcomes out and read its statistics;
+// the slot is free again whatever happens.
+static tqs_status run_finish(tqs_pending *pd, tqs_run_stats *stats) {
+    SlotGuard sg{pd->p};
+    sg.k = pd->slot;
+    HIP_TRY(hipStreamSynchronize(pd->s), "stream synchronize");
+    std::memcpy(pd->outcomes, pd->p->slots[pd->slot].out, pd->n_out * 8);
     if (stats) {
         std::memset(stats, 0, sizeof *stats);
-        float ms = 0;
-        HIP_TRY(hipEventElapsedTime(&ms, e_begin, e_end), "hipEventElapsedTime");
-        stats->ms_device = ms;
-        for (auto &pr : pass_ev) {
-            HIP_TRY(hipEventElapsedTime(&ms, pr.first, pr.second), "hipEventElapsedTime");
-            stats->ms_passes += ms;
+        if (pd->stats) {
+            float ms = 0;
+            HIP_TRY(hipEventElapsedTime(&ms, pd->e_begin, pd->e_end), "hipEventElapsedTime");
+            stats->ms_device = ms;
+            for (auto &pr : pd->pass_ev) {
+                HIP_TRY(hipEventElapsedTime(&ms, pr.first, pr.second), "hipEventElapsedTime");
+                stats->ms_passes += ms;
+            }
+            for (auto &pr : pd->samp_ev) {
+                HIP_TRY(hipEventElapsedTime(&ms, pr.first, pr.second), "hipEventElapsedTime");
+                stats->ms_sample += ms;
+            }
+            for (auto &pr : pd->jit_ev) {
+                HIP_TRY(hipEventElapsedTime(&ms, pr.first, pr.second), "hipEventElapsedTime");
+                stats->ms_jit += ms;
+            }
         }
-        for (auto &pr : samp_ev) {
-            HIP_TRY(hipEventElapsedTime(&ms, pr.first, pr.second), "hipEventElapsedTime");
-            stats->ms_sample += ms;
-        }
-        stats->launches = launches;
-        stats->pass_launches = pass_launches;
-        stats->pass_states = pass_states;
-        stats->bytes_passes = bytes_passes;
-        stats->bytes_sample = bytes_sample;
-        stats->events = nz->ev_gate.size();
-        stats->nodes_merged = merged;
-        stats->jit_launches = jit_launches;
-        stats->jit_states = jit_states;
-        stats->bytes_jit = bytes_jit;
-        for (auto &pr : jit_ev) {
-            HIP_TRY(hipEventElapsedTime(&ms, pr.first, pr.second), "hipEventElapsedTime");
-            stats->ms_jit += ms;
-        }
-        stats->ms_wall =
-            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        stats->launches = pd->launches;
+        stats->pass_launches = pd->pass_launches;
+        stats->pass_states = pd->pass_states;
+        stats->bytes_passes = pd->bytes_passes;
+        stats->bytes_sample = pd->bytes_sample;
+        stats->events = pd->events;
+        stats->nodes_merged = pd->merged;
+        stats->jit_launches = pd->jit_launches;
+        stats->jit_states = pd->jit_states;
+        stats->bytes_jit = pd->bytes_jit;
+        stats->ms_wall = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - pd->t0).count();
     }
     return TQS_OK;
 }
 
-static tqs_status run_any(tqs_plan *p, const tqs_noise *nz, void *ws, uint64_t ws_bytes, void *stream,
-                          uint64_t first, uint64_t last, uint64_t *outcomes, tqs_run_stats *stats,
-                          const Capture &cap) {
+static tqs_status run_start_any(tqs_plan *p, const tqs_noise *nz, void *ws, uint64_t ws_bytes, void *stream,
+                                uint64_t first, uint64_t last, uint64_t *outcomes, bool stats, const Capture &cap,
+                                tqs_pending *pd) {
     if (!p) return fail(TQS_E_ARG, "plan is NULL");
     hipStream_t s = (hipStream_t)stream;
     if (p->prec == TQS_C64)
-        return run_t<float>(p, nz, (unsigned char *)ws, ws_bytes, s, first, last, outcomes, stats, cap);
-    return run_t<double>(p, nz, (unsigned char *)ws, ws_bytes, s, first, last, outcomes, stats, cap);
+        return run_start_t<float>(p, nz, (unsigned char *)ws, ws_bytes, s, first, last, outcomes, stats, cap, pd);
+    return run_start_t<double>(p, nz, (unsigned char *)ws, ws_bytes, s, first, last, outcomes, stats, cap, pd);
+}
+
+// A whole run: started, then finished at once.
+static tqs_status run_any(tqs_plan *p, const tqs_noise *nz, void *ws, uint64_t ws_bytes, void *stream,
+                          uint64_t first, uint64_t last, uint64_t *outcomes, tqs_run_stats *stats,
+                          const Capture &cap) {
+    tqs_pending pd;
+    const tqs_status st = run_start_any(p, nz, ws, ws_bytes, stream, first, last, outcomes, stats != nullptr, cap, &pd);
+    if (st) return st;
+    return run_finish(&pd, stats);
 }
 
 // ------------------------------------------------------------- batches --
@@ -1759,7 +1891,11 @@ static tqs_status batch_run_t(tqs_batch *B, unsigned char *ws, uint64_t ws_bytes
 using namespace tqs;
 
 tqs_plan::~tqs_plan() {
-    for (void *e : events) (void)hipEventDestroy((hipEvent_t)e);
+    for (RunSlot &sl : slots) {
+        for (void *e : sl.events) (void)hipEventDestroy((hipEvent_t)e);
+        if (sl.meta) (void)hipHostFree(sl.meta);
+        if (sl.out) (void)hipHostFree(sl.out);
+    }
     jit_release(this);
 }
 
@@ -1844,6 +1980,30 @@ tqs_status tqs_run_range(tqs_plan *p, const tqs_noise *nz, void *d_workspace, ui
                          tqs_run_stats *stats) {
     TQS_GUARD_BEGIN
     return run_any(p, nz, d_workspace, ws_bytes, stream, first, last, outcomes, stats, Capture());
+    TQS_GUARD_END
+}
+
+tqs_status tqs_run_start(tqs_plan *p, const tqs_noise *nz, void *d_workspace, uint64_t ws_bytes, void *stream,
+                         uint64_t *outcomes, uint32_t flags, tqs_pending **out) {
+    TQS_GUARD_BEGIN
+    if (!out) return fail(TQS_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (!p) return fail(TQS_E_ARG, "plan is NULL");
+    if (flags & ~(uint32_t)TQS_RUN_STATS) return fail(TQS_E_ARG, "unknown flags 0x%x", flags);
+    std::unique_ptr<tqs_pending> pd(new tqs_pending);
+    const tqs_status st = run_start_any(p, nz, d_workspace, ws_bytes, stream, 0, p->arity[0], outcomes,
+                                        (flags & TQS_RUN_STATS) != 0, Capture(), pd.get());
+    if (st) return st;
+    *out = pd.release();
+    return TQS_OK;
+    TQS_GUARD_END
+}
+
+tqs_status tqs_run_finish(tqs_pending *r, tqs_run_stats *stats) {
+    TQS_GUARD_BEGIN
+    if (!r) return fail(TQS_E_ARG, "run is NULL");
+    std::unique_ptr<tqs_pending> pd(r);
+    return run_finish(pd.get(), stats);
     TQS_GUARD_END
 }
 

@@ -243,7 +243,27 @@ int butterfly(const tqs_plan *p, const OpDesc &o, double *s) {
     return neg;
 }
 
-void emit_dense(std::string &s, const tqs_plan *p, const OpDesc &o, double *scale) {
+// Lane bits an op mixes (dense ops whose target, or either qubit of a 4x4,
+// is a lane qubit); a deferred per-lane sign on such a bit must be applied
+// first.
+uint32_t lane_bits_mixed(const OpDesc &o) {
+    if (o.kind == OP_DIAGRUN) return 0;
+    if (o.kind == OP_DENSE1) {
+        const uint32_t tq = o.nq == 2 ? o.tq : 0u;
+        return o.role[tq] == ROLE_LANE ? 1u << o.pos[tq] : 0u;
+    }
+    uint32_t m = 0;
+    for (uint32_t q = 0; q < 2; q++)
+        if (o.role[q] == ROLE_LANE) m |= 1u << o.pos[q];
+    return m;
+}
+
+// sign_bits: lane bits the deferred per-lane sign depends on (updated).
+void emit_dense(std::string &s, const tqs_plan *p, const OpDesc &o, double *scale, uint32_t *sign_bits) {
+    if (lane_bits_mixed(o) & *sign_bits) {
+        s += "  flush_sign<R, RB>(v, sg);\n";
+        *sign_bits = 0;
+    }
     appendf(s, "  advance(w, KEY | %uu);\n", (unsigned)o.slot0);
     appendf(s,
             "  { const uint32_t xl = local2(w.fx, %u, %u, %u), zl = local2(w.fz, %u, %u, %u);\n",
@@ -253,7 +273,12 @@ void emit_dense(std::string &s, const tqs_plan *p, const OpDesc &o, double *scal
     if (neg >= 0) {
         // its common factor joins the pass's scale
         *scale *= bs;
-        appendf(s, "    bf<R, RB, %s, %u, %d>(v, xl, zl, w); }\n", role_name(o.role[0]), (unsigned)o.pos[0], neg);
+        if (o.role[0] == ROLE_LANE) {
+            appendf(s, "    bf_lane<R, RB, %u, %d>(v, xl, zl, w, sg); }\n", (unsigned)o.pos[0], neg);
+            *sign_bits |= 1u << o.pos[0];
+        } else {
+            appendf(s, "    bf_reg<R, RB, %u, %d>(v, xl, zl); }\n", (unsigned)o.pos[0], neg);
+        }
         return;
     }
     if (o.kind == OP_DENSE1) {
@@ -334,7 +359,14 @@ void emit_ops(std::string &s, const tqs_plan *p, uint32_t pi) {
                 pi);
     }
     uint32_t table_slot = 0;
-    double scale = 1.0;  // product of the butterflies' common factors
+    double scale = 1.0;      // product of the butterflies' common factors
+    uint32_t sign_bits = 0;  // lane bits of the deferred per-lane sign
+    bool lane_bf = false;
+    for (uint32_t oi = d.op_begin; oi < d.op_begin + d.op_count; oi++) {
+        double bs = 0.0;
+        if (butterfly(p, p->ops[oi], &bs) >= 0 && p->ops[oi].role[0] == ROLE_LANE) lane_bf = true;
+    }
+    if (lane_bf) s += "  R sg = R(1);  // deferred per-lane sign of the lane butterflies\n";
     size_t bi = 0;
     while (bi < p->blocks.size() && p->blocks[bi].pass < pi) bi++;
     for (uint32_t oi = d.op_begin; oi < d.op_begin + d.op_count; oi++) {
@@ -352,9 +384,10 @@ void emit_ops(std::string &s, const tqs_plan *p, uint32_t pi) {
             continue;
         }
         if (o.kind == OP_DIAGRUN) emit_diag(s, p, d, o, c64, table_slot);
-        else emit_dense(s, p, o, &scale);
+        else emit_dense(s, p, o, &scale, &sign_bits);
     }
-    if (scale != 1.0) appendf(s, "  scale_tile<R, RB>(v, R(%.17g));\n", scale);
+    if (sign_bits) appendf(s, "  scale_tile<R, RB>(v, R(%.17g) * sg);\n", scale);
+    else if (scale != 1.0) appendf(s, "  scale_tile<R, RB>(v, R(%.17g));\n", scale);
 }
 
 // Store v to the node's state in HBM, with the sampling partials when the
@@ -598,7 +631,10 @@ void jit_frame_tables(const tqs_plan *p, uint32_t pi, uint32_t fx0, const uint32
                 const uint32_t y = t ^ fr;
                 uint32_t r = 0;
                 for (uint32_t q = 0; q < g.nq; q++) r |= ((y >> g.pos[q]) & 1u) << q;
-                (*out)[at + t] *= p->mats[g.d + r];
+                // (plain complex product: std::complex's operator* goes through
+                // a library call with infinity and NaN recovery)
+                const cd a = (*out)[at + t], b = p->mats[g.d + r];
+                (*out)[at + t] = cd(a.real() * b.real() - a.imag() * b.imag(), a.real() * b.imag() + a.imag() * b.real());
             }
         }
     }

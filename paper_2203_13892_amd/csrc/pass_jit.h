@@ -183,81 +183,89 @@ __device__ __forceinline__ void d1(cplx<R> (&v)[1 << RB], kptr<cplx<R>> G, uint3
 // pass multiplies the tile by the product of these factors once, before it
 // stores it (scale_tile).  NEG: bit 2r + c set where sigma_rc = -1.  The
 // frame on the qubit conjugates the signs as conj_entry does a matrix,
-// sigma'_rc = sigma_{r^x, c^x} (-1)^{z r + z c}.  With no frame on the qubit
-// (the common case) the signs are compile-time: one add or subtract per
-// real output for a register target; for a lane target one multiply-add
-// (own value times a per-lane sign, plus or minus the partner's) where
-// the partner comes from the swizzle or permute unit.
+// sigma'_rc = sigma_{r^x, c^x} (-1)^{z r + z c}.
 template <int NEG, int RR, int CC>
 struct Sgn {
     static constexpr int value = ((NEG >> (2 * RR + CC)) & 1) ? -1 : 1;
 };
 
-template <typename R, int RB, int TROLE, int TPOS, int NEG>
-__device__ __forceinline__ void bf(cplx<R> (&v)[1 << RB], uint32_t xl, uint32_t zl, const Wave &w) {
+template <int NEG, typename R>
+__device__ __forceinline__ R conj_sign(uint32_t r, uint32_t c, uint32_t xl, uint32_t zl) {
+    const uint32_t flip = ((uint32_t)(NEG >> (2 * (r ^ xl) + (c ^ xl))) & 1u) ^ ((zl & r) ^ (zl & c));
+    return flip ? R(-1) : R(1);
+}
+
+// Register target: one add or subtract per real output with no frame on
+// the qubit (signs known when the pass is compiled), a multiply and a
+// multiply-add with one (signs from the frame).
+template <typename R, int RB, int TPOS, int NEG>
+__device__ __forceinline__ void bf_reg(cplx<R> (&v)[1 << RB], uint32_t xl, uint32_t zl) {
     constexpr int NJ = 1 << RB;
     if ((xl | zl) == 0) {
         constexpr int s00 = Sgn<NEG, 0, 0>::value, s01 = Sgn<NEG, 0, 1>::value;
         constexpr int s10 = Sgn<NEG, 1, 0>::value, s11 = Sgn<NEG, 1, 1>::value;
-        if constexpr (TROLE == ROLE_REG) {
-            sfor<NJ>([&](auto Jc) __attribute__((always_inline)) {
-                constexpr int j = decltype(Jc)::value;
-                if constexpr (!(j & (1 << TPOS))) {
-                    const cplx<R> x0 = v[j], x1 = v[j | (1 << TPOS)];
-                    v[j] = {R(s00) * x0.re + R(s01) * x1.re, R(s00) * x0.im + R(s01) * x1.im};
-                    v[j | (1 << TPOS)] = {R(s10) * x0.re + R(s11) * x1.re, R(s10) * x0.im + R(s11) * x1.im};
-                }
-            });
-        } else {
-            // own row b: own value in column b, partner's in column 1 - b
-            const bool b = ((w.L >> TPOS) & 1u) != 0;
-            const R a = b ? R(s11) : R(s00), c = b ? R(s10) : R(s01);
-            sfor<NJ>([&](auto Jc) __attribute__((always_inline)) {
-                constexpr int j = decltype(Jc)::value;
-                const cplx<R> p = lane_xor_c<1 << TPOS>(v[j]);
-                if constexpr (s01 == s10)
-                    v[j] = {a * v[j].re + R(s01) * p.re, a * v[j].im + R(s01) * p.im};
-                else if constexpr (s00 == s11)
-                    v[j] = {R(s00) * v[j].re + c * p.re, R(s00) * v[j].im + c * p.im};
-                else
-                    v[j] = {a * v[j].re + c * p.re, a * v[j].im + c * p.im};
-                pin(v[j]);
-                shuffle_fence<j>();
-            });
-        }
-    } else {
-        R S[4];
-#pragma unroll
-        for (uint32_t r = 0; r < 2; r++)
-#pragma unroll
-            for (uint32_t c = 0; c < 2; c++) {
-                const uint32_t flip = ((NEG >> (2 * (r ^ xl) + (c ^ xl))) & 1u) ^ ((zl & r) ^ (zl & c));
-                S[2 * r + c] = flip ? R(-1) : R(1);
+        sfor<NJ>([&](auto Jc) __attribute__((always_inline)) {
+            constexpr int j = decltype(Jc)::value;
+            if constexpr (!(j & (1 << TPOS))) {
+                const cplx<R> x0 = v[j], x1 = v[j | (1 << TPOS)];
+                v[j] = {R(s00) * x0.re + R(s01) * x1.re, R(s00) * x0.im + R(s01) * x1.im};
+                v[j | (1 << TPOS)] = {R(s10) * x0.re + R(s11) * x1.re, R(s10) * x0.im + R(s11) * x1.im};
             }
-        if constexpr (TROLE == ROLE_REG) {
-            sfor<NJ>([&](auto Jc) __attribute__((always_inline)) {
-                constexpr int j = decltype(Jc)::value;
-                if constexpr (!(j & (1 << TPOS))) {
-                    const cplx<R> x0 = v[j], x1 = v[j | (1 << TPOS)];
-                    v[j] = {S[0] * x0.re + S[1] * x1.re, S[0] * x0.im + S[1] * x1.im};
-                    v[j | (1 << TPOS)] = {S[2] * x0.re + S[3] * x1.re, S[2] * x0.im + S[3] * x1.im};
-                }
-            });
-        } else {
-            const bool b = ((w.L >> TPOS) & 1u) != 0;
-            const R a = b ? S[3] : S[0], c = b ? S[2] : S[1];
-            sfor<NJ>([&](auto Jc) __attribute__((always_inline)) {
-                constexpr int j = decltype(Jc)::value;
-                const cplx<R> p = lane_xor_c<1 << TPOS>(v[j]);
-                v[j] = {a * v[j].re + c * p.re, a * v[j].im + c * p.im};
-                pin(v[j]);
-                shuffle_fence<j>();
-            });
-        }
+        });
+    } else {
+        const R S0 = conj_sign<NEG, R>(0, 0, xl, zl), S1 = conj_sign<NEG, R>(0, 1, xl, zl);
+        const R S2 = conj_sign<NEG, R>(1, 0, xl, zl), S3 = conj_sign<NEG, R>(1, 1, xl, zl);
+        sfor<NJ>([&](auto Jc) __attribute__((always_inline)) {
+            constexpr int j = decltype(Jc)::value;
+            if constexpr (!(j & (1 << TPOS))) {
+                const cplx<R> x0 = v[j], x1 = v[j | (1 << TPOS)];
+                v[j] = {S0 * x0.re + S1 * x1.re, S0 * x0.im + S1 * x1.im};
+                v[j | (1 << TPOS)] = {S2 * x0.re + S3 * x1.re, S2 * x0.im + S3 * x1.im};
+            }
+        });
     }
 }
 
-// The tile times a real factor (the butterflies' common factors).
+// Lane target: own row b (own value in column b, the partner's in column
+// 1 - b), out = a x_own + c x_partner with a, c = +-1 per lane.  Written as
+// a (x_own + a c x_partner): one multiply-add per real output (the
+// partner's value feeds it straight from the quad permute, swizzle or
+// permute), and the per-lane sign a joins `sg`, the tile's deferred
+// per-lane sign.  That sign depends on lane bit TPOS only, so it commutes
+// with every later op that does not mix that bit (diagonal runs, register
+// ops, ops on other lane bits, ops controlled by it); the pass applies it
+// with the common factors before the store, or earlier (flush_sign) before
+// an op that mixes the bit.  The products are exact, so the results are
+// those of a x_own + c x_partner rounded once.
+template <typename R, int RB, int TPOS, int NEG>
+__device__ __forceinline__ void bf_lane(cplx<R> (&v)[1 << RB], uint32_t xl, uint32_t zl, const Wave &w, R &sg) {
+    constexpr int NJ = 1 << RB;
+    const bool b = ((w.L >> TPOS) & 1u) != 0;
+    const R a = b ? conj_sign<NEG, R>(1, 1, xl, zl) : conj_sign<NEG, R>(0, 0, xl, zl);
+    const R k = a * (b ? conj_sign<NEG, R>(1, 0, xl, zl) : conj_sign<NEG, R>(0, 1, xl, zl));
+    sfor<NJ>([&](auto Jc) __attribute__((always_inline)) {
+        constexpr int j = decltype(Jc)::value;
+        const cplx<R> p = lane_xor_c<1 << TPOS>(v[j]);
+        v[j] = {v[j].re + k * p.re, v[j].im + k * p.im};
+        pin(v[j]);
+        shuffle_fence<j>();
+    });
+    sg *= a;
+}
+
+// The deferred per-lane sign applied now (before an op that mixes a lane
+// bit it depends on).
+template <typename R, int RB>
+__device__ __forceinline__ void flush_sign(cplx<R> (&v)[1 << RB], R &sg) {
+    sfor<(1 << RB)>([&](auto Jc) __attribute__((always_inline)) {
+        constexpr int j = decltype(Jc)::value;
+        v[j] = {v[j].re * sg, v[j].im * sg};
+    });
+    sg = R(1);
+}
+
+// The tile times a real factor (the butterflies' common factors, with the
+// deferred per-lane sign).
 template <typename R, int RB>
 __device__ __forceinline__ void scale_tile(cplx<R> (&v)[1 << RB], R s) {
     sfor<(1 << RB)>([&](auto Jc) __attribute__((always_inline)) {

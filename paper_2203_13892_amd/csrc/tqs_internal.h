@@ -3,6 +3,7 @@
 
 #include <complex>
 #include <cstdint>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -103,7 +104,20 @@ struct tqs_plan {
     uint8_t samp_bsrc[32] = {0};
     std::vector<uint32_t> chunk;  // live states per level
     uint32_t sample_b = 12;
-    std::vector<void *> events;  // hipEvent_t pool for run statistics
+    // host side of the runs in flight (tqs_run_start to tqs_run_finish): two
+    // slots, each with pinned buffers for the metadata upload and the
+    // outcome download (so neither copy waits for the host) and its own
+    // hipEvent_t pool for run statistics
+    struct RunSlot {
+        void *meta = nullptr;
+        uint64_t meta_cap = 0;
+        void *out = nullptr;
+        uint64_t out_cap = 0;
+        std::vector<void *> events;
+        bool busy = false;
+    };
+    RunSlot slots[2];
+    std::mutex slot_mu;
     // plan-specialised pass kernels (jit.cpp): code object, the module
     // loaded on jit_device, one function per pass (NULL: generic kernel)
     std::vector<tqs::FusedBlock> blocks;  // sorted by pass, then op

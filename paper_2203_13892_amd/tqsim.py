@@ -64,6 +64,8 @@ SIGNATURES = {
     "tqs_noise_flips": (i32, [vp, P(P(u32))]),
     "tqs_run": (i32, [vp, vp, vp, u64, vp, P(u64), P(TqsRunStats)]),
     "tqs_run_range": (i32, [vp, vp, vp, u64, vp, u64, u64, P(u64), P(TqsRunStats)]),
+    "tqs_run_start": (i32, [vp, vp, vp, u64, vp, P(u64), u32, P(vp)]),
+    "tqs_run_finish": (i32, [vp, P(TqsRunStats)]),
     "tqs_run_capture": (i32, [vp, vp, vp, u64, vp, P(u64), P(u64), u64, P(dbl)]),
     "tqs_run_noalloc": (i32, [vp, vp, vp, P(u64)]),
     "tqs_histogram": (i32, [P(u64), u64, P(u64), P(u64), P(u64)]),
@@ -381,6 +383,39 @@ def run(plan: Plan, noise: Noise, workspace: Workspace = None, stream=None, stat
                                  first, last, _ptr(out, u64),
                                  C.byref(st) if st is not None else None))
     return (out, st.as_dict()) if stats else out
+
+
+class PendingRun:
+    """A run started with ``run_start``: ``finish()`` waits for it and
+    returns its outcomes (and statistics when asked for at the start)."""
+
+    def __init__(self, h, out, stats, keep):
+        self.h, self.out, self.stats, self._keep = h, out, stats, keep
+
+    def finish(self):
+        if self.h is None:
+            raise RuntimeError("run already finished")
+        st = TqsRunStats() if self.stats else None
+        h, self.h = self.h, None
+        _check(lib.tqs_run_finish(h, C.byref(st) if st is not None else None))
+        self._keep = None
+        return (self.out, st.as_dict()) if self.stats else self.out
+
+    def __del__(self):
+        if getattr(self, "h", None) is not None and lib is not None:
+            lib.tqs_run_finish(self.h, None)
+
+
+def run_start(plan: Plan, noise: Noise, workspace: Workspace, stream=None, stats: bool = False) -> PendingRun:
+    """Start a run (tqs_run_start): its host work and every launch are done
+    when this returns, its device work may still be running.  At most two
+    runs of one plan in flight, each with its own workspace."""
+    out = np.zeros(plan.n_leaves, np.uint64)
+    h = vp()
+    _check(lib.tqs_run_start(plan.h, noise.h, vp(workspace.ptr), workspace.nbytes, _stream(stream),
+                             _ptr(out, u64), 1 if stats else 0, C.byref(h)))
+    # the plan, noise and workspace stay alive while the run is in flight
+    return PendingRun(h, out, stats, (plan, noise, workspace))
 
 
 def run_noalloc(plan: Plan, noise: Noise, stream=None):
