@@ -183,13 +183,18 @@ def precision_sweep(T, W, torch, seed):
         outs = {}
         for prec, (first, last) in (("c64", (0, shape[0])), ("c128", (0, 1))):
             plan = T.Plan(c, tree, prec)
+            # the plan's specialised kernels are compiled beforehand, as a
+            # plan does once (timed on its own)
+            tc = time.perf_counter()
+            plan.compile()
+            compile_s = time.perf_counter() - tc
             ws = T.Workspace(plan.workspace_bytes(nz))
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             o, st = T.run(plan, nz, ws, stats=True, subtrees=(first, last))
             dt = time.perf_counter() - t0
             outs[prec] = o
-            rec[prec] = {"leaves": int(o.size), "shots_per_s": o.size / dt, "s": dt,
+            rec[prec] = {"leaves": int(o.size), "shots_per_s": o.size / dt, "s": dt, "compile_s": compile_s,
                          "pass_GBps": st["bytes_passes"] / (st["ms_passes"] * 1e-3) / 1e9}
             del ws
         # complex64 against complex128 amplitudes of two trajectories of the
@@ -349,7 +354,7 @@ def small_runs_leg(T, W, torch, seed, shots=2048, max_qubits=14, reps=3):
     return rec
 
 
-def batch_bench(T, W, torch, seed, shots=2048, budget_gib=32):
+def batch_bench(T, W, torch, seed, shots=2048, budget_gib=32, extra=False):
     """The mixed workload per-shot at 2048 shots each: one run after another
     (default tuning) against batches (runs grouped in qubit order up to a
     workspace budget, each batch advancing its runs together), with the
@@ -361,6 +366,9 @@ def batch_bench(T, W, torch, seed, shots=2048, budget_gib=32):
     from paper_2203_13892_amd import autotune as AT
     circs = batch_workload(W)
 
+    def note(msg):
+        print("# batch: " + msg, file=sys.stderr, flush=True)
+
     def build(tunings, shape=None):
         items = []
         for i, (name, wc) in enumerate(circs):
@@ -370,9 +378,30 @@ def batch_bench(T, W, torch, seed, shots=2048, budget_gib=32):
             tun = dict(tunings.get(name.split("_")[0], {}))
             # live states per run: about 256 MiB of states, at most 512
             tun["chunk_states"] = int(max(1, min(512, (256 << 20) // (8 << wc.n))))
+            # one run per circuit: the generic kernels (a plan's specialised
+            # kernels cost a hipRTC compile of about a second, more than one
+            # such run)
+            tun["jit"] = 2
             plan = T.Plan(c, tree, "c64", tun)
             items.append((wc.n, plan, T.Noise.sample(c, tree, seed + i), tun.get("tile_qubits", 11)))
         return items
+
+    def pipelined(items):
+        # one run after another, each started before the previous one is
+        # finished (two workspaces): host work overlaps device work
+        wss = [T.Workspace(max(p.workspace_bytes(nz) for _, p, nz, _ in items)) for _ in range(2)]
+        for _, p, nz, _ in items[:4]:
+            T.run(p, nz, wss[0])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out, pend = [], None
+        for k in range(len(items) + 1):
+            nxt = T.run_start(items[k][1], items[k][2], wss[k % 2]) if k < len(items) else None
+            if pend is not None:
+                out.append(pend.finish())
+            pend = nxt
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, out
 
     def sequential(items):
         ws = T.Workspace(max(p.workspace_bytes(nz) for _, p, nz, _ in items))
@@ -416,43 +445,56 @@ def batch_bench(T, W, torch, seed, shots=2048, budget_gib=32):
 
     rec = {"workload": "512 circuits of 12-22 qubits (qft, ghz, qaoa p=2, brick-wall), 2048 shots each, "
                        "per-shot, depolarizing(1e-3,1e-2)", "runs": len(circs), "shots_total": shots * len(circs)}
-    def note(msg):
-        print("# batch: " + msg, file=sys.stderr, flush=True)
 
     items = build({})
     note("%d runs planned" % len(items))
     t_seq, seq = sequential(items)
     note("one after another %.2f s" % t_seq)
+    t_pip, pip = pipelined(items)
+    note("one after another, pipelined %.2f s" % t_pip)
     t_bat, bat, nb = batched(items)
     note("batched %.2f s in %d batches" % (t_bat, nb))
-    rec["sequential_s"], rec["batched_s"], rec["batches"] = t_seq, t_bat, nb
+    rec["sequential_s"], rec["pipelined_s"], rec["batched_s"], rec["batches"] = t_seq, t_pip, t_bat, nb
+    # what a plan's specialised kernels would cost first: the hipRTC
+    # compile of the four 22-qubit circuits' plans
+    comp = []
+    for name, wc in [(nm, w) for nm, w in circs if w.n == 22][:4]:
+        c = T.Circuit.from_workload(wc)
+        plan = T.Plan(c, ([shots], [0, len(wc)]), "c64", {"jit": 1})
+        t0 = time.perf_counter()
+        plan.compile()
+        comp.append(time.perf_counter() - t0)
+    rec["jit_compile_s_22q"] = comp
+    note("hipRTC compile of 22-qubit plans: %s s" % ", ".join("%.2f" % x for x in comp))
     rec["outcomes_identical"] = bool(all(np.array_equal(a, b) for a, b in zip(seq, bat)))
+    rec["pipelined_outcomes_identical"] = bool(all(np.array_equal(a, b) for a, b in zip(seq, pip)))
     t_bg, bat_g, _ = batched(items, graph=True)
     note("batched, graph replay %.2f s" % t_bg)
     rec["batched_graph_s"] = t_bg
     rec["graph_outcomes_identical"] = bool(all(np.array_equal(a, b) for a, b in zip(seq, bat_g)))
-    # autotuned tile width and pass bound per family and size
-    tunings, t_tune = {}, time.perf_counter()
-    for name, wc in circs:
-        key = name.split("_")[0]
-        if key not in tunings:
-            tunings[key], _ = AT.autotune(T, torch, wc)
-            note("autotuned %s: %s" % (key, tunings[key]))
-    t_tune = time.perf_counter() - t_tune
-    items_t = build(tunings)
-    t_auto, _, nb_a = batched(items_t)
-    note("autotuned batched %.2f s" % t_auto)
-    rec["autotuned_batched_s"], rec["autotune_s"], rec["autotuned_batches"] = t_auto, t_tune, nb_a
-    rec["tunings"] = tunings
-    # the same runs as trees (8, 16, 16): tree reuse and batching together
-    items_tree = build({}, (8, 16, 16))
-    t_tseq, tseq = sequential(items_tree)
-    t_tbat, tbat, _ = batched(items_tree)
-    note("trees (8, 16, 16): one after another %.2f s, batched %.2f s" % (t_tseq, t_tbat))
-    rec["tree_shape"] = [8, 16, 16]
-    rec["tree_sequential_s"], rec["tree_batched_s"] = t_tseq, t_tbat
-    rec["tree_outcomes_identical"] = bool(all(np.array_equal(a, b) for a, b in zip(tseq, tbat)))
-    del items_tree, tseq, tbat
+    if extra:
+        # autotuned tile width and pass bound per family and size
+        tunings, t_tune = {}, time.perf_counter()
+        for name, wc in circs:
+            key = name.split("_")[0]
+            if key not in tunings:
+                tunings[key], _ = AT.autotune(T, torch, wc)
+                note("autotuned %s: %s" % (key, tunings[key]))
+        t_tune = time.perf_counter() - t_tune
+        items_t = build(tunings)
+        t_auto, _, nb_a = batched(items_t)
+        note("autotuned batched %.2f s" % t_auto)
+        rec["autotuned_batched_s"], rec["autotune_s"], rec["autotuned_batches"] = t_auto, t_tune, nb_a
+        rec["tunings"] = tunings
+        # the same runs as trees (8, 16, 16): tree reuse and batching together
+        items_tree = build({}, (8, 16, 16))
+        t_tseq, tseq = sequential(items_tree)
+        t_tbat, tbat, _ = batched(items_tree)
+        note("trees (8, 16, 16): one after another %.2f s, batched %.2f s" % (t_tseq, t_tbat))
+        rec["tree_shape"] = [8, 16, 16]
+        rec["tree_sequential_s"], rec["tree_batched_s"] = t_tseq, t_tbat
+        rec["tree_outcomes_identical"] = bool(all(np.array_equal(a, b) for a, b in zip(tseq, tbat)))
+        del items_tree, tseq, tbat
     # the small runs alone
     small = [it for it in items if it[0] <= 16]
     t_ss, _ = sequential(small)
@@ -460,13 +502,16 @@ def batch_bench(T, W, torch, seed, shots=2048, budget_gib=32):
     t_sg, _, _ = batched(small, graph=True)
     rec["small_runs"] = len(small)
     rec["small_sequential_s"], rec["small_batched_s"], rec["small_batched_graph_s"] = t_ss, t_sb, t_sg
-    for k in ("sequential", "batched", "batched_graph", "autotuned_batched", "tree_sequential", "tree_batched"):
-        rec[k + "_shots_per_s"] = rec["shots_total"] / rec[k + "_s"]
+    for k in ("sequential", "pipelined", "batched", "batched_graph", "autotuned_batched", "tree_sequential",
+              "tree_batched"):
+        if k + "_s" in rec:
+            rec[k + "_shots_per_s"] = rec["shots_total"] / rec[k + "_s"]
     rec["small_batch_speedup"] = t_ss / t_sb
     rec["small_batch_graph_speedup"] = t_ss / t_sg
-    print("# batch: sequential %.2f s, batched %.2f s (%d batches, identical %s), autotuned batched %.2f s; "
+    print("# batch: sequential %.2f s, pipelined %.2f s, batched %.2f s (%d batches, identical %s); "
           "12-16q runs: sequential %.3f s, batched %.3f s, graph replay %.3f s" % (
-              t_seq, t_bat, nb, rec["outcomes_identical"], t_auto, t_ss, t_sb, t_sg), file=sys.stderr, flush=True)
+              t_seq, t_pip, t_bat, nb, rec["outcomes_identical"], t_ss, t_sb, t_sg),
+          file=sys.stderr, flush=True)
     return rec
 
 
@@ -595,6 +640,8 @@ def main():
     ap.add_argument("--fid-seeds", type=int, default=20)
     ap.add_argument("--no-small-runs", action="store_true",
                     help="skip the leg of the batched mixed workload's 12-14 qubit circuits")
+    ap.add_argument("--batch-extra", action="store_true",
+                    help="with --batch: also the autotuned tile widths and the (8, 16, 16) trees")
     ap.add_argument("--batch", action="store_true",
                     help="also run the 512-circuit mixed workload one run at a time and batched")
     ap.add_argument("--learned", action="store_true",
@@ -756,7 +803,7 @@ def main():
     if args.precision:
         line["precision_sweep"] = precision_sweep(T, W, torch, args.seed)
     if args.batch:
-        line["batched_mixed"] = batch_bench(T, W, torch, args.seed)
+        line["batched_mixed"] = batch_bench(T, W, torch, args.seed, extra=args.batch_extra)
     if args.learned:
         from paper_2203_13892_amd import learned as Lm
         model = Lm.ShapeModel.load(T)
