@@ -209,7 +209,7 @@ void emit_diag(std::string &s, const tqs_plan *p, const PassDesc &d, const OpDes
                 if (clr[a][i]) appendf(s, " + masked(clr%d_%u, lb.m[%d])", a, i, a);
             s += ";\n";
         }
-        appendf(s, "    run_phase<R, RB, %uu>(v, C, lam, cz, etab);\n", lm);
+        appendf(s, "    run_phase<R, RB, %uu>(v, C, lam, cz);\n", lm);
     }
     if (o.has_t) {
         uint32_t kf = 0, kl = 0;
@@ -345,12 +345,6 @@ void emit_frame_init(std::string &s) {
 void emit_ops(std::string &s, const tqs_plan *p, uint32_t pi) {
     const PassDesc &d = p->passes[pi];
     const bool c64 = p->prec == TQS_C64;
-    bool runs = false;
-    for (uint32_t oi = d.op_begin; oi < d.op_begin + d.op_count; oi++) runs = runs || p->ops[oi].kind == OP_DIAGRUN;
-    if (runs && c64)
-        s += "  __shared__ cplx<float> etab[256];\n  load_exp_table(etab, kExpTab, w.L);\n";
-    else if (runs)
-        s += "  const cplx<R> *etab = nullptr;\n";
     if (jit_table_entries(p, pi)) {
         // the node's own frame tables for this pass, if it has them
         appendf(s,
@@ -467,15 +461,6 @@ std::string jit_source(const tqs_plan *p) {
          "namespace tqs { namespace jit {\n"
          "template <typename T> using gptr = __attribute__((address_space(1))) T *;\n"
          "} }\n\n";
-    if (p->prec == TQS_C64) {
-        // e^{2 pi i k / 256}, k = 0..255, for the phase evaluation (expi_k)
-        s += "__device__ const tqs::cplx<float> kExpTab[256] = {";
-        for (int k = 0; k < 256; k++) {
-            const double a = 2.0 * 3.14159265358979323846 * k / 256.0;
-            appendf(s, "%s{%.9ef, %.9ef}", k ? ", " : "", std::cos(a), std::sin(a));
-        }
-        s += "};\n\n";
-    }
     for (uint32_t pi = 0; pi < (uint32_t)p->passes.size(); pi++)
         if (jit_pass_supported(p, pi)) emit_pass(s, p, pi);
     return s;

@@ -490,119 +490,40 @@ __device__ __forceinline__ LaneBits lane_bits(uint32_t L) {
 __device__ __forceinline__ uint32_t masked(uint32_t c, uint32_t m) { return c & m; }
 __device__ __forceinline__ uint64_t masked(uint64_t c, uint32_t m) { return c & (uint64_t)(int64_t)(int32_t)m; }
 
-// e^{2 pi i t} for fixed-point turns t.  Complex64: t's top eight bits
-// (rounded) pick e^{2 pi i k / 256} from a 256-entry table the pass holds in
-// LDS, and the remainder r (|r| <= 1/512 turn, |x| = 2 pi |r| <= pi / 256)
-// is x - x^3 / 6 and 1 - x^2 / 2 + x^4 / 24 (left out: below 3e-12), one
-// complex product with the table entry: about 14 vector instructions and
-// one LDS read against 25 for the full series.  Complex128: the full series
-// (expi_turns), no table.
-__device__ __forceinline__ cplx<float> expi_k(uint32_t t, const cplx<float> *tab) {
-    const uint32_t q = (t + (1u << 23)) >> 24;
-    const int32_t r = (int32_t)(t - (q << 24));
-    const float x = (float)r * 1.4629180792671596e-09f;  // 2 pi / 2^32
-    const float x2 = x * x;
-    const float sn = x * (1.0f - x2 * (1.0f / 6.0f));
-    const float cs = 1.0f - x2 * (0.5f - x2 * (1.0f / 24.0f));
-    return cmul(tab[q & 255u], cplx<float>{cs, sn});
-}
-__device__ __forceinline__ cplx<double> expi_k(uint64_t t, const cplx<double> *) { return expi_turns(t); }
-
-// A run's factors e^{2 pi i (C + sum_i lam_i x_i)} over the register bits
-// LM known when the pass is compiled (the forms of apply_run_phase, with
-// expi_k).  CZ (wave-uniform): C is zero in every lane, as it is for a run
-// of controlled phases with no X frame on their qubits; then a run with one
-// register bit multiplies only the registers with that bit set, and a run
-// with none is the identity.  (The full product multiplies the others by
-// e^0, exactly 1, so the results are the same.)  The factor e^{2 pi i C} is
-// taken in a branch of its own rather than beside the short form: two forms
-// of the whole product would hold more registers than the tile leaves free.
+// A run's factors e^{2 pi i (C + sum_i lam_i x_i)} (apply_run_phase) with
+// the register bits LM known when the pass is compiled.  CZ (wave-uniform):
+// C is zero in every lane, as it is for a run of controlled phases with no
+// X frame on their qubits; then a run with one register bit multiplies only
+// the registers with that bit set, and a run with none is the identity.
+// (The full product multiplies the others by e^0, exactly 1, so the results
+// are the same.)  The factor e^{2 pi i C} is taken in a branch of its own
+// rather than beside the short form: two forms of the whole product would
+// hold more registers than the tile leaves free.
 template <typename R, int RB, uint32_t LM>
 __device__ __forceinline__ void run_phase(cplx<R> (&v)[1 << RB], typename Turns<R>::T C,
-                                          const typename Turns<R>::T (&lam)[RB], bool cz, const cplx<R> *tab) {
-    constexpr int NJ = 1 << RB;
+                                          const typename Turns<R>::T (&lam)[RB], bool cz) {
     constexpr int NB = __builtin_popcount(LM);
     if constexpr (NB == 1) {
         constexpr int I = __builtin_ctz(LM);
-        const cplx<R> e = expi_k(lam[I], tab);
+        const cplx<R> e = expi_turns(lam[I]);
         cplx<R> w1 = e;
         if (!cz) {
-            const cplx<R> w0 = expi_k(C, tab);
+            const cplx<R> w0 = expi_turns(C);
             w1 = cmul(w0, e);
-            sfor<NJ>([&](auto Jc) __attribute__((always_inline)) {
+            sfor<(1 << RB)>([&](auto Jc) __attribute__((always_inline)) {
                 constexpr int j = decltype(Jc)::value;
                 if constexpr (((j >> I) & 1) == 0) v[j] = cmul(w0, v[j]);
             });
         }
-        sfor<NJ>([&](auto Jc) __attribute__((always_inline)) {
+        sfor<(1 << RB)>([&](auto Jc) __attribute__((always_inline)) {
             constexpr int j = decltype(Jc)::value;
             if constexpr (((j >> I) & 1) != 0) v[j] = cmul(w1, v[j]);
         });
     } else if constexpr (NB == 0) {
-        if (!cz) {
-            const cplx<R> w0 = expi_k(C, tab);
-            sfor<NJ>([&](auto Jc) __attribute__((always_inline)) {
-                constexpr int j = decltype(Jc)::value;
-                v[j] = cmul(w0, v[j]);
-            });
-        }
-    } else if constexpr (NB == 2) {
-        // e^{2 pi i C} on every register, then e^{2 pi i lam_i} on those
-        // with bit i set
-        if (!cz) {
-            const cplx<R> w0 = expi_k(C, tab);
-            sfor<NJ>([&](auto Jc) __attribute__((always_inline)) {
-                constexpr int j = decltype(Jc)::value;
-                v[j] = cmul(w0, v[j]);
-            });
-        }
-        sfor<RB>([&](auto Ic) __attribute__((always_inline)) {
-            constexpr int i = decltype(Ic)::value;
-            if constexpr (((LM >> i) & 1u) != 0) {
-                const cplx<R> e = expi_k(lam[i], tab);
-                sfor<NJ>([&](auto Jc) __attribute__((always_inline)) {
-                    constexpr int j = decltype(Jc)::value;
-                    if constexpr (((j >> i) & 1) != 0) v[j] = cmul(e, v[j]);
-                });
-            }
-        });
+        if (!cz) apply_run_phase<R, RB>(v, C, lam, LM);
     } else {
-        // subset products over the low and high register bits
-        constexpr int LO = RB < 3 ? RB : 3;
-        constexpr int HI = RB - LO;
-        cplx<R> wlo[1 << LO], whi[1 << HI];
-        wlo[0] = expi_k(C, tab);
-        sfor<LO>([&](auto Ic) __attribute__((always_inline)) {
-            constexpr int i = decltype(Ic)::value;
-            const cplx<R> e = (((LM >> i) & 1u) != 0) ? expi_k(lam[i], tab) : cplx<R>{R(1), R(0)};
-            sfor<(1 << i)>([&](auto Sc) __attribute__((always_inline)) {
-                constexpr int s2 = decltype(Sc)::value;
-                wlo[s2 | (1 << i)] = cmul(wlo[s2], e);
-            });
-        });
-        whi[0] = cplx<R>{R(1), R(0)};
-        sfor<HI>([&](auto Ic) __attribute__((always_inline)) {
-            constexpr int i = decltype(Ic)::value;
-            const cplx<R> e = (((LM >> (LO + i)) & 1u) != 0) ? expi_k(lam[LO + i], tab) : cplx<R>{R(1), R(0)};
-            sfor<(1 << i)>([&](auto Sc) __attribute__((always_inline)) {
-                constexpr int s2 = decltype(Sc)::value;
-                whi[s2 | (1 << i)] = cmul(whi[s2], e);
-            });
-        });
-        sfor<NJ>([&](auto Jc) __attribute__((always_inline)) {
-            constexpr int j = decltype(Jc)::value;
-            const cplx<R> w = HI ? cmul(wlo[j & ((1 << LO) - 1)], whi[j >> LO]) : wlo[j & ((1 << LO) - 1)];
-            v[j] = cmul(w, v[j]);
-        });
+        apply_run_phase<R, RB>(v, C, lam, LM);
     }
-}
-
-// The 256-entry phase table of expi_k, loaded into LDS at the start of a
-// complex64 pass (four entries per lane, from the module's copy).
-__device__ __forceinline__ void load_exp_table(cplx<float> *tab, const cplx<float> *src, uint32_t L) {
-#pragma unroll
-    for (uint32_t i = 0; i < 4; i++) tab[L + 64 * i] = src[L + 64 * i];
-    __syncthreads();
 }
 
 // The run's register-only gates: table T (2^RB entries, index j ^ fr);
