@@ -337,7 +337,12 @@ tqs_status tqs_run_capture(tqs_plan *p, const tqs_noise *nz, void *d_workspace,
  * stream (or NULL, the null stream) must belong to the current device.  All
  * calls on one GPU share its array and it keeps the last call's contents:
  * calls that overlap on one GPU (other threads, other streams) race, so
- * the caller orders them.  Outcomes as tqs_run; no statistics. */
+ * the caller orders them.  Outcomes as tqs_run; no statistics.  No HIP
+ * allocation of any kind: the metadata goes up from pageable host memory
+ * and the outcomes come straight down (no pinned staging), and the plan's
+ * specialised kernels are used only when an earlier run already loaded them
+ * on this device (else the generic kernels take every state; same
+ * outcomes up to rounding). */
 tqs_status tqs_run_noalloc(tqs_plan *p, const tqs_noise *nz, void *stream, uint64_t *outcomes);
 
 /* --------------------------------------------------------------- batches

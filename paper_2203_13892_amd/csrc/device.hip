@@ -985,11 +985,13 @@ struct FrameTables {
 // Routes of every (task, pass of its level), appending index lists and the
 // frame-table directories to sched.
 static void route_passes(const tqs_plan *p, const HostMeta &hm, const std::vector<Task> &tasks,
-                         std::vector<uint32_t> *sched, std::vector<std::vector<Route>> *routes, FrameTables *ft) {
+                         std::vector<uint32_t> *sched, std::vector<std::vector<Route>> *routes, FrameTables *ft,
+                         bool jit = true) {
     routes->assign(tasks.size(), {});
+    for (size_t ti = 0; ti < tasks.size(); ti++) (*routes)[ti].assign(p->levels[tasks[ti].level].pass_count, Route());
     ft->tab.clear();
     ft->ct_off.assign(p->n_nodes, 0xFFFFFFFFu);
-    if (p->tune.jit != 1) return;
+    if (p->tune.jit != 1 || !jit) return;
     std::vector<std::vector<JitRun>> runs;
     std::vector<std::vector<JitBlock>> blks;
     jit_runs(p, &runs, &blks);
@@ -1000,7 +1002,6 @@ static void route_passes(const tqs_plan *p, const HostMeta &hm, const std::vecto
     for (size_t ti = 0; ti < tasks.size(); ti++) {
         const Task &t = tasks[ti];
         const tqs::Level &lv = p->levels[t.level];
-        (*routes)[ti].assign(lv.pass_count, Route());
         for (uint32_t k = 0; k < lv.pass_count; k++) {
             const uint32_t pi = lv.pass_begin + k;
             Route &r = (*routes)[ti][k];
@@ -1343,6 +1344,7 @@ struct tqs_pending {
     uint64_t jit_launches = 0, jit_states = 0, bytes_jit = 0, events = 0;
     hipEvent_t e_begin = nullptr, e_end = nullptr;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> jit_ev, pass_ev, samp_ev;
+    std::vector<unsigned char> meta;  // the uploaded metadata of a run without a staging slot
 };
 
 namespace tqs {
@@ -1404,10 +1406,15 @@ struct SlotGuard {
 // slot's pinned buffer), the upload, every pass and sampling launch, and
 // the download into the slot's pinned buffer.  Returns without waiting
 // (capture requests aside, which copy leaf states out as they come).
+// noalloc: no host or device allocation through HIP (tqs_run_noalloc): the
+// metadata goes up from pageable memory and the outcomes come straight down
+// (both copies then wait for the stream), no staging slot, and the plan's
+// specialised kernels only if they are already loaded on this device (else
+// the generic kernels take every state).
 template <typename R>
 static tqs_status run_start_t(tqs_plan *p, const tqs_noise *nz, unsigned char *ws, uint64_t ws_bytes,
                               hipStream_t s, uint64_t first, uint64_t last, uint64_t *outcomes,
-                              bool stats, const Capture &cap, tqs_pending *pd) {
+                              bool stats, const Capture &cap, tqs_pending *pd, bool noalloc) {
     const auto t0 = std::chrono::steady_clock::now();
     tqs_status st = check_noise(p, nz);
     if (st) return st;
@@ -1431,14 +1438,19 @@ static tqs_status run_start_t(tqs_plan *p, const tqs_noise *nz, unsigned char *w
     std::vector<uint32_t> sched;
     Layout Ly0 = make_layout(p, nz->ev_gate.size(), n_out, 0);
     build_schedule(p, first, last, &tasks, &sched, Ly0.slot_base, p->tune.no_merge ? nullptr : &hm);
-    if (p->tune.jit == 1) {
+    bool use_jit = p->tune.jit == 1;
+    if (use_jit && noalloc) {
+        int dev = -1;
+        use_jit = hipGetDevice(&dev) == hipSuccess && p->jit_module && p->jit_device == dev;
+    }
+    if (use_jit) {
         // the plan's specialised kernels, compiled on its first run
         const tqs_status js = jit_prepare(p);
         if (js) return js;
     }
     std::vector<std::vector<Route>> routes;
     FrameTables ftab;
-    route_passes(p, hm, tasks, &sched, &routes, &ftab);
+    route_passes(p, hm, tasks, &sched, &routes, &ftab, use_jit);
     Layout Ly = make_layout(p, nz->ev_gate.size(), n_out, sched.size(), 0, ~0ull, ftab.tab.size());
     if (ws_bytes < Ly.total)
         return fail(TQS_E_WORKSPACE, "workspace has %llu bytes, the run needs %llu",
@@ -1448,11 +1460,18 @@ static tqs_status run_start_t(tqs_plan *p, const tqs_noise *nz, unsigned char *w
     // slot's pinned buffer
     const uint64_t meta_bytes = Ly.off_sums - Ly.off_meta;
     SlotGuard sg{p};
-    st = acquire_slot(p, meta_bytes, n_out * 8, &sg.k);
-    if (st) return st;
-    tqs_plan::RunSlot &slot = p->slots[sg.k];
-    unsigned char *hb = static_cast<unsigned char *>(slot.meta);
-    std::memset(hb, 0, meta_bytes);
+    std::vector<void *> direct_events;  // (event pool of a run without a slot)
+    unsigned char *hb = nullptr;
+    if (noalloc) {
+        pd->meta.assign(meta_bytes, 0);
+        hb = pd->meta.data();
+    } else {
+        st = acquire_slot(p, meta_bytes, n_out * 8, &sg.k);
+        if (st) return st;
+        hb = static_cast<unsigned char *>(p->slots[sg.k].meta);
+        std::memset(hb, 0, meta_bytes);
+    }
+    std::vector<void *> &ev_pool = noalloc ? direct_events : p->slots[sg.k].events;
     pack_meta<R>(p, nz, hm, sched, Ly, hb, Ly.off_meta, &ftab);
 
     DrainOnError drain(s);
@@ -1460,7 +1479,7 @@ static tqs_status run_start_t(tqs_plan *p, const tqs_noise *nz, unsigned char *w
     size_t ev_i = 0;
     hipEvent_t e_begin = nullptr, e_end = nullptr;
     if (stats) {
-        e_begin = pool_event(slot.events, ev_i++);
+        e_begin = pool_event(ev_pool, ev_i++);
         if (!e_begin) return fail(TQS_E_HIP, "hipEventCreate failed");
         HIP_TRY(hipEventRecord(e_begin, s), "hipEventRecord");
     }
@@ -1488,8 +1507,8 @@ static tqs_status run_start_t(tqs_plan *p, const tqs_noise *nz, unsigned char *w
         const MarkerRange range(mark);
         hipEvent_t ea = nullptr, eb = nullptr, ec = nullptr;
         if (stats) {
-            ea = pool_event(slot.events, ev_i++);
-            eb = pool_event(slot.events, ev_i++);
+            ea = pool_event(ev_pool, ev_i++);
+            eb = pool_event(ev_pool, ev_i++);
             if (!ea || !eb) return fail(TQS_E_HIP, "hipEventCreate failed");
             HIP_TRY(hipEventRecord(ea, s), "hipEventRecord");
         }
@@ -1524,8 +1543,8 @@ static tqs_status run_start_t(tqs_plan *p, const tqs_noise *nz, unsigned char *w
             hipEvent_t ej0 = nullptr, ej1 = nullptr;
             if (stats) {
                 // the specialised launch of this pass, timed on its own
-                ej0 = pool_event(slot.events, ev_i++);
-                ej1 = pool_event(slot.events, ev_i++);
+                ej0 = pool_event(ev_pool, ev_i++);
+                ej1 = pool_event(ev_pool, ev_i++);
                 if (!ej0 || !ej1) return fail(TQS_E_HIP, "hipEventCreate failed");
             }
             if (fault.kind == FaultSpec::LAUNCH && pass_iter == fault.at)
@@ -1563,7 +1582,7 @@ static tqs_status run_start_t(tqs_plan *p, const tqs_noise *nz, unsigned char *w
             bytes_sample += (uint64_t)t.ccount * (p->samp_tiled ? (8ull << (p->samp_nfree + p->samp_kv)) : state_bytes) +
                             (uint64_t)t.count * (Ly.amp_bytes << b);
             if (stats) {
-                ec = pool_event(slot.events, ev_i++);
+                ec = pool_event(ev_pool, ev_i++);
                 if (!ec) return fail(TQS_E_HIP, "hipEventCreate failed");
                 HIP_TRY(hipEventRecord(ec, s), "hipEventRecord");
                 samp_ev.push_back({eb, ec});
@@ -1598,9 +1617,11 @@ static tqs_status run_start_t(tqs_plan *p, const tqs_noise *nz, unsigned char *w
         }
         HIP_TRY(hipGetLastError(), "kernel launch");
     }
-    HIP_TRY(hipMemcpyAsync(slot.out, ws + Ly.off_out, n_out * 8, hipMemcpyDeviceToHost, s), "outcome download");
+    HIP_TRY(hipMemcpyAsync(noalloc ? (void *)outcomes : p->slots[sg.k].out, ws + Ly.off_out, n_out * 8,
+                           hipMemcpyDeviceToHost, s),
+            "outcome download");
     if (stats) {
-        e_end = pool_event(slot.events, ev_i++);
+        e_end = pool_event(ev_pool, ev_i++);
         if (!e_end) return fail(TQS_E_HIP, "hipEventCreate failed");
         HIP_TRY(hipEventRecord(e_end, s), "hipEventRecord");
     }
@@ -1638,7 +1659,7 @@ static tqs_status run_finish(tqs_pending *pd, tqs_run_stats *stats) {
     SlotGuard sg{pd->p};
     sg.k = pd->slot;
     HIP_TRY(hipStreamSynchronize(pd->s), "stream synchronize");
-    std::memcpy(pd->outcomes, pd->p->slots[pd->slot].out, pd->n_out * 8);
+    if (pd->slot >= 0) std::memcpy(pd->outcomes, pd->p->slots[pd->slot].out, pd->n_out * 8);
     if (stats) {
         std::memset(stats, 0, sizeof *stats);
         if (pd->stats) {
@@ -1675,20 +1696,23 @@ static tqs_status run_finish(tqs_pending *pd, tqs_run_stats *stats) {
 
 static tqs_status run_start_any(tqs_plan *p, const tqs_noise *nz, void *ws, uint64_t ws_bytes, void *stream,
                                 uint64_t first, uint64_t last, uint64_t *outcomes, bool stats, const Capture &cap,
-                                tqs_pending *pd) {
+                                tqs_pending *pd, bool noalloc = false) {
     if (!p) return fail(TQS_E_ARG, "plan is NULL");
     hipStream_t s = (hipStream_t)stream;
     if (p->prec == TQS_C64)
-        return run_start_t<float>(p, nz, (unsigned char *)ws, ws_bytes, s, first, last, outcomes, stats, cap, pd);
-    return run_start_t<double>(p, nz, (unsigned char *)ws, ws_bytes, s, first, last, outcomes, stats, cap, pd);
+        return run_start_t<float>(p, nz, (unsigned char *)ws, ws_bytes, s, first, last, outcomes, stats, cap, pd,
+                                  noalloc);
+    return run_start_t<double>(p, nz, (unsigned char *)ws, ws_bytes, s, first, last, outcomes, stats, cap, pd,
+                               noalloc);
 }
 
 // A whole run: started, then finished at once.
 static tqs_status run_any(tqs_plan *p, const tqs_noise *nz, void *ws, uint64_t ws_bytes, void *stream,
                           uint64_t first, uint64_t last, uint64_t *outcomes, tqs_run_stats *stats,
-                          const Capture &cap) {
+                          const Capture &cap, bool noalloc = false) {
     tqs_pending pd;
-    const tqs_status st = run_start_any(p, nz, ws, ws_bytes, stream, first, last, outcomes, stats != nullptr, cap, &pd);
+    const tqs_status st =
+        run_start_any(p, nz, ws, ws_bytes, stream, first, last, outcomes, stats != nullptr, cap, &pd, noalloc);
     if (st) return st;
     return run_finish(&pd, stats);
 }
@@ -2072,7 +2096,7 @@ tqs_status tqs_run_noalloc(tqs_plan *p, const tqs_noise *nz, void *stream, uint6
     void *ws = nullptr;
     st = scratch_address(cur, &ws);
     if (st) return st;
-    return run_any(p, nz, ws, kStaticScratchBytes, stream, 0, p->arity[0], outcomes, nullptr, Capture());
+    return run_any(p, nz, ws, kStaticScratchBytes, stream, 0, p->arity[0], outcomes, nullptr, Capture(), true);
     TQS_GUARD_END
 }
 

@@ -168,7 +168,9 @@ int main(int argc, char **argv) {
             CHECK(ftab.tab.size() <= table_bound(p));
             for (size_t ti = 0; ti < tasks.size(); ti++) {
                 const Task &t = tasks[ti];
-                CHECK(routes[ti].size() == (p->tune.jit == 1 ? p->levels[t.level].pass_count : 0));
+                CHECK(routes[ti].size() == p->levels[t.level].pass_count);
+                if (p->tune.jit != 1)
+                    for (const Route &r : routes[ti]) CHECK(r.n_jit == 0 && r.perm == Route::kNoPerm);
                 for (const Route &r : routes[ti]) {
                     CHECK(r.n_jit <= t.ccount);
                     if (r.perm == Route::kNoPerm) continue;

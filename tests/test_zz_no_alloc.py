@@ -52,3 +52,21 @@ def test_noalloc_refuses_runs_beyond_the_scratch(T):
     with pytest.raises(T.TqsError) as e:
         T.run_noalloc(plan, nz)
     assert e.value.status == -3 and "static scratch" in str(e.value)
+
+
+def test_noalloc_with_specialised_kernels(T):
+    # a plan with specialised kernels: before any run has loaded them the
+    # call takes the generic kernels (loading a module allocates), so it
+    # equals the plan run with the generic kernels only; once a run has
+    # loaded them it takes them, and equals that run
+    wc = W.qft(16).with_depolarizing(1e-2, 3e-2)
+    G = len(wc)
+    tree = ([4, 4, 8], [0, G // 3, 2 * G // 3, G])
+    c = T.Circuit.from_workload(wc)
+    nz = T.Noise.sample(c, tree, 3)
+    plan = T.Plan(c, tree, "c64", {"jit": 1, "chunk_states": 16})
+    assert plan.workspace_bytes(nz) <= 64 << 20
+    generic = T.run(T.Plan(c, tree, "c64", {"jit": 2, "chunk_states": 16}), nz)
+    assert np.array_equal(T.run_noalloc(plan, nz), generic)
+    specialised = T.run(plan, nz)
+    assert np.array_equal(T.run_noalloc(plan, nz), specialised)
