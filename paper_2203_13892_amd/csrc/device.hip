@@ -12,6 +12,7 @@
 #include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
+#include <atomic>
 #include <array>
 #include <chrono>
 #include <cmath>
@@ -931,16 +932,18 @@ constexpr int kMaxDevices = 64;
 
 // LDS bytes one workgroup may hold on the current device (cached per device).
 static uint32_t device_lds_limit() {
-    static int cached[kMaxDevices] = {0};
+    static std::atomic<int> cached[kMaxDevices];  // 0: not asked yet, -1: unknown
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return 0;
-    if (!cached[dev]) {
+    int c = cached[dev].load(std::memory_order_relaxed);
+    if (!c) {
         int v = 0;
         if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
             v = -1;
-        cached[dev] = v;
+        cached[dev].store(v, std::memory_order_relaxed);
+        c = v;
     }
-    return cached[dev] > 0 ? (uint32_t)cached[dev] : 0u;
+    return c > 0 ? (uint32_t)c : 0u;
 }
 
 // Waves per workgroup and LDS bytes of the level kernel for level l of the
