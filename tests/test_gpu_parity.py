@@ -74,13 +74,21 @@ def event_arrays(wc, tree, rng, rate=0.3):
             rng.random(leaves))
 
 
+# Hadamard and its sign variants: every entry +-1/sqrt(2) (the specialised
+# kernels' sign-only butterflies)
+_BUTTERFLIES = [np.array(m, complex) / math.sqrt(2.0) for m in
+                ([[1, 1], [1, -1]], [[1, -1], [1, 1]], [[-1, 1], [1, 1]], [[1, 1], [-1, 1]])]
+
+
 def mixed_gates(n, count, rng):
-    """Every op class: dense 1q, diagonal 1q/2q, controlled, dense 2q, swap,
-    on low / high / mixed qubit positions."""
+    """Every op class: dense 1q, Hadamard-like 1q, diagonal 1q/2q,
+    controlled, dense 2q, swap, on low / high / mixed qubit positions."""
     c = W.Circuit(n)
     for i in range(count):
-        kind = i % 7
-        if kind == 0:
+        kind = i % 8
+        if kind == 7:
+            c.add((int(rng.integers(n)),), _BUTTERFLIES[int(rng.integers(4))])
+        elif kind == 0:
             c.add((int(rng.integers(n)),), W.haar_unitary(2, rng))
         elif kind == 1:
             c.add((int(rng.integers(n)),), W.phase(float(rng.uniform(0, 6))))
