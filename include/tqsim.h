@@ -93,7 +93,7 @@ typedef struct {
                                   default 10) */
     uint32_t max_ops_per_pass; /* gates applied per HBM pass (default 1024) */
     uint32_t chunk_states;     /* live states per tree level (default: as many as fill
-                                  4 GiB, between 1 and 512) */
+                                  8 GiB, between 1 and 1024) */
     uint32_t sample_block_log; /* log2 amplitudes per sampling block (default 12) */
     uint32_t pass_cost;        /* estimated lane instructions per amplitude allowed in one
                                   pass before a new pass starts (default 480) */
