@@ -784,11 +784,18 @@ def main():
         cb = T.Circuit.from_workload(bw)
         line["brickwall"] = {"workload": "brickwall20 d20 seed 1, depolarizing(1e-3,1e-2) 16384 shots",
                              "gates": Gb, "forms": {}}
-        for name, tree in (("pershot", ([shots], [0, Gb])), ("tree", ([16, 32, 32], equal_cuts(Gb, 3))),
-                           ("tree4b", ([8, 8, 16, 16], equal_cuts(Gb, 4)))):
-            sps, ms, agg, _ = time_form(T, torch, cb, tree, args.seed, args.steps, args.warmup)
+        # (tree4b_level_exchange: lane exchanges at the end of each level's
+        # last pass, tuning level_exchange = 1)
+        for name, tree, tun in (("pershot", ([shots], [0, Gb]), None),
+                                ("tree", ([16, 32, 32], equal_cuts(Gb, 3)), None),
+                                ("tree4b", ([8, 8, 16, 16], equal_cuts(Gb, 4)), None),
+                                ("tree4b_level_exchange", ([8, 8, 16, 16], equal_cuts(Gb, 4)),
+                                 {"level_exchange": 1})):
+            sps, ms, agg, _ = time_form(T, torch, cb, tree, args.seed, args.steps, args.warmup, tun)
+            pl = T.Plan(cb, tree, "c64", tun)
             line["brickwall"]["forms"][name] = {
                 "shots_per_s": sps, "ms_per_step": ms, "shape": tree[0],
+                "passes_per_level": [pl.info(l)["passes_level"] for l in range(len(tree[0]))],
                 "pass_GBps": agg["bytes_passes"] / (agg["ms_passes"] * 1e-3) / 1e9}
             print("# brickwall %s: %.1f shots/s, %.2f ms/step" % (name, sps, ms), file=sys.stderr, flush=True)
     if not args.no_fidelity:

@@ -155,6 +155,8 @@ extern "C" tqs_status tqs_plan_create(const tqs_circuit *c, const tqs_tree *tree
     if (!tu.mfma_min_ops) tu.mfma_min_ops = 6;
     if (tu.lds_levels > 2) return fail(TQS_E_ARG, "lds_levels must be 0 (default), 1 (on) or 2 (off)");
     if (!tu.lds_levels) tu.lds_levels = 2;
+    if (tu.level_exchange > 2) return fail(TQS_E_ARG, "level_exchange must be 0 (default), 1 (on) or 2 (off)");
+    if (!tu.level_exchange) tu.level_exchange = 2;
     const uint32_t tmax = prec == TQS_C64 ? 12 : 11;
     if (tu.tile_qubits < 10 || tu.tile_qubits > tmax)
         return fail(TQS_E_ARG, "tile_qubits must be in 10..%u at this precision", tmax);
@@ -476,11 +478,30 @@ extern "C" tqs_status tqs_plan_create(const tqs_circuit *c, const tqs_tree *tree
                 p->gate_q1[gi] = pg.pq[1];
             }
             rem.swap(left);
-            if (!rem.empty() && nl == kLaneBits && n > nl) {
+            // the gates the exchange below prepares for: the level's remaining
+            // gates, or (tuning level_exchange), after its last pass, the next
+            // level's when the qubits they change would not fit the lanes plus
+            // the register slots of one tile.  Tail events of this level then
+            // precede an op, so fewer of its nodes may share a state.
+            std::vector<uint32_t> ahead;
+            if (!rem.empty()) {
+                ahead = rem;
+            } else if (tu.level_exchange == 1 && l + 1 < L) {
+                uint32_t chp = 0;
+                for (uint32_t gi = cut[l + 1]; gi < cut[l + 2]; gi++) {
+                    if (swp[gi]) continue;
+                    const uint32_t chl = changed_mask(c->gates[gi], cls[gi], ctl[gi]);
+                    for (uint32_t q = 0; q < n; q++)
+                        if ((chl >> q) & 1u) chp |= 1u << lay[q];
+                }
+                if ((uint32_t)__builtin_popcount(chp & ~lane_mask) > nr_max)
+                    for (uint32_t gi = cut[l + 1]; gi < cut[l + 2]; gi++) ahead.push_back(gi);
+            }
+            if (!ahead.empty() && nl == kLaneBits && n > nl) {
                 // the logical qubits the next gates change, in order of need
                 std::vector<uint32_t> need;
                 uint32_t needm = 0;
-                for (uint32_t gi : rem) {
+                for (uint32_t gi : ahead) {
                     const Gate &g = c->gates[gi];
                     if (swp[gi]) continue;
                     const uint32_t chl = changed_mask(g, cls[gi], ctl[gi]);

@@ -30,7 +30,8 @@ class TqsTree(C.Structure):
 class TqsTuning(C.Structure):
     _fields_ = [("tile_qubits", u32), ("max_ops_per_pass", u32), ("chunk_states", u32),
                 ("sample_block_log", u32), ("pass_cost", u32), ("no_merge", u32),
-                ("separate_sampling", u32), ("jit", u32), ("mfma_min_ops", u32), ("lds_levels", u32)]
+                ("separate_sampling", u32), ("jit", u32), ("mfma_min_ops", u32), ("lds_levels", u32),
+                ("level_exchange", u32)]
 
 
 class TqsRunStats(C.Structure):

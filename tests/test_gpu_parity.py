@@ -1009,3 +1009,50 @@ def test_levels_in_lds(T, n, tile):
     check_outcomes(lds, oout, ost, arr[3], DELTA["c64"])
     print("launches pass by pass", st_b["pass_launches"], "with levels in LDS", st_l["pass_launches"])
     assert st_l["pass_launches"] < st_b["pass_launches"]
+
+
+@pytest.mark.parametrize("family", ["qft", "bw"])
+def test_level_exchange_20q(T, family):
+    # tuning level_exchange = 1: lane exchanges at the end of a level's last
+    # pass (QFT-20: level 1 in one pass instead of two; brick-wall: another
+    # layout at every level) against the oracle, on the first two sibling
+    # groups of subtree 0 and 64 random leaves
+    wc, tree = _c2_case(family)
+    c = T.Circuit.from_workload(wc)
+    on = T.Plan(c, tree, "c64", {"level_exchange": 1})
+    off = T.Plan(c, tree, "c64")
+    p_on = [on.info(l)["passes_level"] for l in range(3)]
+    p_off = [off.info(l)["passes_level"] for l in range(3)]
+    assert on.describe() != off.describe()
+    if family == "qft":
+        assert p_on == [1, 1, 1] and p_off == [1, 2, 1]
+    leaves = np.concatenate([np.arange(64), np.sort(np.random.default_rng(6).choice(
+        np.arange(1024, 16384), 64, replace=False))])
+    out, amps, oout, ost, onz = run_both(T, wc, tree, 0, "c64", leaves, tuning={"level_exchange": 1})
+    err, rel = float(np.max(np.abs(amps - ost))), rel_l2(amps, ost)
+    nb = check_outcomes(out[leaves], oout, ost, onz.leaf_u[leaves], DELTA["c64"])
+    print(family, "passes per level", p_on, "(off:", p_off, ")", "max-abs %.3g rel-l2 %.3g boundary leaves %d"
+          % (err, rel, nb))
+    assert err < 1e-5
+    assert rel < rel_bound("c64", len(wc))
+
+
+@pytest.mark.parametrize("prec,jit", [("c64", 1), ("c64", 2), ("c128", 2)])
+def test_level_exchange_mixed_events(T, prec, jit):
+    # level-end exchanges on 13 qubits in 10-qubit tiles, every op class,
+    # events in every level (also on the gates just before an exchange),
+    # ragged chunks, in the specialised and the generic kernels
+    rng = np.random.default_rng(77)
+    n = 13
+    wc = mixed_gates(n, 60, rng)
+    tree = ([3, 4, 6], [0, 14, 35, 60])
+    arr = event_arrays(wc, tree, rng, rate=0.08)
+    leaves = np.arange(72)
+    tun = {"chunk_states": 5, "tile_qubits": 10, "jit": jit, "level_exchange": 1}
+    c = T.Circuit.from_workload(wc)
+    assert T.Plan(c, tree, prec, tun).describe() != T.Plan(c, tree, prec, dict(tun, level_exchange=2)).describe()
+    out, amps, oout, ost, _ = run_both(T, wc, tree, 0, prec, leaves, tuning=tun, noise_arrays=arr)
+    err = float(np.max(np.abs(amps - ost)))
+    print(prec, "jit", jit, "max-abs %.3g" % err)
+    assert err < TOL[prec]
+    check_outcomes(out, oout, ost, arr[3], DELTA[prec])

@@ -285,6 +285,13 @@ def _random_gates(n, count, rng):
     (10, ([4, 2], None), {"tile_qubits": 10}),
     (10, ([3], None), {"pass_cost": 60}),
     (11, ([2, 3], None), None),
+    # more qubits than one tile holds: exchanges at a level's end prepare
+    # the next level's qubits
+    (12, ([2, 3], None), {"tile_qubits": 10, "level_exchange": 1}),
+    (12, ([3, 2], None), {"level_exchange": 1}),
+    (13, ([2, 2, 2], None), {"tile_qubits": 10, "level_exchange": 1}),
+    (14, ([2, 2], None), {"tile_qubits": 10, "level_exchange": 1}),
+    (14, ([2, 2], None), {"tile_qubits": 10}),
 ])
 def test_planner_schedule_reproduces_trajectories(n, tree, tuning):
     # the plan's ops in its order (gates reordered, swaps relabelled, lane
@@ -309,6 +316,43 @@ def test_planner_schedule_reproduces_trajectories(n, tree, tuning):
             for e in range(int(nz.node_off[node]), int(nz.node_off[node + 1])):
                 events.append((int(nz.ev_gate[e]), int(nz.ev_code[e])))
         assert np.max(np.abs(_emulate(text, events) - st[lam])) < 1e-12
+
+
+def test_level_end_exchange_qft20():
+    # QFT-20 cut in three levels: level 1 changes six qubits outside the lanes
+    # (one more than the register slots).  With level_exchange on, level 0's
+    # pass ends with a lane exchange and every level is one pass; level 1
+    # changes no more than the tile holds afterwards, so its pass ends with no
+    # exchange.  Off (the default), level 1 takes two passes and no pass
+    # holds an exchange.
+    wc = W.qft(20).with_depolarizing(1e-3, 1e-2)
+    G = len(wc)
+    cut = [0, 74, 147, G]
+    c = T.Circuit.from_workload(wc)
+    swap = np.eye(4)[[0, 2, 1, 3]]
+
+    def is_exchange(op):
+        kind, _, gl = op
+        return kind == "dense" and len(gl[0][0]) == 2 and np.array_equal(gl[0][1], swap)
+
+    off = T.Plan(c, ([16, 32, 32], cut), "c64").describe()
+    assert [ln for ln in off.splitlines() if ln.startswith("level")] == ["level 0 0 1", "level 1 1 2",
+                                                                         "level 2 3 1"]
+    assert not any(is_exchange(op) for ops in _parse_plan(off)[3] for op in ops)
+    text = T.Plan(c, ([16, 32, 32], cut), "c64", {"level_exchange": 1}).describe()
+    lines = text.splitlines()
+    assert [ln for ln in lines if ln.startswith("level")] == ["level 0 0 1", "level 1 1 1", "level 2 2 1"]
+    n, lay, gates, passes = _parse_plan(text)
+
+    # a lane position and a register position
+    assert is_exchange(passes[0][-1])
+    qs = passes[0][-1][2][0][0]
+    assert min(qs) < 6 <= max(qs)
+    assert not any(is_exchange(op) for op in passes[1] + passes[2])
+    # the final layout is still a permutation of the 20 positions
+    assert sorted(lay) == list(range(20))
+    with pytest.raises(T.TqsError, match="level_exchange"):
+        T.Plan(c, ([16, 32, 32], cut), "c64", {"level_exchange": 3})
 
 
 def test_one_hip_runtime_per_process():
