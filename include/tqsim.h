@@ -131,11 +131,12 @@ typedef struct {
                                   register slots of one tile, the last pass of a level ends
                                   with lane exchanges that put them in reach, so the next
                                   level may need fewer passes; the later levels' layout
-                                  changes too, which may cost more than it saves (QFT-20 in
-                                  the (16, 32, 32) tree: level 1 in one pass instead of two,
-                                  leaf pass 9% slower; 20-qubit brick-wall in the
-                                  (8, 8, 16, 16) tree: 17 passes instead of 24).  Same
-                                  results either way */
+                                  changes too, which may cost as much as it saves, or more
+                                  (QFT-20 in the (16, 32, 32) tree: level 1 in one pass
+                                  instead of two, the same speed overall; 20-qubit
+                                  brick-wall in the (8, 8, 16, 16) tree: 17 passes instead
+                                  of 24, 9% faster; in the (16, 32, 32) tree 3% slower).
+                                  Same results either way */
 } tqs_tuning;
 
 /* Timing and traffic of one run. */

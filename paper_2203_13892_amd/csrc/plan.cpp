@@ -523,6 +523,21 @@ extern "C" tqs_status tqs_plan_create(const tqs_circuit *c, const tqs_tree *tree
                     if (lay[q] >= nl && ((pend_regs >> lay[q]) & 1u)) in.push_back(q);
                 for (uint32_t pl = 0; pl < nl; pl++)
                     if (!((needm >> inv[pl]) & 1u)) out.push_back(inv[pl]);
+                if (rem.empty() && l + 2 <= L) {
+                    // at a level's end, the lanes given up go in the order in
+                    // which the levels after the next first change their
+                    // qubits, earliest first (on QFT-20 and brick-wall trees
+                    // faster than lane order: the leaf level of QFT-20 keeps
+                    // its lane-controlled phase runs free of register terms)
+                    std::vector<uint32_t> first(n, 0xFFFFFFFFu);
+                    for (uint32_t gi = cut[l + 2]; gi < cut[L]; gi++) {
+                        if (swp[gi]) continue;
+                        const uint32_t chl = changed_mask(c->gates[gi], cls[gi], ctl[gi]);
+                        for (uint32_t q = 0; q < n; q++)
+                            if (((chl >> q) & 1u) && first[q] == 0xFFFFFFFFu) first[q] = gi;
+                    }
+                    std::stable_sort(out.begin(), out.end(), [&](uint32_t a, uint32_t b) { return first[a] < first[b]; });
+                }
                 const size_t k = std::min(in.size(), out.size());
                 for (size_t i = 0; i < k && pend.size() < 60000; i++) {
                     const uint32_t pr = lay[in[i]], pl = lay[out[i]];
