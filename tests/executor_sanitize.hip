@@ -127,6 +127,7 @@ int main(int argc, char **argv) {
         if (g() % 2) tu.chunk_states = 1 + g() % 9;
         if (g() % 2) tu.sample_block_log = 8 + g() % 5;
         tu.separate_sampling = g() % 2;
+        tu.level_exchange = g() % 3;
         // specialised kernels: routing, frame tables and code generation
         // (host side; nothing is compiled or loaded)
         tu.jit = 1 + g() % 2;

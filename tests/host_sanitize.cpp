@@ -91,6 +91,7 @@ int main(int argc, char **argv) {
         if (g() % 2) tu.pass_cost = 50 + g() % 1000;
         tu.no_merge = g() % 2;
         tu.separate_sampling = g() % 2;
+        tu.level_exchange = g() % 3;
         tqs_plan *p = nullptr;
         const tqs_precision prec = g() % 2 ? TQS_C64 : TQS_C128;
         if (tqs_plan_create(c, &tree, prec, &tu, &p) == TQS_OK) {
