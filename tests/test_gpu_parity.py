@@ -836,9 +836,10 @@ def test_c2_20q_tree_sampled_leaves_c128(T):
 
 @pytest.mark.parametrize("seed", range(32))
 def test_random_configurations(T, seed):
-    # random circuits (every op class, swap networks), trees, tunings,
-    # insertion lists with repeated histories, and read-out flips: every
-    # leaf's amplitudes and outcome against the oracle
+    # random circuits (every op class, swap networks), trees, tunings
+    # (level-end exchanges on for half the seeds), insertion lists with
+    # repeated histories, and read-out flips: every leaf's amplitudes and
+    # outcome against the oracle
     rng = np.random.default_rng(900 + seed)
     n = int(rng.integers(11, 15))
     wc = mixed_gates(n, int(rng.integers(30, 70)), rng)
@@ -853,7 +854,8 @@ def test_random_configurations(T, seed):
     tuning = {"chunk_states": int(rng.integers(1, 8)), "tile_qubits": int(rng.choice([10, 11])),
               "sample_block_log": int(rng.integers(8, 13)), "separate_sampling": int(rng.integers(0, 2)),
               "no_merge": int(rng.integers(0, 2)), "pass_cost": int(rng.choice([120, 480])),
-              "jit": 1 + seed % 2, "mfma_min_ops": (1, 2, 1000)[seed % 3]}
+              "jit": 1 + seed % 2, "mfma_min_ops": (1, 2, 1000)[seed % 3],
+              "level_exchange": 1 + (seed // 2) % 2}
     arr = _repeating_events(wc, tree, rng, rate=float(rng.uniform(0.01, 0.1)))
     flips = rng.integers(0, 1 << n, arr[3].size).astype(np.uint32) if seed % 2 else None
     c = T.Circuit.from_workload(wc)
