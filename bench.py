@@ -784,13 +784,13 @@ def main():
         cb = T.Circuit.from_workload(bw)
         line["brickwall"] = {"workload": "brickwall20 d20 seed 1, depolarizing(1e-3,1e-2) 16384 shots",
                              "gates": Gb, "forms": {}}
-        # (tree4b_level_exchange: lane exchanges at the end of each level's
-        # last pass, tuning level_exchange = 1)
+        # (tree4b_no_level_exchange: without lane exchanges at the levels'
+        # ends, tuning level_exchange = 2; the default plan keeps them here)
         for name, tree, tun in (("pershot", ([shots], [0, Gb]), None),
                                 ("tree", ([16, 32, 32], equal_cuts(Gb, 3)), None),
                                 ("tree4b", ([8, 8, 16, 16], equal_cuts(Gb, 4)), None),
-                                ("tree4b_level_exchange", ([8, 8, 16, 16], equal_cuts(Gb, 4)),
-                                 {"level_exchange": 1})):
+                                ("tree4b_no_level_exchange", ([8, 8, 16, 16], equal_cuts(Gb, 4)),
+                                 {"level_exchange": 2})):
             sps, ms, agg, _ = time_form(T, torch, cb, tree, args.seed, args.steps, args.warmup, tun)
             pl = T.Plan(cb, tree, "c64", tun)
             line["brickwall"]["forms"][name] = {

@@ -126,17 +126,16 @@ typedef struct {
                                   default 0: off (such states stay in the device's caches between
                                   passes anyway, and the LDS cuts occupancy).  Amplitudes agree
                                   to rounding with the pass-by-pass form */
-    uint32_t level_exchange;   /* 1 on, 2 off; default 0: off.  On: when the qubits the next
-                                  tree level's gates change do not fit the lanes plus the
+    uint32_t level_exchange;   /* lane exchanges at the end of a tree level: when the qubits
+                                  the next level's gates change do not fit the lanes plus the
                                   register slots of one tile, the last pass of a level ends
-                                  with lane exchanges that put them in reach, so the next
-                                  level may need fewer passes; the later levels' layout
-                                  changes too, which may cost as much as it saves, or more
-                                  (QFT-20 in the (16, 32, 32) tree: level 1 in one pass
-                                  instead of two, the same speed overall; 20-qubit
-                                  brick-wall in the (8, 8, 16, 16) tree: 17 passes instead
-                                  of 24, 9% faster; in the (16, 32, 32) tree 3% slower).
-                                  Same results either way */
+                                  with exchanges that put them in reach, so the next level
+                                  may need fewer passes, while the later levels' layout
+                                  changes too, which can make their passes slower.  1 on,
+                                  2 off; default 0: the tree is planned both ways and the
+                                  exchanges are kept when they save at least a tenth of the
+                                  passes weighted by their levels' node counts.  Same results
+                                  either way */
 } tqs_tuning;
 
 /* Timing and traffic of one run. */

@@ -1022,7 +1022,7 @@ def test_level_exchange_20q(T, family):
     wc, tree = _c2_case(family)
     c = T.Circuit.from_workload(wc)
     on = T.Plan(c, tree, "c64", {"level_exchange": 1})
-    off = T.Plan(c, tree, "c64")
+    off = T.Plan(c, tree, "c64", {"level_exchange": 2})
     p_on = [on.info(l)["passes_level"] for l in range(3)]
     p_off = [off.info(l)["passes_level"] for l in range(3)]
     assert on.describe() != off.describe()

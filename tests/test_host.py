@@ -323,8 +323,9 @@ def test_level_end_exchange_qft20():
     # (one more than the register slots).  With level_exchange on, level 0's
     # pass ends with a lane exchange and every level is one pass; level 1
     # changes no more than the tile holds afterwards, so its pass ends with no
-    # exchange.  Off (the default), level 1 takes two passes and no pass
-    # holds an exchange.
+    # exchange.  Off, level 1 takes two passes and no pass holds an exchange.
+    # The default keeps the exchanges only when they save a tenth of the
+    # passes weighted by their levels' nodes: here they save 3%, so it is off.
     wc = W.qft(20).with_depolarizing(1e-3, 1e-2)
     G = len(wc)
     cut = [0, 74, 147, G]
@@ -335,15 +336,15 @@ def test_level_end_exchange_qft20():
         kind, _, gl = op
         return kind == "dense" and len(gl[0][0]) == 2 and np.array_equal(gl[0][1], swap)
 
-    off = T.Plan(c, ([16, 32, 32], cut), "c64").describe()
+    off = T.Plan(c, ([16, 32, 32], cut), "c64", {"level_exchange": 2}).describe()
     assert [ln for ln in off.splitlines() if ln.startswith("level")] == ["level 0 0 1", "level 1 1 2",
                                                                          "level 2 3 1"]
     assert not any(is_exchange(op) for ops in _parse_plan(off)[3] for op in ops)
+    assert T.Plan(c, ([16, 32, 32], cut), "c64").describe() == off
     text = T.Plan(c, ([16, 32, 32], cut), "c64", {"level_exchange": 1}).describe()
     lines = text.splitlines()
     assert [ln for ln in lines if ln.startswith("level")] == ["level 0 0 1", "level 1 1 1", "level 2 2 1"]
     n, lay, gates, passes = _parse_plan(text)
-
     # a lane position and a register position
     assert is_exchange(passes[0][-1])
     qs = passes[0][-1][2][0][0]
@@ -353,6 +354,25 @@ def test_level_end_exchange_qft20():
     assert sorted(lay) == list(range(20))
     with pytest.raises(T.TqsError, match="level_exchange"):
         T.Plan(c, ([16, 32, 32], cut), "c64", {"level_exchange": 3})
+
+
+@pytest.mark.parametrize("shape,expect_on", [([16, 32, 32], False), ([8, 8, 16, 16], True)])
+def test_default_level_exchange_choice(shape, expect_on):
+    # the default plans a tree both ways and keeps the exchanges when they
+    # save at least a tenth of the passes weighted by their levels' nodes:
+    # the 20-qubit brick-wall saves 28% with them in the (8, 8, 16, 16) tree,
+    # none in the (16, 32, 32) tree
+    wc = W.brickwall(20, 20, seed=1).with_depolarizing(1e-3, 1e-2)
+    G = len(wc)
+    L = len(shape)
+    cut = [G * l // L for l in range(L)] + [G]
+    c = T.Circuit.from_workload(wc)
+    tr = (shape, cut)
+    plans = {v: T.Plan(c, tr, "c64", {"level_exchange": v}) for v in (1, 2)}
+    weight = {v: sum(int(np.prod(shape[:l + 1])) * p.info(l)["passes_level"] for l in range(L))
+              for v, p in plans.items()}
+    assert (weight[1] <= 0.9 * weight[2]) == expect_on
+    assert T.Plan(c, tr, "c64").describe() == plans[1 if expect_on else 2].describe()
 
 
 def test_one_hip_runtime_per_process():
